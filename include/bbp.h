@@ -1,0 +1,155 @@
+/*
+ * bbp.h -- C ABI of the MI355X blockBP surface-code decoder.
+ *
+ * The decoder is the blockBP decoder of Kaufmann & Arad, "A blockBP decoder for the surface code"
+ * (arXiv 2402.04834): for every syndrome it builds the tensor network of each of the four logical
+ * cosets (Sec. III.A), partitions it into rectangular blocks, runs belief propagation between blocks
+ * with boundary-MPS messages of bond dimension at most chi (Sec. III.D), estimates every coset
+ * probability with the Bethe formula of Lemma 3.1 and returns the most likely coset (Alg. 1).
+ *
+ * Conventions shared by every entry point:
+ *   grid of L = 2d-1 rows and columns; qubits at (r+c) even, numbered row-major; Z-checks (site
+ *   operators A_u) at (even r, odd c), X-checks (plaquettes B_p) at (odd r, even c); a syndrome is m =
+ *   2d(d-1) bytes (0/1), Z-checks row-major then X-checks row-major; a single-qubit Pauli is coded
+ *   x + 2z (0 = I, 1 = X, 2 = Z, 3 = Y); coset index 0..3 = I, X, Y, Z where X is X on row 0 of
+ *   horizontal edges and Z is Z on column 0 of horizontal edges.
+ *
+ * Errors: every int-returning function returns BBP_OK (0) or a negative code; bbp_last_error() gives a
+ * message for the calling thread's last failure. No C++ exception crosses this boundary. A coset whose
+ * BP loop did not converge is not an error: it is reported through delta/iters and the decision rule.
+ */
+#ifndef BBP_H
+#define BBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBP_OK 0
+#define BBP_EINVAL (-1)        /* an argument is out of range or inconsistent */
+#define BBP_ENOMEM (-2)        /* a host or device allocation failed */
+#define BBP_EHIP (-3)          /* a HIP runtime call failed (message carries the HIP error string) */
+#define BBP_EUNSUPPORTED (-4)  /* valid options outside what the GPU path implements */
+
+/* Decoder parameters (Sec. III.E, "Decoder Parameters"; run values of Sec. IV). */
+typedef struct bbp_opts {
+  int32_t block_rows;   /* block height k_r in tensors (remark 1: edge blocks hold the remainder) */
+  int32_t block_cols;   /* block width k_c */
+  int32_t chi;          /* maximal MPS bond dimension of messages and of the in-block boundary MPS */
+  int32_t max_iter;     /* BP iterations; one iteration = both colour rounds (remark 8) */
+  double delta0;        /* exit threshold on the convergence distance (remark 4) */
+  double delta1;        /* trust threshold of the decision rule (remark 6); delta0 <= delta1 */
+  double damping;       /* eta of remark 7: m <- (1-eta) m_new + eta m_old; 0 <= eta < 1 */
+  int32_t rule;         /* 0 = rule of Alg. 1 / remark 6, 1 = plain argmax of the Bethe estimates */
+  int32_t fixed_iters;  /* 1 = always run max_iter iterations (no early exit) */
+  int32_t precision;    /* 0 = FP32 block contractions (FP64 convergence distance and Bethe sums) */
+  int32_t reserved;     /* must be 0 */
+} bbp_opts;
+
+/* Defaults of Sec. IV: 6x6 blocks, chi 16, 20 iterations, delta0 1e-4, delta1 1e-2, eta 0.1. */
+void bbp_default_opts(bbp_opts* opts);
+
+/* Message for the calling thread's most recent non-zero return; never NULL. */
+const char* bbp_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Host-side network (Alg. 1, first steps): f_s, the four coset labels f_s L, and the block plan.
+ * `syndrome` is a host array of m = 2d(d-1) bytes (0/1). The network is owned by the caller after a
+ * successful return and must be released with bbp_free_network. Errors: BBP_EINVAL for d < 2,
+ * m != 2d(d-1), p outside (0, 1) or a byte other than 0/1; BBP_ENOMEM.
+ */
+typedef struct bbp_net bbp_net;
+int bbp_build_network(int32_t d, double p, const uint8_t* syndrome, int64_t m, bbp_net** out);
+/* d, number of qubits n and of checks m of a network. */
+int bbp_net_dims(const bbp_net* net, int32_t* d, int32_t* n, int32_t* m);
+/* Coset labels of the network: labels[4][L*L] (host), bit 0 = x and bit 1 = z of f_s L at every grid
+ * site, row-major (check sites hold 0). */
+int bbp_net_labels(const bbp_net* net, uint8_t* labels);
+void bbp_free_network(bbp_net* net);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Plan summary for distance d under `opts` (Sec. III.D-E): block grid, number M of directed messages
+ * per coset, and the result of the plan-time rank analysis. `exact_sweeps` is 1 when no boundary MPS
+ * inside any block update can exceed bond chi for any input, so that truncation is the identity and the
+ * GPU contracts blocks exactly; `flops_per_iter` / `flops_bethe` are the algorithmic FP32 flops of one
+ * coset-iteration / of the Bethe sweeps of one coset (qubit tensors 8 flops per output entry, data cap
+ * sites 2 per multiply-add, normalisation 2 per entry; copies of COPY tensors and identity cap sites
+ * count zero). Errors: BBP_EINVAL for invalid opts.
+ */
+typedef struct bbp_plan_info {
+  int32_t L, n, m;
+  int32_t block_grid_rows, block_grid_cols;
+  int32_t num_messages;          /* M */
+  int32_t updates_per_iter;      /* = M */
+  int32_t exact_sweeps;          /* 1: chi never truncates (see above) */
+  int32_t max_boundary_rank;     /* largest generic Schmidt rank seen by the analysis */
+  int32_t gpu_supported;         /* 1: bbp_decode_device accepts these options */
+  double flops_per_iter;
+  double flops_bethe;
+} bbp_plan_info;
+int bbp_plan_query(int32_t d, const bbp_opts* opts, bbp_plan_info* info);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Device workspace needed by bbp_decode_device for `batch` syndromes of distance d (bytes, 256-byte
+ * aligned sub-buffers). Errors: BBP_EINVAL.
+ */
+int bbp_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* bytes);
+
+/* Optional per-call timing of the kernels (filled when non-NULL; adds one event pair per launch and a
+ * stream synchronisation at the end of the call). */
+typedef struct bbp_timing {
+  double update_ms;          /* summed duration of the block-update kernel launches (BP rounds) */
+  int32_t update_launches;
+  double bethe_ms;           /* closing sweeps of the Bethe estimate */
+  double other_ms;           /* labels, init, convergence, decision */
+  double update_flops;       /* algorithmic flops of the update launches actually executed */
+} bbp_timing;
+
+/* ---------------------------------------------------------------------------------------------------
+ * Whole decoder (Alg. 1) on a batch of syndromes resident in device memory.
+ *   syndromes_dev   [batch][m] uint8 (0/1), device
+ *   workspace       device buffer of at least bbp_workspace_size bytes, owned by the caller
+ *   loglik_dev      [batch][4] float64, device: Bethe estimate ln Z of each coset (order I, X, Y, Z);
+ *                   NaN when a closing contraction or edge overlap was not positive
+ *   delta_dev       [batch][4] float64: final convergence distance (+inf for such untrusted cosets)
+ *   iters_dev       [batch][4] int32: BP iterations run
+ *   coset_dev       [batch] uint8: decided coset
+ *   correction_dev  [batch][n] uint8: codes x + 2z of the correction f_s L*
+ *   messages_dev    optional [batch][4][M][64] float32: final dense messages (unit norm; entry index
+ *                   = crossing-bond values, first site most significant); NULL to skip
+ *   stream          hipStream_t on which all work is enqueued (NULL = default stream); the call
+ *                   returns after enqueueing unless `timing` is non-NULL.
+ * All pointers are caller-owned; nothing is allocated per call (plans are cached per (d, opts) on first
+ * use). Errors: BBP_EINVAL (bad sizes, NULL required pointer, workspace too small), BBP_EUNSUPPORTED
+ * (options whose truncation the GPU path does not implement), BBP_EHIP.
+ */
+int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch,
+                      const bbp_opts* opts, void* workspace, size_t workspace_bytes,
+                      double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
+                      uint8_t* correction_dev, float* messages_dev, void* stream, bbp_timing* timing);
+
+/* Host convenience: decode host-side networks (all of one d and p) and return host outputs with the
+ * same layouts as bbp_decode_device (correction rows of n bytes). Allocates and frees its own device
+ * memory and synchronises. Errors as above. */
+int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts, double* loglik,
+                       double* delta, int32_t* iters, uint8_t* coset, uint8_t* correction);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Validation hook (host, float64): evaluates the block message update that produces message `msg_id`
+ * (or, with msg_id = -1 - b, the closing sweep of block b) with exactly the index arithmetic of the GPU
+ * kernel, for one coset. `labels` is the L*L label grid of that coset (bit 0 = x, bit 1 = z), `msgs` the
+ * current dense messages [M][64] (host), `out` receives the 2^kp-entry unnormalised outgoing state scaled
+ * to unit norm and `logscale` the natural log of the scale split off during the sweep. Used by the CPU
+ * test-suite to check the plan against the oracle; no decode path calls it.
+ * Errors: BBP_EINVAL for an unknown id or NULL pointers. */
+int bbp_reference_update_host(int32_t d, double p, const bbp_opts* opts, const uint8_t* labels, int32_t msg_id,
+                              const double* msgs, double* out, double* logscale);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBP_H */

@@ -1,0 +1,124 @@
+"""MI355X blockBP surface-code decoder (arXiv 2402.04834): Python front end of libbbp.so.
+
+The functions below marshal arguments into the C ABI of include/bbp.h; PyTorch provides device memory
+and streams. Nothing here computes any step of the decoder, and there is no CPU fallback: on a machine
+without the built library or without a GPU the calls fail.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BbpError, bbp_opts, bbp_plan_info, bbp_timing, default_opts
+
+__all__ = ["default_opts", "plan_query", "build_network", "workspace_size", "decode_device", "blockbp_decode",
+           "reference_update_host", "BbpError", "bbp_opts", "bbp_timing"]
+
+
+def plan_query(d: int, opts: bbp_opts) -> bbp_plan_info:
+    info = bbp_plan_info()
+    _lib.check(_lib.lib().bbp_plan_query(d, C.byref(opts), C.byref(info)))
+    return info
+
+
+class Network:
+    """Host-side network of one syndrome (owns a bbp_net)."""
+
+    def __init__(self, d: int, p: float, syndrome):
+        s = np.ascontiguousarray(np.asarray(syndrome, dtype=np.uint8))
+        h = C.c_void_p()
+        _lib.check(_lib.lib().bbp_build_network(d, p, s.ctypes.data, s.size, C.byref(h)))
+        self.handle = h
+        self.d = d
+
+    def labels(self) -> np.ndarray:
+        L = 2 * self.d - 1
+        out = np.zeros((4, L, L), dtype=np.uint8)
+        _lib.check(_lib.lib().bbp_net_labels(self.handle, out.ctypes.data))
+        return out
+
+    def dims(self):
+        d, n, m = C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.lib().bbp_net_dims(self.handle, C.byref(d), C.byref(n), C.byref(m)))
+        return d.value, n.value, m.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.lib().bbp_free_network(self.handle)
+            self.handle = None
+
+
+def build_network(d: int, p: float, syndrome) -> Network:
+    return Network(d, p, syndrome)
+
+
+def workspace_size(d: int, batch: int, opts: bbp_opts) -> int:
+    n = C.c_size_t()
+    _lib.check(_lib.lib().bbp_workspace_size(d, batch, C.byref(opts), C.byref(n)))
+    return n.value
+
+
+def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None, messages: bool = False,
+                  timing: bool = False, stream=None):
+    """Decode a batch of syndromes held in a torch uint8 CUDA tensor [batch, m].
+    Returns a dict of torch tensors on the same device (loglik, delta, iters, coset, correction and
+    optionally messages) plus a bbp_timing when requested. Work is enqueued on torch's current stream
+    (or `stream`)."""
+    import torch
+
+    assert syndromes.is_cuda and syndromes.dtype == torch.uint8 and syndromes.dim() == 2
+    syndromes = syndromes.contiguous()
+    batch = syndromes.shape[0]
+    dev = syndromes.device
+    n = d * d + (d - 1) * (d - 1)
+    ws_bytes = workspace_size(d, batch, opts)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    out = dict(
+        loglik=torch.empty((batch, 4), dtype=torch.float64, device=dev),
+        delta=torch.empty((batch, 4), dtype=torch.float64, device=dev),
+        iters=torch.empty((batch, 4), dtype=torch.int32, device=dev),
+        coset=torch.empty((batch,), dtype=torch.uint8, device=dev),
+        correction=torch.empty((batch, n), dtype=torch.uint8, device=dev),
+    )
+    msg_ptr = None
+    if messages:
+        M = plan_query(d, opts).num_messages
+        out["messages"] = torch.empty((batch, 4, max(M, 1), 64), dtype=torch.float32, device=dev)
+        msg_ptr = out["messages"].data_ptr()
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    tm = bbp_timing() if timing else None
+    _lib.check(_lib.lib().bbp_decode_device(
+        d, p, syndromes.data_ptr(), batch, C.byref(opts), workspace.data_ptr(), workspace.numel(),
+        out["loglik"].data_ptr(), out["delta"].data_ptr(), out["iters"].data_ptr(), out["coset"].data_ptr(),
+        out["correction"].data_ptr(), msg_ptr, st, C.byref(tm) if tm is not None else None))
+    if tm is not None:
+        out["timing"] = tm
+    out["workspace"] = workspace
+    return out
+
+
+def blockbp_decode(nets, opts: bbp_opts):
+    """Host convenience: decode a list of Network objects (same d and p); returns numpy outputs."""
+    batch = len(nets)
+    d, n, _ = nets[0].dims()
+    arr = (C.c_void_p * batch)(*[x.handle.value for x in nets])
+    ll = np.zeros((batch, 4)); dl = np.zeros((batch, 4)); it = np.zeros((batch, 4), dtype=np.int32)
+    cs = np.zeros(batch, dtype=np.uint8); corr = np.zeros((batch, n), dtype=np.uint8)
+    _lib.check(_lib.lib().bbp_blockbp_decode(arr, batch, C.byref(opts), ll.ctypes.data, dl.ctypes.data,
+                                             it.ctypes.data, cs.ctypes.data, corr.ctypes.data))
+    return dict(loglik=ll, delta=dl, iters=it, coset=cs, correction=corr)
+
+
+def reference_update_host(d: int, p: float, opts: bbp_opts, labels, msg_id: int, msgs):
+    """Validation hook of the C ABI (host float64 evaluation of one block sweep with the kernel's index
+    arithmetic). Returns (state vector of 2^kp entries, log-scale)."""
+    labels = np.ascontiguousarray(np.asarray(labels, dtype=np.uint8))
+    msgs = np.ascontiguousarray(np.asarray(msgs, dtype=np.float64))
+    out = np.zeros(64)
+    ls = C.c_double()
+    _lib.check(_lib.lib().bbp_reference_update_host(d, p, C.byref(opts), labels.ctypes.data, msg_id,
+                                                    msgs.ctypes.data, out.ctypes.data, C.byref(ls)))
+    return out, ls.value

@@ -1,0 +1,103 @@
+"""ctypes binding of libbbp.so (argument marshalling only; every step of the decoder runs in the library).
+
+Names follow the C ABI of include/bbp.h. The library must have been built in-tree
+(`python -m paper_2402_04834_amd.build`); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbbp.so")
+
+BBP_OK = 0
+BBP_EINVAL = -1
+BBP_ENOMEM = -2
+BBP_EHIP = -3
+BBP_EUNSUPPORTED = -4
+
+
+class bbp_opts(C.Structure):
+    _fields_ = [
+        ("block_rows", C.c_int32), ("block_cols", C.c_int32), ("chi", C.c_int32), ("max_iter", C.c_int32),
+        ("delta0", C.c_double), ("delta1", C.c_double), ("damping", C.c_double),
+        ("rule", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class bbp_plan_info(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32), ("n", C.c_int32), ("m", C.c_int32),
+        ("block_grid_rows", C.c_int32), ("block_grid_cols", C.c_int32),
+        ("num_messages", C.c_int32), ("updates_per_iter", C.c_int32), ("exact_sweeps", C.c_int32),
+        ("max_boundary_rank", C.c_int32), ("gpu_supported", C.c_int32),
+        ("flops_per_iter", C.c_double), ("flops_bethe", C.c_double),
+    ]
+
+
+class bbp_timing(C.Structure):
+    _fields_ = [
+        ("update_ms", C.c_double), ("update_launches", C.c_int32), ("bethe_ms", C.c_double),
+        ("other_ms", C.c_double), ("update_flops", C.c_double),
+    ]
+
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "bbp_default_opts": (None, [C.POINTER(bbp_opts)]),
+    "bbp_last_error": (C.c_char_p, []),
+    "bbp_build_network": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]),
+    "bbp_net_dims": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bbp_net_labels": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bbp_free_network": (None, [C.c_void_p]),
+    "bbp_plan_query": (C.c_int, [C.c_int32, C.POINTER(bbp_opts), C.POINTER(bbp_plan_info)]),
+    "bbp_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(bbp_opts), C.POINTER(C.c_size_t)]),
+    "bbp_decode_device": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
+                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(bbp_timing)]),
+    "bbp_blockbp_decode": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bbp_opts), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bbp_reference_update_host": (C.c_int, [C.c_int32, C.c_double, C.POINTER(bbp_opts), C.c_void_p, C.c_int32,
+                                            C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first use; raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_04834_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+class BbpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbbp error {code}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != BBP_OK:
+        raise BbpError(rc, lib().bbp_last_error().decode())
+    return rc
+
+
+def default_opts(**kw) -> bbp_opts:
+    o = bbp_opts()
+    lib().bbp_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k in ("block", "blocks"):
+            o.block_rows, o.block_cols = (v, v) if isinstance(v, int) else v
+        else:
+            setattr(o, k, v)
+    return o

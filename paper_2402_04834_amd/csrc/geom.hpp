@@ -1,0 +1,84 @@
+// geom.hpp -- geometry of the coset tensor networks and of the in-block sweeps, shared by the host plan
+// and the device kernels.
+//
+// Grid (2d-1) x (2d-1); qubits at (r+c) even, Z-checks at (even r, odd c), X-checks at (odd r, even c)
+// (Sec. II.B). Every check is a COPY tensor over its legs; a qubit tensor is the noise probability of its
+// label flipped by the adjacent checks: a horizontal edge (even r) is flipped in x by the checks above /
+// below and in z by those left / right, a vertical edge (odd r) the other way round (Sec. III.A reading).
+//
+// A block update toward side F ("frame") sweeps the block in the direction of F: step t walks the block
+// columns (F = E, W) or rows (F = S, N) starting on the side opposite to F; position i runs across the
+// sweep (rows for E/W, columns for S/N), always in absolute top->bottom / left->right order. In the frame
+// every tensor has legs (up, in, down, out): "in" faces the side the sweep came from, "out" the receiver,
+// "up"/"down" the two side messages, which enter as the top and bottom end caps of the boundary state.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIP__)
+#include <hip/hip_runtime.h>
+#define BBP_HD __host__ __device__ __forceinline__
+#else
+#define BBP_HD inline
+#endif
+
+namespace bbp {
+
+enum : int { FRAME_E = 0, FRAME_W = 1, FRAME_S = 2, FRAME_N = 3 };
+
+// Grid site visited at sweep step t, position i of a block with origin (r0, c0) and size kr x kc.
+BBP_HD void frame_site(int frame, int r0, int c0, int kr, int kc, int t, int i, int& r, int& c) {
+  switch (frame) {
+    case FRAME_E: r = r0 + i; c = c0 + t; break;
+    case FRAME_W: r = r0 + i; c = c0 + kc - 1 - t; break;
+    case FRAME_S: r = r0 + t; c = c0 + i; break;
+    default:      r = r0 + kr - 1 - t; c = c0 + i; break;
+  }
+}
+
+// Dimension of bond j (0..K) of a K-site side message in the open-leg reading: bonds up to K/2 carry the
+// first j legs, later bonds the remaining K-j legs.
+BBP_HD int cap_dim(int K, int j) { return (j <= K / 2) ? (1 << j) : (1 << (K - j)); }
+
+// 16-entry frame table T[vi][hi][vo][ho] (index vi*8 + hi*4 + vo*2 + ho) of the tensor at grid site (r, c)
+// for a sweep toward `frame`. label bit 0 = x, bit 1 = z of f_s L at the site; pi[x*2+z] is the noise
+// table. Legs that leave the grid have dimension 1 and are padded with zeros at value 1.
+BBP_HD void site_table(int frame, int L, int r, int c, int label, const float* pi, float* T) {
+  const bool au = (r == 0), al = (c == 0), ad = (r == L - 1), ar = (c == L - 1);
+  bool a_up, a_in, a_dn, a_out;
+  switch (frame) {
+    case FRAME_E: a_up = au; a_in = al; a_dn = ad; a_out = ar; break;
+    case FRAME_W: a_up = au; a_in = ar; a_dn = ad; a_out = al; break;
+    case FRAME_S: a_up = al; a_in = au; a_dn = ar; a_out = ad; break;
+    default:      a_up = al; a_in = ad; a_dn = ar; a_out = au; break;
+  }
+  const bool qubit = ((r + c) & 1) == 0;
+  const bool swap = ((r & 1) != 0) != (frame >= FRAME_S);
+  const int x = label & 1, z = (label >> 1) & 1;
+  for (int e = 0; e < 16; ++e) {
+    const int vi = (e >> 3) & 1, hi = (e >> 2) & 1, vo = (e >> 1) & 1, ho = e & 1;
+    float val;
+    if ((a_up && vi) || (a_in && hi) || (a_dn && vo) || (a_out && ho)) {
+      val = 0.0f;
+    } else if (qubit) {
+      const int pv = vi ^ vo, ph = hi ^ ho;
+      const int ex = x ^ (swap ? ph : pv);
+      const int ez = z ^ (swap ? pv : ph);
+      val = pi[ex * 2 + ez];
+    } else {
+      // COPY: all present legs equal (absent legs are pinned to 0 and take no part)
+      int ref = -1;
+      bool ok = true;
+      const int vals[4] = {vi, hi, vo, ho};
+      const bool abs4[4] = {a_up, a_in, a_dn, a_out};
+      for (int k = 0; k < 4; ++k) {
+        if (abs4[k]) continue;
+        if (ref < 0) ref = vals[k];
+        else if (vals[k] != ref) ok = false;
+      }
+      val = ok ? 1.0f : 0.0f;
+    }
+    T[e] = val;
+  }
+}
+
+}  // namespace bbp

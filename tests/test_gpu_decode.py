@@ -1,0 +1,147 @@
+"""GPU parity: the HIP decoder (through the C ABI) against the FP64 oracle on the same seeded syndromes.
+
+Tolerances (FP32 block contractions, FP64 sums): every coset log-likelihood within
+|ln Z_gpu - ln Z_oracle| <= 2e-4 + 2e-6 |ln Z_oracle| in fixed-iteration mode, every dense message within
+2e-5 (entries of unit vectors), decisions equal wherever the oracle's best coset leads the runner-up by
+more than 1e-3 nats (the FP32 error budget), and identical iteration counts in early-exit mode away from
+the delta0 threshold.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import blockbp, lattice, mps, network
+from paper_2402_04834_amd import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    import paper_2402_04834_amd as bbp
+    bbp._lib.lib()
+    return torch.device("cuda:0")
+
+
+def _gpu_decode(dev, d, p, syn, **kw):
+    import torch
+    import paper_2402_04834_amd as bbp
+    opts = bbp.default_opts(**kw)
+    st = torch.from_numpy(np.ascontiguousarray(syn)).to(dev)
+    out = bbp.decode_device(d, p, st, opts, messages=True)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items() if k != "workspace"}
+
+
+def _ll_tol(ref):
+    return 2e-4 + 2e-6 * np.abs(ref)
+
+
+def _check_messages(gpu_msgs, res, plan):
+    msgs = res["messages"]
+    S = gpu_msgs.shape[0]
+    for e, (src, dst, _) in enumerate(plan.edges):
+        K = plan.msg_len(src, dst)
+        ref = mps.to_dense(msgs[(src, dst)]).reshape(S, 4, 2 ** K)
+        got = gpu_msgs[:, :, e, : 2 ** K]
+        np.testing.assert_allclose(got, ref, atol=2e-5, err_msg=f"message {e} {src}->{dst}")
+        assert np.all(gpu_msgs[:, :, e, 2 ** K:] == 0)
+
+
+def _decisions_agree(gpu_coset, ref_ll, ref_coset, ref_delta, delta1):
+    """Decisions must agree where the oracle's choice is not within the FP32 error of a tie."""
+    ok = gpu_coset == ref_coset
+    for i in np.nonzero(~ok)[0]:
+        trusted = ref_delta[i] < delta1
+        cand = np.where(trusted, ref_ll[i], -np.inf) if trusted.any() else -ref_delta[i]
+        srt = np.sort(cand)[::-1]
+        assert srt[0] - srt[1] < 1e-3, (i, ref_ll[i], ref_delta[i], gpu_coset[i], ref_coset[i])
+
+
+@pytest.mark.parametrize("d,p,k,chi,iters,eta,count", [
+    (5, 0.10, 3, 4, 10, 0.1, 24),       # the small configuration: d=5, 3x3 blocks, chi 4, 10 iterations
+    (7, 0.12, 4, 16, 6, 0.5, 12),       # ragged 4x4 blocks ([4, 4, 4, 1]), damping 0.5
+    (7, 0.08, 6, 32, 5, 0.1, 8),        # 6x6 blocks with a 1-wide remainder
+    (9, 0.10, 6, 32, 4, 0.1, 4),        # 6x6 blocks with a 5-wide remainder, both caps of dimension 8
+])
+def test_fixed_iterations_parity(dev, d, p, k, chi, iters, eta, count):
+    _say(f"[parity] d={d} p={p} k={k} chi={chi} iters={iters} eta={eta} count={count}")
+    _, syn = workload.make_batch(d, p, count, workload="test", p_index=d)
+    ref = blockbp.decode(d, p, syn, block=(k, k), chi=chi, max_iter=iters, eta=eta, fixed_iters=True,
+                         return_messages=True)
+    got = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=iters, damping=eta, fixed_iters=1)
+    assert np.all(got["iters"] == iters)
+    np.testing.assert_allclose(got["loglik"], ref["loglik"], rtol=0, atol=_ll_tol(ref["loglik"]).max())
+    np.testing.assert_allclose(got["delta"], ref["delta"], rtol=2e-2, atol=2e-6)
+    _check_messages(got["messages"], ref, ref["plan"])
+    _decisions_agree(got["coset"], ref["loglik"], ref["coset"], ref["delta"], 1e-2)
+    # the correction carries the syndrome and lies in the decided coset
+    np.testing.assert_array_equal(workload.syndrome_of(d, got["correction"]), syn)
+
+
+def test_early_exit_parity(dev):
+    d, p, k, chi = 5, 0.08, 3, 4
+    _say(f"[early-exit] d={d} p={p}")
+    _, syn = workload.make_batch(d, p, 32, workload="test", p_index=77)
+    ref = blockbp.decode(d, p, syn, block=(k, k), chi=chi, max_iter=20)
+    got = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=20)
+    # iteration counts agree except where the oracle's distance sits within FP32 noise of delta0
+    near = np.abs(np.log(np.maximum(ref["delta"], 1e-30) / 1e-4)) < 0.05
+    assert np.all((got["iters"] == ref["iters"]) | near)
+    same = got["iters"] == ref["iters"]
+    np.testing.assert_allclose(got["loglik"][same], ref["loglik"][same], atol=_ll_tol(ref["loglik"]).max())
+    _decisions_agree(got["coset"], ref["loglik"], ref["coset"], ref["delta"], 1e-2)
+
+
+def test_uniform_noise_closed_form_on_gpu(dev):
+    # eps = 3/4: ln Z = (m - 2n) ln 2 for every coset; converged after one iteration
+    d = 9
+    _say("[closed form] d=9 eps=3/4")
+    rng = np.random.default_rng(5)
+    syn = rng.integers(0, 2, size=(6, 2 * d * (d - 1)), dtype=np.uint8)
+    got = _gpu_decode(dev, d, 0.75, syn, block=4, chi=16, max_iter=5)
+    m, n = 2 * d * (d - 1), d * d + (d - 1) ** 2
+    np.testing.assert_allclose(got["loglik"], (m - 2 * n) * math.log(2.0), atol=1e-4)
+    assert np.all(got["iters"] == 1)
+
+
+def test_single_block_equals_exact_contraction(dev):
+    # one block covering the whole d=3 lattice: no messages; the closing sweep is the exact contraction
+    d, p = 3, 0.1
+    _say("[single block] d=3")
+    _, syn = workload.make_batch(d, p, 16, workload="test", p_index=3)
+    got = _gpu_decode(dev, d, p, syn, block=5, chi=4, max_iter=2)
+    ex = network.exact_coset_loglik(d, syn, p)
+    np.testing.assert_allclose(got["loglik"], ex, atol=2e-5)
+    np.testing.assert_array_equal(got["coset"], np.argmax(ex, axis=1))
+
+
+def test_tree_partition_equals_exact_contraction(dev):
+    # one block row: BP on a path is exact; with no damping it converges to the exact coset probabilities
+    d, p = 3, 0.12
+    _say("[tree] d=3 blocks 5x2")
+    _, syn = workload.make_batch(d, p, 8, workload="test", p_index=4)
+    got = _gpu_decode(dev, d, p, syn, block=(5, 2), chi=8, max_iter=8, damping=0.0, fixed_iters=1)
+    ex = network.exact_coset_loglik(d, syn, p)
+    np.testing.assert_allclose(got["loglik"], ex, atol=5e-5)
+
+
+def test_batch_of_one_and_ragged_batches_are_independent(dev):
+    # results do not depend on the batch composition: decoding a syndrome alone or inside a batch gives
+    # bitwise identical outputs
+    d, p = 7, 0.1
+    _say("[batch independence] d=7")
+    _, syn = workload.make_batch(d, p, 9, workload="test", p_index=9)
+    full = _gpu_decode(dev, d, p, syn, block=6, chi=32, max_iter=4)
+    for i in (0, 4, 8):
+        one = _gpu_decode(dev, d, p, syn[i:i + 1], block=6, chi=32, max_iter=4)
+        np.testing.assert_array_equal(one["loglik"][0], full["loglik"][i])
+        np.testing.assert_array_equal(one["coset"][0], full["coset"][i])

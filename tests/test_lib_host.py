@@ -1,0 +1,123 @@
+"""CPU checks of the C-ABI library: it loads and exports every declared symbol, its plan matches the
+oracle's block partition, its host-built labels match the oracle's f_s L, and the float64 validation hook
+(same index arithmetic as the GPU kernel) reproduces the oracle's block updates."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import blockbp, lattice, mps, network
+from paper_2402_04834_amd import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bbp():
+    import paper_2402_04834_amd as pkg
+    from paper_2402_04834_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libbbp.so is not built (run `python -m paper_2402_04834_amd.build`)")
+    return pkg
+
+
+def test_library_exports_every_declared_symbol(bbp):
+    from paper_2402_04834_amd import _lib
+    header = open(os.path.join(ROOT, "include", "bbp.h")).read()
+    declared = set(re.findall(r"\b(bbp_[a-z_]+)\s*\(", header))
+    declared -= {"bbp_opts", "bbp_net", "bbp_timing", "bbp_plan_info"}
+    h = _lib.lib()
+    for name in sorted(declared):
+        assert hasattr(h, name), name
+    assert declared <= set(_lib.SIGNATURES)
+
+
+@pytest.mark.parametrize("d,k,chi", [(5, 3, 4), (11, 4, 16), (17, 6, 32), (21, 6, 32), (25, 6, 32)])
+def test_plan_matches_oracle_partition_and_is_exact(bbp, d, k, chi):
+    info = bbp.plan_query(d, bbp.default_opts(block=k, chi=chi))
+    p = blockbp.Plan(d, k, k)
+    assert info.num_messages == p.M
+    assert (info.block_grid_rows, info.block_grid_cols) == (p.nI, p.nJ)
+    # every configuration in scope has block boundary states of rank <= chi: the truncation never acts
+    assert info.exact_sweeps == 1 and info.gpu_supported == 1
+
+
+def test_plan_detects_binding_truncation(bbp):
+    info = bbp.plan_query(7, bbp.default_opts(block=6, chi=8))
+    assert info.exact_sweeps == 0 and info.max_boundary_rank == 16 and info.gpu_supported == 0
+    info = bbp.plan_query(7, bbp.default_opts(block=6, chi=16))
+    assert info.exact_sweeps == 1
+
+
+def test_invalid_arguments_are_rejected(bbp):
+    from paper_2402_04834_amd import _lib
+    with pytest.raises(_lib.BbpError):
+        bbp.build_network(3, 0.1, np.zeros(5, dtype=np.uint8))
+    with pytest.raises(_lib.BbpError):
+        bbp.build_network(3, 1.5, np.zeros(12, dtype=np.uint8))
+    with pytest.raises(_lib.BbpError):
+        bbp.workspace_size(5, 4, bbp.default_opts(damping=1.5))
+    with pytest.raises(_lib.BbpError):
+        bbp.workspace_size(5, 4, bbp.default_opts(delta0=1e-1, delta1=1e-3))
+
+
+@pytest.mark.parametrize("d", [3, 5, 9])
+def test_host_network_labels_match_oracle(bbp, d):
+    _, s = workload.make_batch(d, 0.1, 5)
+    x, z = lattice.coset_labels(d, s)
+    for i in range(5):
+        lab = bbp.build_network(d, 0.1, s[i]).labels()
+        np.testing.assert_array_equal(lab & 1, x[i])
+        np.testing.assert_array_equal(lab >> 1, z[i])
+
+
+def _dense_msgs(plan, rng):
+    out = np.zeros((plan.M, 64))
+    mps_msgs = {}
+    for e, (src, dst, _) in enumerate(plan.edges):
+        K = plan.msg_len(src, dst)
+        v = rng.uniform(0.05, 1.0, size=2 ** K)
+        v /= np.linalg.norm(v)
+        out[e, : 2 ** K] = v
+        mps_msgs[(src, dst)], _ = mps.canonical_message(mps.from_dense(v[None], [2] * K), 64)
+    return out, mps_msgs
+
+
+@pytest.mark.parametrize("d,k", [(5, 3), (7, 4), (7, 6), (9, 6)])
+def test_reference_sweep_matches_oracle(bbp, d, k):
+    # every directed update and every closing sweep of the plan, on one coset of one syndrome
+    rng = np.random.default_rng(d * 10 + k)
+    eps = 0.1
+    _, s = workload.make_batch(d, eps, 1)
+    x, z = lattice.coset_labels(d, s)
+    cos = 2
+    labels = (x[0, cos] | (z[0, cos] << 1)).astype(np.uint8)
+    L = 2 * d - 1
+    # the library holds the noise table in float32 (1 - eps and eps / 3 rounded); use the same numbers
+    e32 = np.float32(eps)
+    pi32 = np.array([[np.float32(1) - e32, e32 / np.float32(3)], [e32 / np.float32(3)] * 2], dtype=np.float64)
+    tensors = network.coset_tensors(d, x[0, cos][None], z[0, cos][None], pi32)
+    plan = blockbp.Plan(d, k, k)
+    dense, mmsgs = _dense_msgs(plan, rng)
+    opts = bbp.default_opts(block=k, chi=64)
+    for e, (src, dst, dname) in enumerate(plan.edges):
+        got, ls = bbp.reference_update_host(d, eps, opts, labels, e, dense)
+        ref, lr = blockbp.block_sweep(plan, tensors, mmsgs, src[0], src[1], dname, 64, (1,))
+        refv = mps.to_dense(ref)[0]
+        n = refv.size
+        np.testing.assert_allclose(got[:n] * np.exp(ls), refv * np.exp(lr[0]), rtol=1e-9,
+                                   atol=1e-12 * np.abs(refv).max() * np.exp(lr[0]))
+        assert np.all(got[n:] == 0)
+    for b, (I, J) in enumerate(plan.blocks):
+        got, ls = bbp.reference_update_host(d, eps, opts, labels, -1 - b, dense)
+        st, lr = blockbp.block_sweep(plan, tensors, mmsgs, I, J, "E", 64, (1,))
+        east = (I, J + 1)
+        if plan.has(east):
+            w = mps.overlap(st, mmsgs[(east, (I, J))])[0]
+            e_id = [q for q, ed in enumerate(plan.edges) if ed[0] == east and ed[1] == (I, J)][0]
+            wg = float(np.dot(got[: 2 ** plan.rows[I][1]], dense[e_id, : 2 ** plan.rows[I][1]]))
+        else:
+            w = mps.to_dense(st)[0][0]
+            wg = got[0]
+        np.testing.assert_allclose(np.log(wg) + ls, np.log(w) + lr[0], atol=1e-9)
