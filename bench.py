@@ -1,0 +1,132 @@
+"""Throughput benchmark of the blockBP decoder on one MI355X.
+
+Workload (one "step"): decode 4096 seeded syndromes of the d=17 planar surface code under i.i.d.
+depolarizing noise p=0.10 (X, Y, Z each p/3) -- blocks of 6x6 tensors, chi=32, at most 20 BP iterations
+with early exit (delta0 1e-4, delta1 1e-2, damping 0.1). The syndromes are resident in HBM before the
+timed region starts. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "syndromes decoded/s at d=17, chi=32 (1 GPU); agreement vs FP64 oracle"
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk (packed dual FMA)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "d17_p010_k6_chi32.json")
+
+
+def cpu_baseline(d, p, block, chi, max_iter):
+    """The FP64 oracle on one syndrome of the same workload, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import blockbp
+    from paper_2402_04834_amd import workload
+
+    _, syn = workload.make_batch(d, p, 1, workload="d17")
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        blockbp.decode(d, p, syn, block=(block, block), chi=chi, max_iter=max_iter)
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="syndromes/s", cores=1, kind="oracle",
+                sample=f"syndrome 0 of the d={d} p={p} workload, all 4 cosets, {block}x{block} blocks, chi={chi}, "
+                       f"<= {max_iter} iterations with early exit, float64, one thread ({dt:.1f} s)")
+
+
+def agreement(out, batch):
+    if not os.path.exists(GOLDEN):
+        return None
+    g = json.load(open(GOLDEN))
+    recs = [r for r in g["records"] if r["index"] < batch]
+    if not recs:
+        return None
+    import numpy as np
+    cos = out["coset"].cpu().numpy()
+    ll = out["loglik"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    eq = sum(int(cos[r["index"]] == r["coset"]) for r in recs)
+    diffs = [abs(ll[r["index"], k] - r["loglik"][k]) for r in recs for k in range(4)
+             if it[r["index"], k] == r["iters"][k] and np.isfinite(r["loglik"][k])]
+    same_it = sum(int(it[r["index"], k] == r["iters"][k]) for r in recs for k in range(4))
+    return dict(syndromes=len(recs), decisions_equal=eq, frac=eq / len(recs),
+                cosets_same_iterations=same_it, cosets=4 * len(recs),
+                max_abs_dlnz_same_iterations=float(max(diffs)) if diffs else None,
+                median_abs_dlnz_same_iterations=float(np.median(diffs)) if diffs else None,
+                oracle=os.path.relpath(GOLDEN, ROOT))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py: this decoder runs on one GPU; only --gpus 1 is supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import workload
+
+    d, p, block, chi, max_iter = 17, 0.10, 6, 32, 20
+    _, syn = workload.make_batch(d, p, a.batch, workload="d17")
+    dev = torch.device("cuda:0")
+    syn_dev = torch.from_numpy(syn).to(dev)
+    opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1)
+    info = bbp.plan_query(d, opts)
+    ws = torch.empty(bbp.workspace_size(d, a.batch, opts), dtype=torch.uint8, device=dev)
+    for _ in range(a.warmup):
+        bbp.decode_device(d, p, syn_dev, opts, workspace=ws)
+    torch.cuda.synchronize()
+    upd_ms = upd_flops = bethe_ms = other_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = bbp.decode_device(d, p, syn_dev, opts, workspace=ws, timing=True)
+        tm = out["timing"]
+        upd_ms += tm.update_ms
+        upd_flops += tm.update_flops
+        bethe_ms += tm.bethe_ms
+        other_ms += tm.other_ms
+        launches += tm.update_launches
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = a.batch * a.steps / elapsed
+    achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    iters = out["iters"].double().mean().item()
+    line = dict(
+        metric=METRIC, value=value, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
+        config=dict(workload=f"planar surface code d={d}, depolarizing p={p}, {a.batch} seeded syndromes, "
+                             f"{block}x{block} blocks, chi={chi}, <= {max_iter} BP iterations, early exit",
+                    d=d, p=p, batch=a.batch, block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
+                    damping=0.1, parallelism="single GPU"),
+        roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None,
+                      kernel="update_kernel", avg_launch_ms=upd_ms / max(launches, 1),
+                      flops_per_launch=upd_flops / max(launches, 1)),
+        kernel_ms_per_step=dict(update=upd_ms / a.steps, bethe=bethe_ms / a.steps, other=other_ms / a.steps),
+        mean_iterations_per_coset=iters,
+        plan=dict(messages_per_coset=info.num_messages, exact_sweeps=bool(info.exact_sweeps),
+                  max_boundary_rank=info.max_boundary_rank),
+        agreement=agreement(out, a.batch),
+    )
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(d, p, block, chi, max_iter)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
