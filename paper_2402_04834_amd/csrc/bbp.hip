@@ -32,6 +32,7 @@
 #include "../../include/bbp.h"
 #include "geom.hpp"
 #include "plan.hpp"
+#include "sweep.hpp"
 
 using bbp::SweepDesc;
 
@@ -39,6 +40,7 @@ namespace {
 
 constexpr int NT = 256;          // threads per update workgroup
 constexpr int SMAX = 4096;       // max dense boundary-state entries (6x6 blocks, caps of dimension 8)
+constexpr int BMAX = 2048;       // max pass-1 intermediate (top cap advanced, bottom cap not yet)
 constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
 
 thread_local std::string g_err = "no error";
@@ -111,8 +113,117 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // --------------------------------------------------------------------------------------------------
-// One block sweep per workgroup. mode 0: BP update of message s.msg_out; mode 1: closing sweep W_v.
-__global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict__ sweeps, int d,
+// Block sweeps. Lane h of a wavefront holds the crossing-bond configuration h (position 0 in the most
+// significant of kp bits). The boundary state is a set of rows (top cap index n, bottom cap index s), one
+// float per lane, stored in LDS as rows of 64 floats (row = n * Ps + s); the four waves of a workgroup take
+// the rows round-robin. A qubit's 2x2 transform pairs lane h with lane h ^ bit: a cross-lane shuffle and two
+// multiply-adds with coefficients chosen per lane from the check bits above and below. Only the cap sites
+// mix rows (through LDS). The column structure is described in sweep.hpp.
+
+// phi[np][v] of a cap site of kind KIND, reading psi[n] = sc * base[n * stride].
+template <int KIND>
+__device__ __forceinline__ float capv(const float* __restrict__ m, int Pold, int lPold, int Pnew, int R2, int np,
+                                      int v, const float* base, int stride, float sc) {
+  if constexpr (KIND == bbp::CAP_NONE) {
+    return v == 0 ? sc * base[0] : 0.0f;
+  } else if constexpr (KIND == bbp::CAP_F_LT) {
+    return v == (np & 1) ? sc * base[(np >> 1) * stride] : 0.0f;
+  } else if constexpr (KIND == bbp::CAP_F_EQ) {
+    float acc = 0.0f;
+    for (int a = 0; a < Pold; ++a) acc = fmaf(m[(a * 2 + v) * R2 + np], base[a * stride], acc);
+    return sc * acc;
+  } else if constexpr (KIND == bbp::CAP_F_GT) {
+    return sc * base[(v * Pnew + np) * stride];
+  } else if constexpr (KIND == bbp::CAP_B_GT) {
+    return (v == (np >> lPold)) ? sc * base[(np & (Pold - 1)) * stride] : 0.0f;
+  } else if constexpr (KIND == bbp::CAP_B_EQ) {
+    float acc = 0.0f;
+    for (int b = 0; b < Pold; ++b) acc = fmaf(m[(np * 2 + v) * R2 + b], base[b * stride], acc);
+    return sc * acc;
+  } else {   // CAP_B_LT
+    return sc * base[(2 * np + v) * stride];
+  }
+}
+
+struct LaneCoef {
+  // site 0 (qubit): coefficients for (v, own / partner input bit); middle qubits: own / partner
+  float q00, q01, q10, q11;
+  float cm_own[3], cm_par[3];
+  int bm[3];
+};
+
+constexpr int NW = NT / 64;
+
+// pass 1 (A -> B): top cap of kind KIND, site 0 and the middle qubits, for this wave's rows
+template <int KIND>
+__device__ __forceinline__ void pass1_rows(const bbp::ColumnDesc& cd, const LaneCoef& lc, const float* A, float* B,
+                                           const float* mt, int h, int hr, int b0, int vchk, int Ptn, int Pso,
+                                           int lso, float sc, int wid) {
+  const bool q0 = cd.flags & 1;
+  const int lPold = __builtin_ctz(cd.top_Pold);
+  const int stride = Pso * 64;
+  for (int row = wid; row < Ptn * Pso; row += NW) {
+    const int np = row >> lso, sb = row & (Pso - 1);
+    const float* base = A + sb * 64 + hr;
+    float out;
+    if (q0) {
+      const float f0 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 0, base, stride, sc);
+      const float f1 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 1, base, stride, sc);
+      const float g0 = __shfl_xor(f0, b0);
+      const float g1 = __shfl_xor(f1, b0);
+      out = lc.q00 * f0 + lc.q01 * g0 + lc.q10 * f1 + lc.q11 * g1;
+    } else {
+      out = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, vchk, base, stride, sc);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (j < cd.nmid) {
+        const float par = __shfl_xor(out, lc.bm[j]);
+        out = lc.cm_own[j] * out + lc.cm_par[j] * par;
+      }
+    }
+    B[(np * Pso + sb) * 64 + h] = out;
+  }
+}
+
+// pass 2 (B -> A): bottom cap of kind KIND and the last site, then the out-leg projections; returns the
+// wave-local sum of squares
+template <int KIND>
+__device__ __forceinline__ float pass2_rows(const bbp::ColumnDesc& cd, const float* B, float* A, const float* mb,
+                                            int h, int kp, int bl, int vchk, float l00, float l01, float l10,
+                                            float l11, int Ptn, int Pso, int Psn, int lsn, int wid) {
+  const bool ql = cd.flags & 4;
+  const int lPold = __builtin_ctz(cd.bot_Pold);
+  float ss = 0.0f;
+  for (int row = wid; row < Ptn * Psn; row += NW) {
+    const int n = row >> lsn, sp = row & (Psn - 1);
+    const float* base = B + n * Pso * 64 + h;
+    float out;
+    if (ql) {
+      const float f0 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 0, base, 64, 1.0f);
+      const float f1 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 1, base, 64, 1.0f);
+      const float g0 = __shfl_xor(f0, bl);
+      const float g1 = __shfl_xor(f1, bl);
+      out = l00 * f0 + l01 * g0 + l10 * f1 + l11 * g1;
+    } else {
+      out = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, vchk, base, 64, 1.0f);
+    }
+    if (cd.out_absent) {
+      for (int b = 0; b < kp; ++b)
+        if (cd.out_absent & (1 << b)) {
+          const float o2 = __shfl_xor(out, 1 << b);
+          out = (h & (1 << b)) ? 0.0f : out + o2;
+        }
+    }
+    A[(n * Psn + sp) * 64 + h] = out;
+    ss = fmaf(out, out, ss);
+  }
+  return ss;
+}
+
+// mode 0: BP update of message s.msg_out; mode 1: closing sweep W_v of block s.block.
+__global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict__ sweeps,
+                                                    const bbp::ColumnDesc* __restrict__ cols, int d,
                                                     const uint8_t* __restrict__ labels, float* __restrict__ msgs,
                                                     int M, double* __restrict__ terms,
                                                     const int32_t* __restrict__ conv, float p0, float p1, float p2,
@@ -122,152 +233,172 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
   if (mode == 0 && conv[job]) return;
   const SweepDesc s = sweeps[blockIdx.y];
   const int L = 2 * d - 1;
-  const int kt = s.kt, kp = s.kp, H = 1 << kp, K = kt, D = K / 2;
-  const bool fwd = (s.frame == bbp::FRAME_E || s.frame == bbp::FRAME_S);
-  const int tid = threadIdx.x;
+  const int kt = s.kt, kp = s.kp, H = 1 << kp;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   __shared__ float A[SMAX];
-  __shared__ float B[SMAX];
+  __shared__ float B[BMAX];
   __shared__ float T[36 * 16];
-  __shared__ float mt[MSTRIDE], mb[MSTRIDE], mx[MSTRIDE];
-  __shared__ float red[NT / 64];
+  __shared__ float mt[MSTRIDE], mb[MSTRIDE];
+  __shared__ float red[NW];
 
-  const float pi[4] = {p0, p1, p2, p3};
   const uint8_t* lab = labels + job * L * L;
-  for (int q = tid; q < kt * kp; q += NT) {
+  for (int q = tid; q < kt * kp * 16; q += NT) {
     int r, c;
-    bbp::frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, q / kp, q % kp, r, c);
-    bbp::site_table(s.frame, L, r, c, lab[r * L + c], pi, &T[q * 16]);
+    const int site = q >> 4;
+    bbp::frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, site / kp, site % kp, r, c);
+    T[q] = bbp::site_entry(s.frame, L, r, c, lab[r * L + c], p0, p1, p2, p3, q & 15);
   }
   const float* mbase = msgs + job * M * MSTRIDE;
   const bool has_top = s.msg_top >= 0, has_bot = s.msg_bot >= 0;
-  if (tid < MSTRIDE) {
-    mt[tid] = has_top ? mbase[s.msg_top * MSTRIDE + tid] : 0.0f;
-    mb[tid] = has_bot ? mbase[s.msg_bot * MSTRIDE + tid] : 0.0f;
+  if (wid == 0) {
+    mt[lane] = has_top ? mbase[s.msg_top * MSTRIDE + lane] : 0.0f;
+    mb[lane] = has_bot ? mbase[s.msg_bot * MSTRIDE + lane] : 0.0f;
+    A[lane] = (s.msg_init >= 0) ? mbase[s.msg_init * MSTRIDE + lane] : (lane == 0 ? 1.0f : 0.0f);
   }
-  for (int h = tid; h < H; h += NT) A[h] = (s.msg_init >= 0) ? mbase[s.msg_init * MSTRIDE + h] : (h == 0 ? 1.0f : 0.0f);
   __syncthreads();
 
+  const int h = lane;
   double logscale = 0.0;
-  int Pt = 1, Ps = 1;
-  const int R2 = 1 << (K - D - 1);
+  float scale = 1.0f;
+  int Ps = 1;
   for (int t = 0; t < kt; ++t) {
-    const int js = fwd ? t : kt - 1 - t;
-    const int bnew = fwd ? t + 1 : kt - 1 - t;
-    const int Ptn = has_top ? bbp::cap_dim(K, bnew) : 1;
-    const int Psn = has_bot ? bbp::cap_dim(K, bnew) : 1;
-    const int HS = H * Ps;
-    // top cap site: B[(n'*2+v)*HS + hs]
-    const int nB = Ptn * 2 * HS;
-    for (int idx = tid; idx < nB; idx += NT) {
-      const int hs = idx % HS, v = (idx / HS) & 1, np = idx / (2 * HS);
-      float val = 0.0f;
-      if (!has_top) {
-        if (v == 0) val = A[hs];
-      } else if (fwd) {
-        if (js < D) { if (v == (np & 1)) val = A[(np >> 1) * HS + hs]; }
-        else if (js == D) {
-          for (int a = 0; a < (1 << D); ++a) val = fmaf(mt[(a * 2 + v) * R2 + np], A[a * HS + hs], val);
-        } else { const int R = 1 << (K - js - 1); val = A[(v * R + np) * HS + hs]; }
-      } else {
-        if (js > D) { const int R = 1 << (K - js - 1); if (v == np / R) val = A[(np % R) * HS + hs]; }
-        else if (js == D) {
-          for (int b = 0; b < R2; ++b) val = fmaf(mt[(np * 2 + v) * R2 + b], A[b * HS + hs], val);
-        } else { val = A[(2 * np + v) * HS + hs]; }
-      }
-      B[idx] = val;
-    }
-    __syncthreads();
-    // the column's tensors, top to bottom
-    const int half = H >> 1;
-    const int groups = Ptn * half * Ps;
-    for (int i = 0; i < kp; ++i) {
-      const float* Ti = &T[(t * kp + i) * 16];
-      const int sh = kp - 1 - i;
-      const int hbit = 1 << sh;
-      for (int g = tid; g < groups; g += NT) {
-        const int sb = g % Ps;
-        const int rest = g / Ps;
-        const int hl = rest % half, np = rest / half;
-        const int h0 = ((hl >> sh) << (sh + 1)) | (hl & (hbit - 1));
-        const int i00 = ((np * 2 + 0) * H + h0) * Ps + sb;
-        const int i01 = i00 + hbit * Ps;
-        const int i10 = i00 + H * Ps;
-        const int i11 = i10 + hbit * Ps;
-        const float a00 = B[i00], a01 = B[i01], a10 = B[i10], a11 = B[i11];
-        // out[vo*2+ho] = sum_{vi,hi} T[vi*8+hi*4+vo*2+ho] * in[vi][hi]
-        B[i00] = Ti[0] * a00 + Ti[4] * a01 + Ti[8] * a10 + Ti[12] * a11;
-        B[i01] = Ti[1] * a00 + Ti[5] * a01 + Ti[9] * a10 + Ti[13] * a11;
-        B[i10] = Ti[2] * a00 + Ti[6] * a01 + Ti[10] * a10 + Ti[14] * a11;
-        B[i11] = Ti[3] * a00 + Ti[7] * a01 + Ti[11] * a10 + Ti[15] * a11;
+    const bbp::ColumnDesc cd = cols[s.col_off + t];
+    const float* Tt = &T[t * kp * 16];
+    const int Ptn = cd.top_Pnew, Psn = cd.bot_Pnew, Pso = Ps;
+    const int lso = __builtin_ctz(Pso), lsn = __builtin_ctz(Psn);
+    const float sc = scale;
+    const int hr = h & ~cd.in_absent;      // checks entering from outside the grid: free variable
+    if (cd.flags & 16) {
+      // ---- one position (kp == 1): generic path --------------------------------------------------------
+      bbp::CapInfo top{cd.top_kind, cd.top_Pold, cd.top_Pnew, cd.top_R2};
+      bbp::CapInfo bot{cd.bot_kind, cd.bot_Pold, cd.bot_Pnew, cd.bot_R2};
+      for (int row = wid; row < Ptn * Pso; row += NW) {
+        const int np = row >> lso, sb = row & (Pso - 1);
+        auto get = [&](int n) { return sc * A[(n * Pso + sb) * 64 + hr]; };
+        for (int vt = 0; vt < 2; ++vt)
+          B[((np * 2 + vt) * Pso + sb) * 64 + h] = bbp::cap_phi<float>(top, mt, np, vt, get);
       }
       __syncthreads();
-    }
-    // bottom cap site: A[(n'*H + h)*Psn + s']
-    const int nA = Ptn * H * Psn;
-    float ss = 0.0f;
-    for (int idx = tid; idx < nA; idx += NT) {
-      const int sp = idx % Psn, h = (idx / Psn) % H, np = idx / (Psn * H);
-      auto Bat = [&](int v, int sb) { return B[((np * 2 + v) * H + h) * Ps + sb]; };
-      float val = 0.0f;
-      if (!has_bot) {
-        val = Bat(0, 0);
-      } else if (fwd) {
-        if (js < D) val = Bat(sp & 1, sp >> 1);
-        else if (js == D) {
-          for (int a = 0; a < (1 << D); ++a)
-            for (int v = 0; v < 2; ++v) val = fmaf(mb[(a * 2 + v) * R2 + sp], Bat(v, a), val);
-        } else { const int R = 1 << (K - js - 1); val = Bat(0, sp) + Bat(1, R + sp); }
-      } else {
-        if (js > D) { const int R = 1 << (K - js - 1); val = Bat(sp / R, sp % R); }
-        else if (js == D) {
-          for (int b = 0; b < R2; ++b)
-            for (int v = 0; v < 2; ++v) val = fmaf(mb[(sp * 2 + v) * R2 + b], Bat(v, b), val);
-        } else { val = Bat(0, 2 * sp) + Bat(1, 2 * sp + 1); }
+      const int hol = h & 1;
+      float ss = 0.0f;
+      for (int row = wid; row < Ptn * Psn; row += NW) {
+        const int n = row >> lsn, sp = row & (Psn - 1);
+        float out = 0.0f;
+        if (cd.flags & 4) {
+          for (int vt = 0; vt < 2; ++vt)
+            for (int vb = 0; vb < 2; ++vb) {
+              auto get = [&](int sb) { return B[((n * 2 + vt) * Pso + sb) * 64 + h]; };
+              const float f = bbp::cap_phi<float>(bot, mb, sp, vb, get);
+              const float g = __shfl_xor(f, 1);
+              out += Tt[vt * 8 + hol * 4 + vb * 2 + hol] * f + Tt[vt * 8 + (1 - hol) * 4 + vb * 2 + hol] * g;
+            }
+        } else {
+          const int vt = (cd.flags & 2) ? 0 : hol;
+          const int vb = (cd.flags & 8) ? 0 : hol;
+          auto get = [&](int sb) { return B[((n * 2 + vt) * Pso + sb) * 64 + h]; };
+          out = bbp::cap_phi<float>(bot, mb, sp, vb, get);
+        }
+        if (cd.out_absent & 1) {
+          const float o2 = __shfl_xor(out, 1);
+          out = hol ? 0.0f : out + o2;
+        }
+        A[(n * Psn + sp) * 64 + h] = out;
+        ss = fmaf(out, out, ss);
       }
-      A[idx] = val;
-      ss = fmaf(val, val, ss);
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      if (lane == 0) red[wid] = ss;
+    } else {
+      // ---- pass 1 -----------------------------------------------------------------------------------
+      LaneCoef lc;
+      const int b0 = bbp::pos_bit(kp, 0);
+      const int ho0 = (h & b0) ? 1 : 0;
+      const int vo0 = (h & bbp::pos_bit(kp, 1)) ? 1 : 0;
+      lc.q00 = Tt[0 * 8 + ho0 * 4 + vo0 * 2 + ho0];
+      lc.q01 = Tt[0 * 8 + (1 - ho0) * 4 + vo0 * 2 + ho0];
+      lc.q10 = Tt[1 * 8 + ho0 * 4 + vo0 * 2 + ho0];
+      lc.q11 = Tt[1 * 8 + (1 - ho0) * 4 + vo0 * 2 + ho0];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        lc.cm_own[j] = 0.0f;
+        lc.cm_par[j] = 0.0f;
+        lc.bm[j] = 0;
+        if (j < cd.nmid) {
+          const int i = (cd.mids >> (4 * j)) & 15;
+          const int bi = bbp::pos_bit(kp, i);
+          const int vi = (h & bbp::pos_bit(kp, i - 1)) ? 1 : 0;
+          const int vo = (h & bbp::pos_bit(kp, i + 1)) ? 1 : 0;
+          const int ho = (h & bi) ? 1 : 0;
+          lc.cm_own[j] = Tt[i * 16 + vi * 8 + ho * 4 + vo * 2 + ho];
+          lc.cm_par[j] = Tt[i * 16 + vi * 8 + (1 - ho) * 4 + vo * 2 + ho];
+          lc.bm[j] = bi;
+        }
+      }
+      const int vchk0 = (cd.flags & 2) ? 0 : ho0;
+      switch (cd.top_kind) {
+        case bbp::CAP_NONE: pass1_rows<bbp::CAP_NONE>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_LT: pass1_rows<bbp::CAP_F_LT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_EQ: pass1_rows<bbp::CAP_F_EQ>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_GT: pass1_rows<bbp::CAP_F_GT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_B_GT: pass1_rows<bbp::CAP_B_GT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_B_EQ: pass1_rows<bbp::CAP_B_EQ>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        default:            pass1_rows<bbp::CAP_B_LT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+      }
+      __syncthreads();
+      // ---- pass 2 -----------------------------------------------------------------------------------
+      const int bl = bbp::pos_bit(kp, kp - 1);
+      const int hol = (h & bl) ? 1 : 0;
+      const float* Tl = Tt + (kp - 1) * 16;
+      const int vil = (h & bbp::pos_bit(kp, kp - 2)) ? 1 : 0;
+      const float l00 = Tl[vil * 8 + hol * 4 + 0 * 2 + hol], l01 = Tl[vil * 8 + (1 - hol) * 4 + 0 * 2 + hol];
+      const float l10 = Tl[vil * 8 + hol * 4 + 1 * 2 + hol], l11 = Tl[vil * 8 + (1 - hol) * 4 + 1 * 2 + hol];
+      const int vchkl = (cd.flags & 8) ? 0 : hol;
+      float ss;
+      switch (cd.bot_kind) {
+        case bbp::CAP_NONE: ss = pass2_rows<bbp::CAP_NONE>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_LT: ss = pass2_rows<bbp::CAP_F_LT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_EQ: ss = pass2_rows<bbp::CAP_F_EQ>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_GT: ss = pass2_rows<bbp::CAP_F_GT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_B_GT: ss = pass2_rows<bbp::CAP_B_GT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_B_EQ: ss = pass2_rows<bbp::CAP_B_EQ>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        default:            ss = pass2_rows<bbp::CAP_B_LT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+      }
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      if (lane == 0) red[wid] = ss;
     }
-    const float tot = block_sum(ss, red);
-    const float nrm = sqrtf(tot);
-    const float inv = (nrm > 0.0f) ? 1.0f / nrm : 0.0f;
-    for (int idx = tid; idx < nA; idx += NT) A[idx] *= inv;
-    logscale += (double)logf(nrm);
-    Pt = Ptn;
-    Ps = Psn;
     __syncthreads();
+    float tot = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += red[w];
+    const float nrm = sqrtf(tot);
+    scale = (nrm > 0.0f) ? 1.0f / nrm : 0.0f;
+    logscale += (double)logf(nrm);
+    Ps = Psn;
   }
+  if (wid != 0) return;
 
+  const float fin = (lane < H) ? A[lane] * scale : 0.0f;
   if (mode == 1) {
     // closing contraction with the message from the receiver side (or the grid edge)
-    if (tid < 64) {
-      double w = 0.0;
-      if (s.msg_close >= 0) {
-        const float* mc = mbase + s.msg_close * MSTRIDE;
-        for (int h = tid; h < H; h += 64) w += (double)mc[h] * (double)A[h];
-      } else if (tid == 0) {
-        w = A[0];
-      }
-      w = wave_sum_d(w);
-      if (tid == 0) lnW[job * nblocks + s.block] = (w > 0.0) ? logscale + log(w) : NAN;
-    }
+    double w = 0.0;
+    if (s.msg_close >= 0) w = (double)mbase[s.msg_close * MSTRIDE + lane] * (double)fin;
+    else if (lane == 0) w = fin;
+    w = wave_sum_d(w);
+    if (lane == 0) lnW[job * nblocks + s.block] = (w > 0.0) ? logscale + log(w) : NAN;
     return;
   }
-  // normalised new message, damping against the old one, distance term (first wave)
-  if (tid < 64) {
-    float* mo = msgs + job * M * MSTRIDE + s.msg_out * MSTRIDE;
-    const float old = (tid < H) ? mo[tid] : 0.0f;
-    const float nw = (tid < H) ? A[tid] : 0.0f;
-    const double n2 = wave_sum_d((double)nw * nw);
-    const float inv = (float)(1.0 / sqrt(n2));
-    const float dm = (1.0f - eta) * (nw * inv) + eta * old;
-    const double dd = wave_sum_d((double)dm * dm);
-    const double od = wave_sum_d((double)old * old);
-    const double c = wave_sum_d((double)dm * old);
-    const float fin = dm * (float)(1.0 / sqrt(dd));
-    if (tid < H) mo[tid] = fin;
-    if (tid == 0) terms[job * M + s.msg_out] = 2.0 - 2.0 * (c * c) / (dd * od);
-  }
+  // normalised new message, damping against the old one, distance term
+  float* mo = msgs + job * M * MSTRIDE + s.msg_out * MSTRIDE;
+  const float old = (lane < H) ? mo[lane] : 0.0f;
+  const double n2 = wave_sum_d((double)fin * fin);
+  const float inv = (float)(1.0 / sqrt(n2));
+  const float dm = (1.0f - eta) * (fin * inv) + eta * old;
+  const double dd = wave_sum_d((double)dm * dm);
+  const double od = wave_sum_d((double)old * old);
+  const double c = wave_sum_d((double)dm * old);
+  const float fm = dm * (float)(1.0 / sqrt(dd));
+  if (lane < H) mo[lane] = fm;
+  if (lane == 0) terms[job * M + s.msg_out] = 2.0 - 2.0 * (c * c) / (dd * od);
 }
 
 __global__ void delta_kernel(const double* __restrict__ terms, int M, int64_t jobs, int32_t* __restrict__ conv,
@@ -373,6 +504,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 // --------------------------------------------------------------------------------------------------
 struct DevPlan {
   bbp::Plan plan;
+  bbp::ColumnDesc* cols = nullptr;
   SweepDesc* round[2] = {nullptr, nullptr};
   SweepDesc* bethe = nullptr;
   int32_t* edge_len = nullptr;
@@ -422,6 +554,8 @@ int device_plan(int d, const bbp_opts* o, DevPlan** out) {
     if (!p.round[c].empty())
       HIP_TRY(hipMemcpy(dp->round[c], p.round[c].data(), sizeof(SweepDesc) * p.round[c].size(), hipMemcpyHostToDevice));
   }
+  HIP_TRY(hipMalloc(&dp->cols, sizeof(bbp::ColumnDesc) * p.columns.size()));
+  HIP_TRY(hipMemcpy(dp->cols, p.columns.data(), sizeof(bbp::ColumnDesc) * p.columns.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMalloc(&dp->bethe, sizeof(SweepDesc) * p.bethe.size()));
   HIP_TRY(hipMemcpy(dp->bethe, p.bethe.data(), sizeof(SweepDesc) * p.bethe.size(), hipMemcpyHostToDevice));
   std::vector<int32_t> el(p.edge_len.begin(), p.edge_len.end());
@@ -626,7 +760,7 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
     for (int c = 0; c < 2; ++c) {
       if (P.round[c].empty()) continue;
       update_kernel<<<dim3((unsigned)jobs, (unsigned)P.round[c].size()), dim3(NT), 0, st>>>(
-          dp->round[c], d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 0, lnw,
+          dp->round[c], dp->cols, d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 0, lnw,
           P.nblocks);
       HIP_TRY(hipGetLastError());
       if ((rc = mark())) return rc;
@@ -643,7 +777,7 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
     iv_flops.push_back(0.0);
   }
   update_kernel<<<dim3((unsigned)jobs, (unsigned)P.bethe.size()), dim3(NT), 0, st>>>(
-      dp->bethe, d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 1, lnw, P.nblocks);
+      dp->bethe, dp->cols, d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 1, lnw, P.nblocks);
   HIP_TRY(hipGetLastError());
   if ((rc = mark())) return rc;
   kinds.push_back(2);

@@ -39,10 +39,12 @@ BBP_HD void frame_site(int frame, int r0, int c0, int kr, int kc, int t, int i, 
 // first j legs, later bonds the remaining K-j legs.
 BBP_HD int cap_dim(int K, int j) { return (j <= K / 2) ? (1 << j) : (1 << (K - j)); }
 
-// 16-entry frame table T[vi][hi][vo][ho] (index vi*8 + hi*4 + vo*2 + ho) of the tensor at grid site (r, c)
-// for a sweep toward `frame`. label bit 0 = x, bit 1 = z of f_s L at the site; pi[x*2+z] is the noise
-// table. Legs that leave the grid have dimension 1 and are padded with zeros at value 1.
-BBP_HD void site_table(int frame, int L, int r, int c, int label, const float* pi, float* T) {
+// Entry e = vi*8 + hi*4 + vo*2 + ho of the frame table T[vi][hi][vo][ho] of the tensor at grid site (r, c)
+// for a sweep toward `frame`. label bit 0 = x, bit 1 = z of f_s L at the site; pi = noise table
+// {p(I), p(Z), p(X), p(Y)} indexed x*2 + z. Legs that leave the grid have dimension 1 and are padded with
+// zeros at value 1.
+BBP_HD float site_entry(int frame, int L, int r, int c, int label, float p00, float p01, float p10, float p11,
+                        int e) {
   const bool au = (r == 0), al = (c == 0), ad = (r == L - 1), ar = (c == L - 1);
   bool a_up, a_in, a_dn, a_out;
   switch (frame) {
@@ -51,34 +53,29 @@ BBP_HD void site_table(int frame, int L, int r, int c, int label, const float* p
     case FRAME_S: a_up = al; a_in = au; a_dn = ar; a_out = ad; break;
     default:      a_up = al; a_in = ad; a_dn = ar; a_out = au; break;
   }
-  const bool qubit = ((r + c) & 1) == 0;
-  const bool swap = ((r & 1) != 0) != (frame >= FRAME_S);
-  const int x = label & 1, z = (label >> 1) & 1;
-  for (int e = 0; e < 16; ++e) {
-    const int vi = (e >> 3) & 1, hi = (e >> 2) & 1, vo = (e >> 1) & 1, ho = e & 1;
-    float val;
-    if ((a_up && vi) || (a_in && hi) || (a_dn && vo) || (a_out && ho)) {
-      val = 0.0f;
-    } else if (qubit) {
-      const int pv = vi ^ vo, ph = hi ^ ho;
-      const int ex = x ^ (swap ? ph : pv);
-      const int ez = z ^ (swap ? pv : ph);
-      val = pi[ex * 2 + ez];
-    } else {
-      // COPY: all present legs equal (absent legs are pinned to 0 and take no part)
-      int ref = -1;
-      bool ok = true;
-      const int vals[4] = {vi, hi, vo, ho};
-      const bool abs4[4] = {a_up, a_in, a_dn, a_out};
-      for (int k = 0; k < 4; ++k) {
-        if (abs4[k]) continue;
-        if (ref < 0) ref = vals[k];
-        else if (vals[k] != ref) ok = false;
-      }
-      val = ok ? 1.0f : 0.0f;
-    }
-    T[e] = val;
+  const int vi = (e >> 3) & 1, hi = (e >> 2) & 1, vo = (e >> 1) & 1, ho = e & 1;
+  if ((a_up && vi) || (a_in && hi) || (a_dn && vo) || (a_out && ho)) return 0.0f;
+  if (((r + c) & 1) == 0) {
+    const bool swap = ((r & 1) != 0) != (frame >= FRAME_S);
+    const int pv = vi ^ vo, ph = hi ^ ho;
+    const int ex = (label & 1) ^ (swap ? ph : pv);
+    const int ez = ((label >> 1) & 1) ^ (swap ? pv : ph);
+    const int k = ex * 2 + ez;
+    return (k == 0) ? p00 : (k == 1) ? p01 : (k == 2) ? p10 : p11;
   }
+  // COPY: all present legs equal (absent legs are pinned to 0 and take no part)
+  int ref = -1;
+  bool ok = true;
+  if (!a_up) ref = vi;
+  if (!a_in) { if (ref < 0) ref = hi; else if (hi != ref) ok = false; }
+  if (!a_dn) { if (ref < 0) ref = vo; else if (vo != ref) ok = false; }
+  if (!a_out) { if (ref < 0) ref = ho; else if (ho != ref) ok = false; }
+  return ok ? 1.0f : 0.0f;
+}
+
+// All 16 entries of the frame table (see site_entry).
+BBP_HD void site_table(int frame, int L, int r, int c, int label, const float* pi, float* T) {
+  for (int e = 0; e < 16; ++e) T[e] = site_entry(frame, L, r, c, label, pi[0], pi[1], pi[2], pi[3], e);
 }
 
 }  // namespace bbp

@@ -23,6 +23,7 @@
 #include <tuple>
 
 #include "geom.hpp"
+#include "sweep.hpp"
 
 namespace bbp {
 
@@ -247,29 +248,29 @@ int analyse_sweep(const Plan& p, const SweepDesc& s, Rng& rng) {
 }
 
 double sweep_flops(const Plan& p, const SweepDesc& s) {
-  const int kt = s.kt, kp = s.kp, H = 1 << kp, K = kt, D = K / 2;
-  const bool fwd = (s.frame == FRAME_E || s.frame == FRAME_S);
+  // algorithmic flops of the column passes of sweep.hpp: a qubit between two checks is a 2x2 transform
+  // (2 multiply-adds per state entry), a qubit at an end of the column also sums over the emitted cap leg
+  // (4 multiply-adds per entry), the middle site of a side message contracts the cap index (one
+  // multiply-add per old cap value), the normalisation costs 3 flops per entry; copies cost nothing
+  const int H = 1 << s.kp;
   double f = 0.0;
-  int Pt = 1, Ps = 1;
-  for (int t = 0; t < kt; ++t) {
-    const int js = fwd ? t : kt - 1 - t;
-    const int bnew = fwd ? t + 1 : kt - 1 - t;
-    const int Ptn = s.msg_top >= 0 ? cap_dim(K, bnew) : 1;
-    const int Psn = s.msg_bot >= 0 ? cap_dim(K, bnew) : 1;
-    const double mid = (double)Ptn * 2 * H * Ps;
-    if (s.msg_top >= 0 && js == D) f += mid * 2.0 * Pt;
-    for (int i = 0; i < kp; ++i) {
-      int r, c;
-      frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, t, i, r, c);
-      if (((r + c) & 1) == 0) f += 8.0 * mid;
-    }
-    const double outn = (double)Ptn * H * Psn;
-    if (s.msg_bot >= 0 && js == D) f += outn * 2.0 * 2.0 * Ps;
-    f += 2.0 * outn;      // normalisation
-    Pt = Ptn;
-    Ps = Psn;
+  int Ps = 1;
+  for (int t = 0; t < s.kt; ++t) {
+    Column col;
+    make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, s.kt, s.kp, p.L, t, s.msg_top >= 0, s.msg_bot >= 0);
+    const double mid = (double)col.top.Pnew * H * Ps;
+    const double outn = (double)col.top.Pnew * H * col.bot.Pnew;
+    const bool teq = (col.top.kind == CAP_F_EQ || col.top.kind == CAP_B_EQ);
+    const bool beq = (col.bot.kind == CAP_F_EQ || col.bot.kind == CAP_B_EQ);
+    if (col.q0 || col.single) f += 8.0 * mid;
+    if (teq) f += 2.0 * col.top.Pold * mid * ((col.q0 || col.single) ? 2.0 : 1.0);
+    f += 4.0 * col.nmid * mid;
+    if (col.qlast && !col.single) f += 8.0 * outn;
+    if (beq) f += 2.0 * col.bot.Pold * outn * ((col.qlast || col.single) ? 2.0 : 1.0);
+    f += 3.0 * outn;
+    Ps = col.bot.Pnew;
   }
-  f += 10.0 * H;          // final normalisation, damping, distance term or closing overlap
+  f += 10.0 * H;      // final normalisation, damping and distance term, or the closing overlap
   return f;
 }
 
@@ -348,6 +349,27 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       p.bethe.push_back(s);
       p.flops_bethe += s.flops;
     }
+  // per-column descriptors of every sweep
+  auto add_columns = [&](SweepDesc& s) {
+    s.col_off = (int32_t)p.columns.size();
+    for (int t = 0; t < s.kt; ++t) {
+      Column col;
+      make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, s.kt, s.kp, p.L, t, s.msg_top >= 0, s.msg_bot >= 0);
+      ColumnDesc cd;
+      std::memset(&cd, 0, sizeof(cd));
+      cd.top_kind = col.top.kind; cd.top_Pold = col.top.Pold; cd.top_Pnew = col.top.Pnew; cd.top_R2 = col.top.R2;
+      cd.bot_kind = col.bot.kind; cd.bot_Pold = col.bot.Pold; cd.bot_Pnew = col.bot.Pnew; cd.bot_R2 = col.bot.R2;
+      cd.flags = (col.q0 ? 1 : 0) | (col.up_absent0 ? 2 : 0) | (col.qlast ? 4 : 0) | (col.dn_absent_last ? 8 : 0) |
+                 (col.single ? 16 : 0);
+      cd.nmid = col.nmid;
+      cd.mids = col.m0 | (col.m1 << 4) | (col.m2 << 8);
+      cd.in_absent = col.in_absent;
+      cd.out_absent = col.out_absent;
+      p.columns.push_back(cd);
+    }
+  };
+  for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) add_columns(s);
+  for (auto& s : p.bethe) add_columns(s);
   for (int e = 0; e < p.M; ++e)
     if (p.edge_src[e] < p.edge_dst[e]) {
       p.pair_ids.push_back(e);
@@ -377,23 +399,21 @@ Plan make_plan(int d, int kr, int kc, int chi) {
   const int kmax = std::max(*std::max_element(p.rowsz.begin(), p.rowsz.end()),
                             *std::max_element(p.colsz.begin(), p.colsz.end()));
   // largest dense boundary state of any sweep (the device keeps it in 4096-entry LDS buffers)
-  size_t max_state = 0;
+  size_t max_state = 0, max_mid = 0;
   auto state_size = [&](const SweepDesc& s) {
-    const int K = s.kt, H = 1 << s.kp;
-    const bool fwd = (s.frame == FRAME_E || s.frame == FRAME_S);
     int Ps = 1;
     for (int t = 0; t < s.kt; ++t) {
-      const int bnew = fwd ? t + 1 : s.kt - 1 - t;
-      const int Ptn = s.msg_top >= 0 ? cap_dim(K, bnew) : 1;
-      const int Psn = s.msg_bot >= 0 ? cap_dim(K, bnew) : 1;
-      max_state = std::max(max_state, (size_t)Ptn * 2 * H * Ps);
-      max_state = std::max(max_state, (size_t)Ptn * H * Psn);
-      Ps = Psn;
+      Column col;
+      make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, s.kt, s.kp, p.L, t, s.msg_top >= 0, s.msg_bot >= 0);
+      const size_t H = 64;   // the device stores rows of 64 lanes
+      max_mid = std::max(max_mid, (size_t)col.top.Pnew * H * Ps * (col.single ? 2 : 1));
+      max_state = std::max(max_state, (size_t)col.top.Pnew * H * col.bot.Pnew);
+      Ps = col.bot.Pnew;
     }
   };
   for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) state_size(s);
   for (auto& s : p.bethe) state_size(s);
-  if (kmax > 6 || max_state > 4096) {
+  if (kmax > 6 || max_state > 4096 || max_mid > 2048) {
     p.gpu_ok = false;
     p.why = "blocks larger than 6 tensors per side are not implemented on the GPU";
   } else if (!msg_exact) {
@@ -410,29 +430,58 @@ Plan make_plan(int d, int kr, int kc, int chi) {
 
 int host_sweep(const Plan& p, const SweepDesc& s, const uint8_t* labels, const float* pi, const double* msgs,
                double* out, double* logscale) {
-  const int kt = s.kt, kp = s.kp;
-  std::vector<double> tables((size_t)kt * kp * 16);
+  // the kernel's algorithm (sweep.hpp), evaluated sequentially in float64 with float32 inputs
+  const int kt = s.kt, kp = s.kp, H = 1 << kp, L = p.L;
+  std::vector<float> tables((size_t)kt * kp * 16);
   for (int t = 0; t < kt; ++t)
     for (int i = 0; i < kp; ++i) {
       int r, c;
       frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, t, i, r, c);
-      float T[16];
-      site_table(s.frame, p.L, r, c, labels[r * p.L + c], pi, T);
-      for (int e = 0; e < 16; ++e) tables[(size_t)(t * kp + i) * 16 + e] = T[e];
+      site_table(s.frame, L, r, c, labels[r * L + c], pi, &tables[(size_t)(t * kp + i) * 16]);
     }
-  auto m = [&](int id) -> const double* { return id >= 0 ? msgs + (size_t)id * 64 : nullptr; };
-  std::vector<double> A;
-  double ls = 0.0;
-  generic_sweep<F64>(s, tables.data(), m(s.msg_init), m(s.msg_top), m(s.msg_bot), A,
-                     [&](int, std::vector<double>& St, int Pt, int H, int Ps) {
-                       double ss = 0.0;
-                       const size_t n = (size_t)Pt * H * Ps;
-                       for (size_t k = 0; k < n; ++k) ss += St[k] * St[k];
-                       const double nrm = std::sqrt(ss);
-                       for (size_t k = 0; k < n; ++k) St[k] /= nrm;
-                       ls += std::log(nrm);
-                     });
-  for (int h = 0; h < (1 << kp); ++h) out[h] = A[h];
+  std::vector<float> mt(64, 0.0f), mb(64, 0.0f);
+  if (s.msg_top >= 0) for (int h = 0; h < 64; ++h) mt[h] = (float)msgs[(size_t)s.msg_top * 64 + h];
+  if (s.msg_bot >= 0) for (int h = 0; h < 64; ++h) mb[h] = (float)msgs[(size_t)s.msg_bot * 64 + h];
+  std::vector<double> A(H, 0.0), B;
+  if (s.msg_init >= 0) for (int h = 0; h < H; ++h) A[h] = (float)msgs[(size_t)s.msg_init * 64 + h];
+  else A[0] = 1.0;
+  int Ps = 1;
+  double scale = 1.0, ls = 0.0;
+  for (int t = 0; t < kt; ++t) {
+    Column col;
+    make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, kt, kp, L, t, s.msg_top >= 0, s.msg_bot >= 0);
+    const float* T = &tables[(size_t)t * kp * 16];
+    const int Ptn = col.top.Pnew, Psn = col.bot.Pnew;
+    const int HB = col.single ? 2 * H : H;
+    B.assign((size_t)Ptn * HB * Ps, 0.0);
+    auto getA = [&](int n, int h, int sb) { return scale * A[((size_t)n * H + h) * Ps + sb]; };
+    auto put = [&](int np, int h, int sb, double v) { B[((size_t)np * H + h) * Ps + sb] = v; };
+    if (col.single) {
+      for (int np = 0; np < Ptn; ++np)
+        for (int sb = 0; sb < Ps; ++sb) pass1_item<double>(col, T, mt.data(), np, 0, sb, getA, put);
+    } else {
+      for (int np = 0; np < Ptn; ++np)
+        for (int h = 0; h < H; ++h) {
+          if (h & col.gmask) continue;
+          for (int sb = 0; sb < Ps; ++sb) pass1_item<double>(col, T, mt.data(), np, h, sb, getA, put);
+        }
+    }
+    auto getB = [&](int n, int h, int sb) { return B[((size_t)n * H + h) * Ps + sb]; };
+    A.assign((size_t)Ptn * H * Psn, 0.0);
+    double ss = 0.0;
+    for (int n = 0; n < Ptn; ++n)
+      for (int h = 0; h < H; ++h)
+        for (int sp = 0; sp < Psn; ++sp) {
+          const double v = pass2_output<double>(col, T, mb.data(), n, h, sp, getB);
+          A[((size_t)n * H + h) * Psn + sp] = v;
+          ss += v * v;
+        }
+    const double nrm = std::sqrt(ss);
+    scale = 1.0 / nrm;
+    ls += std::log(nrm);
+    Ps = Psn;
+  }
+  for (int h = 0; h < H; ++h) out[h] = A[h] * scale;
   *logscale = ls;
   return 0;
 }

@@ -79,12 +79,13 @@ def _dense_msgs(plan, rng):
         K = plan.msg_len(src, dst)
         v = rng.uniform(0.05, 1.0, size=2 ** K)
         v /= np.linalg.norm(v)
+        v = v.astype(np.float32).astype(np.float64)     # the library stores messages in float32
         out[e, : 2 ** K] = v
         mps_msgs[(src, dst)], _ = mps.canonical_message(mps.from_dense(v[None], [2] * K), 64)
     return out, mps_msgs
 
 
-@pytest.mark.parametrize("d,k", [(5, 3), (7, 4), (7, 6), (9, 6)])
+@pytest.mark.parametrize("d,k", [(3, 2), (5, 3), (5, 4), (7, 4), (7, 6), (9, 6), (7, 5), (4, 3), (5, 1)])
 def test_reference_sweep_matches_oracle(bbp, d, k):
     # every directed update and every closing sweep of the plan, on one coset of one syndrome
     rng = np.random.default_rng(d * 10 + k)
@@ -106,7 +107,7 @@ def test_reference_sweep_matches_oracle(bbp, d, k):
         ref, lr = blockbp.block_sweep(plan, tensors, mmsgs, src[0], src[1], dname, 64, (1,))
         refv = mps.to_dense(ref)[0]
         n = refv.size
-        np.testing.assert_allclose(got[:n] * np.exp(ls), refv * np.exp(lr[0]), rtol=1e-9,
+        np.testing.assert_allclose(got[:n] * np.exp(ls), refv * np.exp(lr[0]), rtol=1e-7,
                                    atol=1e-12 * np.abs(refv).max() * np.exp(lr[0]))
         assert np.all(got[n:] == 0)
     for b, (I, J) in enumerate(plan.blocks):
@@ -120,4 +121,4 @@ def test_reference_sweep_matches_oracle(bbp, d, k):
         else:
             w = mps.to_dense(st)[0][0]
             wg = got[0]
-        np.testing.assert_allclose(np.log(wg) + ls, np.log(w) + lr[0], atol=1e-9)
+        np.testing.assert_allclose(np.log(wg) + ls, np.log(w) + lr[0], atol=1e-7)
