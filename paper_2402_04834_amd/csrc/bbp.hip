@@ -38,7 +38,7 @@ using bbp::SweepDesc;
 
 namespace {
 
-constexpr int NT = 256;          // threads per update workgroup
+constexpr int NT = 256;          // threads per update workgroup (4 waves)
 constexpr int SMAX = 4096;       // max dense boundary-state entries (6x6 blocks, caps of dimension 8)
 constexpr int BMAX = 2048;       // max pass-1 intermediate (top cap advanced, bottom cap not yet)
 constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
@@ -146,39 +146,66 @@ __device__ __forceinline__ float capv(const float* __restrict__ m, int Pold, int
 }
 
 struct LaneCoef {
-  // site 0 (qubit): coefficients for (v, own / partner input bit); middle qubits: own / partner
+  // site 0 (qubit): coefficients for (emitted leg v, own / partner input bit), scaled by the column scale;
+  // middle qubits: own / partner
   float q00, q01, q10, q11;
   float cm_own[3], cm_par[3];
-  int bm[3];
+  int am[3];      // byte addresses of the partner lanes of the middle qubits (ds_bpermute)
 };
 
 constexpr int NW = NT / 64;
 
+// cross-lane read of `x` from the lane whose byte address is `addr` (= 4 * lane)
+__device__ __forceinline__ float lane_read(int addr, float x) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
+
+// Kinds whose emitted leg is fixed by the new cap index (one of the two values of v is zero).
+template <int KIND>
+__device__ __forceinline__ constexpr bool single_v() {
+  return KIND == bbp::CAP_NONE || KIND == bbp::CAP_F_LT || KIND == bbp::CAP_B_GT;
+}
+template <int KIND>
+__device__ __forceinline__ int the_v(int np, int lPold) {
+  if constexpr (KIND == bbp::CAP_NONE) return 0;
+  else if constexpr (KIND == bbp::CAP_F_LT) return np & 1;
+  else return np >> lPold;
+}
+
 // pass 1 (A -> B): top cap of kind KIND, site 0 and the middle qubits, for this wave's rows
 template <int KIND>
 __device__ __forceinline__ void pass1_rows(const bbp::ColumnDesc& cd, const LaneCoef& lc, const float* A, float* B,
-                                           const float* mt, int h, int hr, int b0, int vchk, int Ptn, int Pso,
+                                           const float* mt, int h, int hr, int a0, int vchk, int Ptn, int Pso,
                                            int lso, float sc, int wid) {
   const bool q0 = cd.flags & 1;
   const int lPold = __builtin_ctz(cd.top_Pold);
   const int stride = Pso * 64;
+  const int nmid = cd.nmid;
+#pragma unroll 4
   for (int row = wid; row < Ptn * Pso; row += NW) {
     const int np = row >> lso, sb = row & (Pso - 1);
     const float* base = A + sb * 64 + hr;
     float out;
     if (q0) {
-      const float f0 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 0, base, stride, sc);
-      const float f1 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 1, base, stride, sc);
-      const float g0 = __shfl_xor(f0, b0);
-      const float g1 = __shfl_xor(f1, b0);
-      out = lc.q00 * f0 + lc.q01 * g0 + lc.q10 * f1 + lc.q11 * g1;
+      if constexpr (single_v<KIND>()) {
+        const int v = the_v<KIND>(np, lPold);
+        const float f = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, v, base, stride, 1.0f);
+        const float g = lane_read(a0, f);
+        out = v ? (lc.q10 * f + lc.q11 * g) : (lc.q00 * f + lc.q01 * g);
+      } else {
+        const float f0 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 0, base, stride, 1.0f);
+        const float f1 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 1, base, stride, 1.0f);
+        const float g0 = lane_read(a0, f0);
+        const float g1 = lane_read(a0, f1);
+        out = lc.q00 * f0 + lc.q01 * g0 + lc.q10 * f1 + lc.q11 * g1;
+      }
     } else {
-      out = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, vchk, base, stride, sc);
+      out = sc * capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, vchk, base, stride, 1.0f);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      if (j < cd.nmid) {
-        const float par = __shfl_xor(out, lc.bm[j]);
+      if (j < nmid) {
+        const float par = lane_read(lc.am[j], out);
         out = lc.cm_own[j] * out + lc.cm_par[j] * par;
       }
     }
@@ -190,21 +217,29 @@ __device__ __forceinline__ void pass1_rows(const bbp::ColumnDesc& cd, const Lane
 // wave-local sum of squares
 template <int KIND>
 __device__ __forceinline__ float pass2_rows(const bbp::ColumnDesc& cd, const float* B, float* A, const float* mb,
-                                            int h, int kp, int bl, int vchk, float l00, float l01, float l10,
+                                            int h, int kp, int al, int vchk, float l00, float l01, float l10,
                                             float l11, int Ptn, int Pso, int Psn, int lsn, int wid) {
   const bool ql = cd.flags & 4;
   const int lPold = __builtin_ctz(cd.bot_Pold);
   float ss = 0.0f;
+#pragma unroll 4
   for (int row = wid; row < Ptn * Psn; row += NW) {
     const int n = row >> lsn, sp = row & (Psn - 1);
     const float* base = B + n * Pso * 64 + h;
     float out;
     if (ql) {
-      const float f0 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 0, base, 64, 1.0f);
-      const float f1 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 1, base, 64, 1.0f);
-      const float g0 = __shfl_xor(f0, bl);
-      const float g1 = __shfl_xor(f1, bl);
-      out = l00 * f0 + l01 * g0 + l10 * f1 + l11 * g1;
+      if constexpr (single_v<KIND>()) {
+        const int v = the_v<KIND>(sp, lPold);
+        const float f = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, v, base, 64, 1.0f);
+        const float g = lane_read(al, f);
+        out = v ? (l10 * f + l11 * g) : (l00 * f + l01 * g);
+      } else {
+        const float f0 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 0, base, 64, 1.0f);
+        const float f1 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 1, base, 64, 1.0f);
+        const float g0 = lane_read(al, f0);
+        const float g1 = lane_read(al, f1);
+        out = l00 * f0 + l01 * g0 + l10 * f1 + l11 * g1;
+      }
     } else {
       out = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, vchk, base, 64, 1.0f);
     }
@@ -229,18 +264,20 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
                                                     const int32_t* __restrict__ conv, float p0, float p1, float p2,
                                                     float p3, float eta, int mode, double* __restrict__ lnW,
                                                     int nblocks) {
-  const int64_t job = blockIdx.x;
-  if (mode == 0 && conv[job]) return;
-  const SweepDesc s = sweeps[blockIdx.y];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform within the wave
   const int L = 2 * d - 1;
-  const int kt = s.kt, kp = s.kp, H = 1 << kp;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   __shared__ float A[SMAX];
   __shared__ float B[BMAX];
   __shared__ float T[36 * 16];
   __shared__ float mt[MSTRIDE], mb[MSTRIDE];
   __shared__ float red[NW];
+
+  const int64_t job = blockIdx.x;
+  if (mode == 0 && conv[job]) return;
+  const SweepDesc s = sweeps[blockIdx.y];
+  const int kt = s.kt, kp = s.kp, H = 1 << kp;
 
   const uint8_t* lab = labels + job * L * L;
   for (int q = tid; q < kt * kp * 16; q += NT) {
@@ -265,6 +302,8 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
   for (int t = 0; t < kt; ++t) {
     const bbp::ColumnDesc cd = cols[s.col_off + t];
     const float* Tt = &T[t * kp * 16];
+    // frame-table entry T(vi, hi, vo, ho) of the site at position i of this column
+    auto coef = [&](int i, int vi, int hi, int vo, int ho) { return Tt[i * 16 + vi * 8 + hi * 4 + vo * 2 + ho]; };
     const int Ptn = cd.top_Pnew, Psn = cd.bot_Pnew, Pso = Ps;
     const int lso = __builtin_ctz(Pso), lsn = __builtin_ctz(Psn);
     const float sc = scale;
@@ -291,7 +330,7 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
               auto get = [&](int sb) { return B[((n * 2 + vt) * Pso + sb) * 64 + h]; };
               const float f = bbp::cap_phi<float>(bot, mb, sp, vb, get);
               const float g = __shfl_xor(f, 1);
-              out += Tt[vt * 8 + hol * 4 + vb * 2 + hol] * f + Tt[vt * 8 + (1 - hol) * 4 + vb * 2 + hol] * g;
+              out += coef(0, vt, hol, vb, hol) * f + coef(0, vt, 1 - hol, vb, hol) * g;
             }
         } else {
           const int vt = (cd.flags & 2) ? 0 : hol;
@@ -314,54 +353,55 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
       const int b0 = bbp::pos_bit(kp, 0);
       const int ho0 = (h & b0) ? 1 : 0;
       const int vo0 = (h & bbp::pos_bit(kp, 1)) ? 1 : 0;
-      lc.q00 = Tt[0 * 8 + ho0 * 4 + vo0 * 2 + ho0];
-      lc.q01 = Tt[0 * 8 + (1 - ho0) * 4 + vo0 * 2 + ho0];
-      lc.q10 = Tt[1 * 8 + ho0 * 4 + vo0 * 2 + ho0];
-      lc.q11 = Tt[1 * 8 + (1 - ho0) * 4 + vo0 * 2 + ho0];
+      lc.q00 = sc * coef(0, 0, ho0, vo0, ho0);
+      lc.q01 = sc * coef(0, 0, 1 - ho0, vo0, ho0);
+      lc.q10 = sc * coef(0, 1, ho0, vo0, ho0);
+      lc.q11 = sc * coef(0, 1, 1 - ho0, vo0, ho0);
+      const int a0 = (h ^ b0) << 2;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         lc.cm_own[j] = 0.0f;
         lc.cm_par[j] = 0.0f;
-        lc.bm[j] = 0;
+        lc.am[j] = h << 2;
         if (j < cd.nmid) {
           const int i = (cd.mids >> (4 * j)) & 15;
           const int bi = bbp::pos_bit(kp, i);
           const int vi = (h & bbp::pos_bit(kp, i - 1)) ? 1 : 0;
           const int vo = (h & bbp::pos_bit(kp, i + 1)) ? 1 : 0;
           const int ho = (h & bi) ? 1 : 0;
-          lc.cm_own[j] = Tt[i * 16 + vi * 8 + ho * 4 + vo * 2 + ho];
-          lc.cm_par[j] = Tt[i * 16 + vi * 8 + (1 - ho) * 4 + vo * 2 + ho];
-          lc.bm[j] = bi;
+          lc.cm_own[j] = coef(i, vi, ho, vo, ho);
+          lc.cm_par[j] = coef(i, vi, 1 - ho, vo, ho);
+          lc.am[j] = (h ^ bi) << 2;
         }
       }
       const int vchk0 = (cd.flags & 2) ? 0 : ho0;
       switch (cd.top_kind) {
-        case bbp::CAP_NONE: pass1_rows<bbp::CAP_NONE>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_LT: pass1_rows<bbp::CAP_F_LT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_EQ: pass1_rows<bbp::CAP_F_EQ>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_GT: pass1_rows<bbp::CAP_F_GT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_B_GT: pass1_rows<bbp::CAP_B_GT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_B_EQ: pass1_rows<bbp::CAP_B_EQ>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        default:            pass1_rows<bbp::CAP_B_LT>(cd, lc, A, B, mt, h, hr, b0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_NONE: pass1_rows<bbp::CAP_NONE>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_LT: pass1_rows<bbp::CAP_F_LT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_EQ: pass1_rows<bbp::CAP_F_EQ>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_F_GT: pass1_rows<bbp::CAP_F_GT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_B_GT: pass1_rows<bbp::CAP_B_GT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        case bbp::CAP_B_EQ: pass1_rows<bbp::CAP_B_EQ>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
+        default:            pass1_rows<bbp::CAP_B_LT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
       }
       __syncthreads();
       // ---- pass 2 -----------------------------------------------------------------------------------
       const int bl = bbp::pos_bit(kp, kp - 1);
       const int hol = (h & bl) ? 1 : 0;
-      const float* Tl = Tt + (kp - 1) * 16;
       const int vil = (h & bbp::pos_bit(kp, kp - 2)) ? 1 : 0;
-      const float l00 = Tl[vil * 8 + hol * 4 + 0 * 2 + hol], l01 = Tl[vil * 8 + (1 - hol) * 4 + 0 * 2 + hol];
-      const float l10 = Tl[vil * 8 + hol * 4 + 1 * 2 + hol], l11 = Tl[vil * 8 + (1 - hol) * 4 + 1 * 2 + hol];
+      const float l00 = coef(kp - 1, vil, hol, 0, hol), l01 = coef(kp - 1, vil, 1 - hol, 0, hol);
+      const float l10 = coef(kp - 1, vil, hol, 1, hol), l11 = coef(kp - 1, vil, 1 - hol, 1, hol);
       const int vchkl = (cd.flags & 8) ? 0 : hol;
+      const int al = (h ^ bl) << 2;
       float ss;
       switch (cd.bot_kind) {
-        case bbp::CAP_NONE: ss = pass2_rows<bbp::CAP_NONE>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_LT: ss = pass2_rows<bbp::CAP_F_LT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_EQ: ss = pass2_rows<bbp::CAP_F_EQ>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_GT: ss = pass2_rows<bbp::CAP_F_GT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_B_GT: ss = pass2_rows<bbp::CAP_B_GT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_B_EQ: ss = pass2_rows<bbp::CAP_B_EQ>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        default:            ss = pass2_rows<bbp::CAP_B_LT>(cd, B, A, mb, h, kp, bl, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_NONE: ss = pass2_rows<bbp::CAP_NONE>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_LT: ss = pass2_rows<bbp::CAP_F_LT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_EQ: ss = pass2_rows<bbp::CAP_F_EQ>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_F_GT: ss = pass2_rows<bbp::CAP_F_GT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_B_GT: ss = pass2_rows<bbp::CAP_B_GT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        case bbp::CAP_B_EQ: ss = pass2_rows<bbp::CAP_B_EQ>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
+        default:            ss = pass2_rows<bbp::CAP_B_LT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
       }
       for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
       if (lane == 0) red[wid] = ss;
@@ -375,30 +415,30 @@ __global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict_
     logscale += (double)logf(nrm);
     Ps = Psn;
   }
-  if (wid != 0) return;
-
-  const float fin = (lane < H) ? A[lane] * scale : 0.0f;
-  if (mode == 1) {
-    // closing contraction with the message from the receiver side (or the grid edge)
-    double w = 0.0;
-    if (s.msg_close >= 0) w = (double)mbase[s.msg_close * MSTRIDE + lane] * (double)fin;
-    else if (lane == 0) w = fin;
-    w = wave_sum_d(w);
-    if (lane == 0) lnW[job * nblocks + s.block] = (w > 0.0) ? logscale + log(w) : NAN;
-    return;
+  if (wid == 0) {
+    const float fin = (lane < H) ? A[lane] * scale : 0.0f;
+    if (mode == 1) {
+      // closing contraction with the message from the receiver side (or the grid edge)
+      double w = 0.0;
+      if (s.msg_close >= 0) w = (double)mbase[s.msg_close * MSTRIDE + lane] * (double)fin;
+      else if (lane == 0) w = fin;
+      w = wave_sum_d(w);
+      if (lane == 0) lnW[job * nblocks + s.block] = (w > 0.0) ? logscale + log(w) : NAN;
+    } else {
+      // normalised new message, damping against the old one, distance term
+      float* mo = msgs + job * M * MSTRIDE + s.msg_out * MSTRIDE;
+      const float old = (lane < H) ? mo[lane] : 0.0f;
+      const double n2 = wave_sum_d((double)fin * fin);
+      const float inv = (float)(1.0 / sqrt(n2));
+      const float dm = (1.0f - eta) * (fin * inv) + eta * old;
+      const double dd = wave_sum_d((double)dm * dm);
+      const double od = wave_sum_d((double)old * old);
+      const double c = wave_sum_d((double)dm * old);
+      const float fm = dm * (float)(1.0 / sqrt(dd));
+      if (lane < H) mo[lane] = fm;
+      if (lane == 0) terms[job * M + s.msg_out] = 2.0 - 2.0 * (c * c) / (dd * od);
+    }
   }
-  // normalised new message, damping against the old one, distance term
-  float* mo = msgs + job * M * MSTRIDE + s.msg_out * MSTRIDE;
-  const float old = (lane < H) ? mo[lane] : 0.0f;
-  const double n2 = wave_sum_d((double)fin * fin);
-  const float inv = (float)(1.0 / sqrt(n2));
-  const float dm = (1.0f - eta) * (fin * inv) + eta * old;
-  const double dd = wave_sum_d((double)dm * dm);
-  const double od = wave_sum_d((double)old * old);
-  const double c = wave_sum_d((double)dm * old);
-  const float fm = dm * (float)(1.0 / sqrt(dd));
-  if (lane < H) mo[lane] = fm;
-  if (lane == 0) terms[job * M + s.msg_out] = 2.0 - 2.0 * (c * c) / (dd * od);
 }
 
 __global__ void delta_kernel(const double* __restrict__ terms, int M, int64_t jobs, int32_t* __restrict__ conv,

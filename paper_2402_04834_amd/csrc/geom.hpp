@@ -39,6 +39,33 @@ BBP_HD void frame_site(int frame, int r0, int c0, int kr, int kc, int t, int i, 
 // first j legs, later bonds the remaining K-j legs.
 BBP_HD int cap_dim(int K, int j) { return (j <= K / 2) ? (1 << j) : (1 << (K - j)); }
 
+// Coefficient T(vi, hi, vo, ho) of a qubit tensor in a sweep frame: the noise probability of its label
+// flipped by the parities of its vertical (vi ^ vo) and crossing (hi ^ ho) legs -- which of x / z each parity
+// flips depends on the edge orientation and the frame (`swap`). absent = bits (up, in, down, out) of legs
+// that leave the grid; such a leg only takes the value 0.
+BBP_HD float qubit_coef(int label, int swap, int absent, float p00, float p01, float p10, float p11, int vi, int hi,
+                        int vo, int ho) {
+  if (((absent & 1) && vi) || ((absent & 2) && hi) || ((absent & 4) && vo) || ((absent & 8) && ho)) return 0.0f;
+  const int pv = vi ^ vo, ph = hi ^ ho;
+  const int ex = (label & 1) ^ (swap ? ph : pv);
+  const int ez = ((label >> 1) & 1) ^ (swap ? pv : ph);
+  const int k = ex * 2 + ez;
+  return (k == 0) ? p00 : (k == 1) ? p01 : (k == 2) ? p10 : p11;
+}
+
+// Entry e = vi*8 + hi*4 + vo*2 + ho of a COPY tensor in a sweep frame: 1 when all present legs agree.
+BBP_HD float copy_coef(int absent, int e) {
+  const int vi = (e >> 3) & 1, hi = (e >> 2) & 1, vo = (e >> 1) & 1, ho = e & 1;
+  if (((absent & 1) && vi) || ((absent & 2) && hi) || ((absent & 4) && vo) || ((absent & 8) && ho)) return 0.0f;
+  int ref = -1;
+  bool ok = true;
+  if (!(absent & 1)) ref = vi;
+  if (!(absent & 2)) { if (ref < 0) ref = hi; else if (hi != ref) ok = false; }
+  if (!(absent & 4)) { if (ref < 0) ref = vo; else if (vo != ref) ok = false; }
+  if (!(absent & 8)) { if (ref < 0) ref = ho; else if (ho != ref) ok = false; }
+  return ok ? 1.0f : 0.0f;
+}
+
 // Entry e = vi*8 + hi*4 + vo*2 + ho of the frame table T[vi][hi][vo][ho] of the tensor at grid site (r, c)
 // for a sweep toward `frame`. label bit 0 = x, bit 1 = z of f_s L at the site; pi = noise table
 // {p(I), p(Z), p(X), p(Y)} indexed x*2 + z. Legs that leave the grid have dimension 1 and are padded with
@@ -54,23 +81,13 @@ BBP_HD float site_entry(int frame, int L, int r, int c, int label, float p00, fl
     default:      a_up = al; a_in = ad; a_dn = ar; a_out = au; break;
   }
   const int vi = (e >> 3) & 1, hi = (e >> 2) & 1, vo = (e >> 1) & 1, ho = e & 1;
-  if ((a_up && vi) || (a_in && hi) || (a_dn && vo) || (a_out && ho)) return 0.0f;
   if (((r + c) & 1) == 0) {
-    const bool swap = ((r & 1) != 0) != (frame >= FRAME_S);
-    const int pv = vi ^ vo, ph = hi ^ ho;
-    const int ex = (label & 1) ^ (swap ? ph : pv);
-    const int ez = ((label >> 1) & 1) ^ (swap ? pv : ph);
-    const int k = ex * 2 + ez;
-    return (k == 0) ? p00 : (k == 1) ? p01 : (k == 2) ? p10 : p11;
+    const int swap = ((r & 1) != 0) != (frame >= FRAME_S);
+    const int absent = (a_up ? 1 : 0) | (a_in ? 2 : 0) | (a_dn ? 4 : 0) | (a_out ? 8 : 0);
+    return qubit_coef(label, swap, absent, p00, p01, p10, p11, vi, hi, vo, ho);
   }
   // COPY: all present legs equal (absent legs are pinned to 0 and take no part)
-  int ref = -1;
-  bool ok = true;
-  if (!a_up) ref = vi;
-  if (!a_in) { if (ref < 0) ref = hi; else if (hi != ref) ok = false; }
-  if (!a_dn) { if (ref < 0) ref = vo; else if (vo != ref) ok = false; }
-  if (!a_out) { if (ref < 0) ref = ho; else if (ho != ref) ok = false; }
-  return ok ? 1.0f : 0.0f;
+  return copy_coef((a_up ? 1 : 0) | (a_in ? 2 : 0) | (a_dn ? 4 : 0) | (a_out ? 8 : 0), e);
 }
 
 // All 16 entries of the frame table (see site_entry).

@@ -365,6 +365,15 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       cd.mids = col.m0 | (col.m1 << 4) | (col.m2 << 8);
       cd.in_absent = col.in_absent;
       cd.out_absent = col.out_absent;
+      for (int i = 0; i < s.kp; ++i) {
+        int r, c, a_up, a_in, a_dn, a_out;
+        frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, t, i, r, c);
+        site_flags(s.frame, p.L, r, c, a_up, a_in, a_dn, a_out);
+        const int qubit = ((r + c) & 1) == 0;
+        const int swap = ((r & 1) != 0) != (s.frame >= FRAME_S);
+        cd.site[i] = (r - s.r0) | ((c - s.c0) << 4) | (qubit << 8) | (swap << 9) | (a_up << 10) | (a_in << 11) |
+                     (a_dn << 12) | (a_out << 13);
+      }
       p.columns.push_back(cd);
     }
   };

@@ -33,8 +33,12 @@ struct ColumnDesc {
   int32_t mids;        // their positions, 4 bits each
   int32_t in_absent, out_absent;
   int32_t pad[3];
+  // per position i: block-local row r - r0 in bits 0..3 and column c - c0 in bits 4..7, qubit flag bit 8,
+  // orientation swap bit 9, absent legs (up, in, down, out) bits 10..13
+  int32_t site[6];
+  int32_t pad2[10];
 };
-static_assert(sizeof(ColumnDesc) == 64, "ColumnDesc layout");
+static_assert(sizeof(ColumnDesc) == 128, "ColumnDesc layout");
 
 struct Plan {
   int d = 0, L = 0, kr = 0, kc = 0, chi = 0;
