@@ -101,11 +101,18 @@ int bbp_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* b
 /* Optional per-call timing of the kernels (filled when non-NULL; adds one event pair per launch and a
  * stream synchronisation at the end of the call). */
 typedef struct bbp_timing {
-  double update_ms;          /* summed duration of the block-update kernel launches (BP rounds) */
-  int32_t update_launches;
+  double update_ms;          /* summed duration of the block-sweep launches of the BP rounds */
+  int32_t update_launches;   /* one launch per sweep class per colour round */
   double bethe_ms;           /* closing sweeps of the Bethe estimate */
   double other_ms;           /* labels, init, convergence, decision */
   double update_flops;       /* algorithmic flops of the update launches actually executed */
+  /* The sweep-kernel instantiation with the largest summed duration in the BP rounds. Its class code is
+   * ((steps - 1) * 4 + top * 2 + bottom) * 2 + single: sweep length 1..6, side messages present at the
+   * top / bottom end of the columns, one position across the sweep. */
+  int32_t top_class;
+  int32_t top_launches;
+  double top_ms;
+  double top_flops;
 } bbp_timing;
 
 /* ---------------------------------------------------------------------------------------------------

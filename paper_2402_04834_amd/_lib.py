@@ -40,7 +40,15 @@ class bbp_timing(C.Structure):
     _fields_ = [
         ("update_ms", C.c_double), ("update_launches", C.c_int32), ("bethe_ms", C.c_double),
         ("other_ms", C.c_double), ("update_flops", C.c_double),
+        ("top_class", C.c_int32), ("top_launches", C.c_int32), ("top_ms", C.c_double), ("top_flops", C.c_double),
     ]
+
+
+def sweep_kernel_name(cls: int) -> str:
+    """Kernel instantiation of a sweep class code (see bbp_timing.top_class)."""
+    single, bot, top, kt = cls & 1, (cls >> 1) & 1, (cls >> 2) & 1, (cls >> 3) + 1
+    b = lambda v: "true" if v else "false"
+    return f"sweep_kernel<{kt}, {b(top)}, {b(bot)}, {b(single)}>"
 
 
 # exported symbol -> (restype, argtypes)

@@ -1,24 +1,20 @@
-// bbp.hip -- gfx950 kernels and C ABI of the blockBP surface-code decoder.
+// bbp.hip -- gfx950 kernels (other than the block sweeps) and the C ABI of the blockBP surface-code decoder.
 //
 // Data path for a batch of syndromes (one "job" = one syndrome x one coset, job = 4*syndrome + coset):
 //   labels_kernel     syndrome -> f_s (left/up check chains) -> coset labels f_s L on the grid (Alg. 1)
 //   init_kernel       uniform unit messages (remark 2), convergence flags cleared
-//   update_kernel     one block message update per workgroup (eq. of the BP update evaluated as in
-//                     Sec. III.D), normalisation (remark 3), damping (remark 7), distance term (remark 4)
+//   sweep_kernel      block message updates, one wavefront per (job, sweep), launched per sweep class
+//                     (sweep_kernel.hip, wave_sweep.hpp): Sec. III.D update, normalisation (remark 3),
+//                     damping (remark 7), distance term (remark 4)
 //   delta_kernel      convergence distance per job and early exit (Alg. 1 BP loop)
-//   update_kernel     (closing mode) W_v of every block for the Bethe estimate (Lemma 3.1)
+//   sweep_kernel      (closing mode) W_v of every block for the Bethe estimate (Lemma 3.1)
 //   finalize_kernel   ln Z = sum ln W_v - sum ln <m_uv, m_vu>, decision rule, correction f_s L*
 //
-// Block update. The boundary state of the sweep is a dense FP32 array psi[top cap][h_0..h_{kp-1}][bottom
-// cap] in LDS (<= 4096 entries for 6x6 blocks). A column is absorbed in kp+2 passes: the top side-message
-// site (cap pass), the kp tensors of the column as in-place 4x4 transforms on the pair (vertical bond,
-// crossing bond), and the bottom side-message site. The side messages enter in the open-leg reading: bond
-// j of a K-site message carries its first j legs up to the middle site and its last K-j legs after it, the
-// dense message sitting on the middle site. After every column the state is normalised and the norm is
-// accumulated as a log-scale. The plan proves (exact rank analysis) that no boundary state can exceed
-// bond chi for the options accepted here, so the compression to chi is the identity and is not executed.
+// The plan proves (exact rank analysis) that no boundary state can exceed bond chi for the options
+// accepted here, so the compression to chi is the identity and is not executed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,16 +28,14 @@
 #include "../../include/bbp.h"
 #include "geom.hpp"
 #include "plan.hpp"
-#include "sweep.hpp"
+#include "sweep_launch.hpp"
 
 using bbp::SweepDesc;
 
 namespace {
 
-constexpr int NT = 256;          // threads per update workgroup (4 waves)
-constexpr int SMAX = 4096;       // max dense boundary-state entries (6x6 blocks, caps of dimension 8)
-constexpr int BMAX = 2048;       // max pass-1 intermediate (top cap advanced, bottom cap not yet)
-constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
+using bbp::MSTRIDE;
+using bbp::SWEEP_WAVES;
 
 thread_local std::string g_err = "no error";
 
@@ -96,350 +90,11 @@ __global__ void init_kernel(float* __restrict__ msgs, const int32_t* __restrict_
   }
 }
 
-__device__ __forceinline__ float block_sum(float v, float* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  float t = 0.0f;
-  for (int w = 0; w < NT / 64; ++w) t += red[w];
-  return t;
-}
-
 __device__ __forceinline__ double wave_sum_d(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-  return __shfl(v, 0);
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
-// --------------------------------------------------------------------------------------------------
-// Block sweeps. Lane h of a wavefront holds the crossing-bond configuration h (position 0 in the most
-// significant of kp bits). The boundary state is a set of rows (top cap index n, bottom cap index s), one
-// float per lane, stored in LDS as rows of 64 floats (row = n * Ps + s); the four waves of a workgroup take
-// the rows round-robin. A qubit's 2x2 transform pairs lane h with lane h ^ bit: a cross-lane shuffle and two
-// multiply-adds with coefficients chosen per lane from the check bits above and below. Only the cap sites
-// mix rows (through LDS). The column structure is described in sweep.hpp.
-
-// phi[np][v] of a cap site of kind KIND, reading psi[n] = sc * base[n * stride].
-template <int KIND>
-__device__ __forceinline__ float capv(const float* __restrict__ m, int Pold, int lPold, int Pnew, int R2, int np,
-                                      int v, const float* base, int stride, float sc) {
-  if constexpr (KIND == bbp::CAP_NONE) {
-    return v == 0 ? sc * base[0] : 0.0f;
-  } else if constexpr (KIND == bbp::CAP_F_LT) {
-    return v == (np & 1) ? sc * base[(np >> 1) * stride] : 0.0f;
-  } else if constexpr (KIND == bbp::CAP_F_EQ) {
-    float acc = 0.0f;
-    for (int a = 0; a < Pold; ++a) acc = fmaf(m[(a * 2 + v) * R2 + np], base[a * stride], acc);
-    return sc * acc;
-  } else if constexpr (KIND == bbp::CAP_F_GT) {
-    return sc * base[(v * Pnew + np) * stride];
-  } else if constexpr (KIND == bbp::CAP_B_GT) {
-    return (v == (np >> lPold)) ? sc * base[(np & (Pold - 1)) * stride] : 0.0f;
-  } else if constexpr (KIND == bbp::CAP_B_EQ) {
-    float acc = 0.0f;
-    for (int b = 0; b < Pold; ++b) acc = fmaf(m[(np * 2 + v) * R2 + b], base[b * stride], acc);
-    return sc * acc;
-  } else {   // CAP_B_LT
-    return sc * base[(2 * np + v) * stride];
-  }
-}
-
-struct LaneCoef {
-  // site 0 (qubit): coefficients for (emitted leg v, own / partner input bit), scaled by the column scale;
-  // middle qubits: own / partner
-  float q00, q01, q10, q11;
-  float cm_own[3], cm_par[3];
-  int am[3];      // byte addresses of the partner lanes of the middle qubits (ds_bpermute)
-};
-
-constexpr int NW = NT / 64;
-
-// cross-lane read of `x` from the lane whose byte address is `addr` (= 4 * lane)
-__device__ __forceinline__ float lane_read(int addr, float x) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
-}
-
-// Kinds whose emitted leg is fixed by the new cap index (one of the two values of v is zero).
-template <int KIND>
-__device__ __forceinline__ constexpr bool single_v() {
-  return KIND == bbp::CAP_NONE || KIND == bbp::CAP_F_LT || KIND == bbp::CAP_B_GT;
-}
-template <int KIND>
-__device__ __forceinline__ int the_v(int np, int lPold) {
-  if constexpr (KIND == bbp::CAP_NONE) return 0;
-  else if constexpr (KIND == bbp::CAP_F_LT) return np & 1;
-  else return np >> lPold;
-}
-
-// pass 1 (A -> B): top cap of kind KIND, site 0 and the middle qubits, for this wave's rows
-template <int KIND>
-__device__ __forceinline__ void pass1_rows(const bbp::ColumnDesc& cd, const LaneCoef& lc, const float* A, float* B,
-                                           const float* mt, int h, int hr, int a0, int vchk, int Ptn, int Pso,
-                                           int lso, float sc, int wid) {
-  const bool q0 = cd.flags & 1;
-  const int lPold = __builtin_ctz(cd.top_Pold);
-  const int stride = Pso * 64;
-  const int nmid = cd.nmid;
-#pragma unroll 4
-  for (int row = wid; row < Ptn * Pso; row += NW) {
-    const int np = row >> lso, sb = row & (Pso - 1);
-    const float* base = A + sb * 64 + hr;
-    float out;
-    if (q0) {
-      if constexpr (single_v<KIND>()) {
-        const int v = the_v<KIND>(np, lPold);
-        const float f = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, v, base, stride, 1.0f);
-        const float g = lane_read(a0, f);
-        out = v ? (lc.q10 * f + lc.q11 * g) : (lc.q00 * f + lc.q01 * g);
-      } else {
-        const float f0 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 0, base, stride, 1.0f);
-        const float f1 = capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, 1, base, stride, 1.0f);
-        const float g0 = lane_read(a0, f0);
-        const float g1 = lane_read(a0, f1);
-        out = lc.q00 * f0 + lc.q01 * g0 + lc.q10 * f1 + lc.q11 * g1;
-      }
-    } else {
-      out = sc * capv<KIND>(mt, cd.top_Pold, lPold, cd.top_Pnew, cd.top_R2, np, vchk, base, stride, 1.0f);
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      if (j < nmid) {
-        const float par = lane_read(lc.am[j], out);
-        out = lc.cm_own[j] * out + lc.cm_par[j] * par;
-      }
-    }
-    B[(np * Pso + sb) * 64 + h] = out;
-  }
-}
-
-// pass 2 (B -> A): bottom cap of kind KIND and the last site, then the out-leg projections; returns the
-// wave-local sum of squares
-template <int KIND>
-__device__ __forceinline__ float pass2_rows(const bbp::ColumnDesc& cd, const float* B, float* A, const float* mb,
-                                            int h, int kp, int al, int vchk, float l00, float l01, float l10,
-                                            float l11, int Ptn, int Pso, int Psn, int lsn, int wid) {
-  const bool ql = cd.flags & 4;
-  const int lPold = __builtin_ctz(cd.bot_Pold);
-  float ss = 0.0f;
-#pragma unroll 4
-  for (int row = wid; row < Ptn * Psn; row += NW) {
-    const int n = row >> lsn, sp = row & (Psn - 1);
-    const float* base = B + n * Pso * 64 + h;
-    float out;
-    if (ql) {
-      if constexpr (single_v<KIND>()) {
-        const int v = the_v<KIND>(sp, lPold);
-        const float f = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, v, base, 64, 1.0f);
-        const float g = lane_read(al, f);
-        out = v ? (l10 * f + l11 * g) : (l00 * f + l01 * g);
-      } else {
-        const float f0 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 0, base, 64, 1.0f);
-        const float f1 = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, 1, base, 64, 1.0f);
-        const float g0 = lane_read(al, f0);
-        const float g1 = lane_read(al, f1);
-        out = l00 * f0 + l01 * g0 + l10 * f1 + l11 * g1;
-      }
-    } else {
-      out = capv<KIND>(mb, cd.bot_Pold, lPold, cd.bot_Pnew, cd.bot_R2, sp, vchk, base, 64, 1.0f);
-    }
-    if (cd.out_absent) {
-      for (int b = 0; b < kp; ++b)
-        if (cd.out_absent & (1 << b)) {
-          const float o2 = __shfl_xor(out, 1 << b);
-          out = (h & (1 << b)) ? 0.0f : out + o2;
-        }
-    }
-    A[(n * Psn + sp) * 64 + h] = out;
-    ss = fmaf(out, out, ss);
-  }
-  return ss;
-}
-
-// mode 0: BP update of message s.msg_out; mode 1: closing sweep W_v of block s.block.
-__global__ __launch_bounds__(NT) void update_kernel(const SweepDesc* __restrict__ sweeps,
-                                                    const bbp::ColumnDesc* __restrict__ cols, int d,
-                                                    const uint8_t* __restrict__ labels, float* __restrict__ msgs,
-                                                    int M, double* __restrict__ terms,
-                                                    const int32_t* __restrict__ conv, float p0, float p1, float p2,
-                                                    float p3, float eta, int mode, double* __restrict__ lnW,
-                                                    int nblocks) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform within the wave
-  const int L = 2 * d - 1;
-
-  __shared__ float A[SMAX];
-  __shared__ float B[BMAX];
-  __shared__ float T[36 * 16];
-  __shared__ float mt[MSTRIDE], mb[MSTRIDE];
-  __shared__ float red[NW];
-
-  const int64_t job = blockIdx.x;
-  if (mode == 0 && conv[job]) return;
-  const SweepDesc s = sweeps[blockIdx.y];
-  const int kt = s.kt, kp = s.kp, H = 1 << kp;
-
-  const uint8_t* lab = labels + job * L * L;
-  for (int q = tid; q < kt * kp * 16; q += NT) {
-    int r, c;
-    const int site = q >> 4;
-    bbp::frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, site / kp, site % kp, r, c);
-    T[q] = bbp::site_entry(s.frame, L, r, c, lab[r * L + c], p0, p1, p2, p3, q & 15);
-  }
-  const float* mbase = msgs + job * M * MSTRIDE;
-  const bool has_top = s.msg_top >= 0, has_bot = s.msg_bot >= 0;
-  if (wid == 0) {
-    mt[lane] = has_top ? mbase[s.msg_top * MSTRIDE + lane] : 0.0f;
-    mb[lane] = has_bot ? mbase[s.msg_bot * MSTRIDE + lane] : 0.0f;
-    A[lane] = (s.msg_init >= 0) ? mbase[s.msg_init * MSTRIDE + lane] : (lane == 0 ? 1.0f : 0.0f);
-  }
-  __syncthreads();
-
-  const int h = lane;
-  double logscale = 0.0;
-  float scale = 1.0f;
-  int Ps = 1;
-  for (int t = 0; t < kt; ++t) {
-    const bbp::ColumnDesc cd = cols[s.col_off + t];
-    const float* Tt = &T[t * kp * 16];
-    // frame-table entry T(vi, hi, vo, ho) of the site at position i of this column
-    auto coef = [&](int i, int vi, int hi, int vo, int ho) { return Tt[i * 16 + vi * 8 + hi * 4 + vo * 2 + ho]; };
-    const int Ptn = cd.top_Pnew, Psn = cd.bot_Pnew, Pso = Ps;
-    const int lso = __builtin_ctz(Pso), lsn = __builtin_ctz(Psn);
-    const float sc = scale;
-    const int hr = h & ~cd.in_absent;      // checks entering from outside the grid: free variable
-    if (cd.flags & 16) {
-      // ---- one position (kp == 1): generic path --------------------------------------------------------
-      bbp::CapInfo top{cd.top_kind, cd.top_Pold, cd.top_Pnew, cd.top_R2};
-      bbp::CapInfo bot{cd.bot_kind, cd.bot_Pold, cd.bot_Pnew, cd.bot_R2};
-      for (int row = wid; row < Ptn * Pso; row += NW) {
-        const int np = row >> lso, sb = row & (Pso - 1);
-        auto get = [&](int n) { return sc * A[(n * Pso + sb) * 64 + hr]; };
-        for (int vt = 0; vt < 2; ++vt)
-          B[((np * 2 + vt) * Pso + sb) * 64 + h] = bbp::cap_phi<float>(top, mt, np, vt, get);
-      }
-      __syncthreads();
-      const int hol = h & 1;
-      float ss = 0.0f;
-      for (int row = wid; row < Ptn * Psn; row += NW) {
-        const int n = row >> lsn, sp = row & (Psn - 1);
-        float out = 0.0f;
-        if (cd.flags & 4) {
-          for (int vt = 0; vt < 2; ++vt)
-            for (int vb = 0; vb < 2; ++vb) {
-              auto get = [&](int sb) { return B[((n * 2 + vt) * Pso + sb) * 64 + h]; };
-              const float f = bbp::cap_phi<float>(bot, mb, sp, vb, get);
-              const float g = __shfl_xor(f, 1);
-              out += coef(0, vt, hol, vb, hol) * f + coef(0, vt, 1 - hol, vb, hol) * g;
-            }
-        } else {
-          const int vt = (cd.flags & 2) ? 0 : hol;
-          const int vb = (cd.flags & 8) ? 0 : hol;
-          auto get = [&](int sb) { return B[((n * 2 + vt) * Pso + sb) * 64 + h]; };
-          out = bbp::cap_phi<float>(bot, mb, sp, vb, get);
-        }
-        if (cd.out_absent & 1) {
-          const float o2 = __shfl_xor(out, 1);
-          out = hol ? 0.0f : out + o2;
-        }
-        A[(n * Psn + sp) * 64 + h] = out;
-        ss = fmaf(out, out, ss);
-      }
-      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-      if (lane == 0) red[wid] = ss;
-    } else {
-      // ---- pass 1 -----------------------------------------------------------------------------------
-      LaneCoef lc;
-      const int b0 = bbp::pos_bit(kp, 0);
-      const int ho0 = (h & b0) ? 1 : 0;
-      const int vo0 = (h & bbp::pos_bit(kp, 1)) ? 1 : 0;
-      lc.q00 = sc * coef(0, 0, ho0, vo0, ho0);
-      lc.q01 = sc * coef(0, 0, 1 - ho0, vo0, ho0);
-      lc.q10 = sc * coef(0, 1, ho0, vo0, ho0);
-      lc.q11 = sc * coef(0, 1, 1 - ho0, vo0, ho0);
-      const int a0 = (h ^ b0) << 2;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        lc.cm_own[j] = 0.0f;
-        lc.cm_par[j] = 0.0f;
-        lc.am[j] = h << 2;
-        if (j < cd.nmid) {
-          const int i = (cd.mids >> (4 * j)) & 15;
-          const int bi = bbp::pos_bit(kp, i);
-          const int vi = (h & bbp::pos_bit(kp, i - 1)) ? 1 : 0;
-          const int vo = (h & bbp::pos_bit(kp, i + 1)) ? 1 : 0;
-          const int ho = (h & bi) ? 1 : 0;
-          lc.cm_own[j] = coef(i, vi, ho, vo, ho);
-          lc.cm_par[j] = coef(i, vi, 1 - ho, vo, ho);
-          lc.am[j] = (h ^ bi) << 2;
-        }
-      }
-      const int vchk0 = (cd.flags & 2) ? 0 : ho0;
-      switch (cd.top_kind) {
-        case bbp::CAP_NONE: pass1_rows<bbp::CAP_NONE>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_LT: pass1_rows<bbp::CAP_F_LT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_EQ: pass1_rows<bbp::CAP_F_EQ>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_F_GT: pass1_rows<bbp::CAP_F_GT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_B_GT: pass1_rows<bbp::CAP_B_GT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        case bbp::CAP_B_EQ: pass1_rows<bbp::CAP_B_EQ>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-        default:            pass1_rows<bbp::CAP_B_LT>(cd, lc, A, B, mt, h, hr, a0, vchk0, Ptn, Pso, lso, sc, wid); break;
-      }
-      __syncthreads();
-      // ---- pass 2 -----------------------------------------------------------------------------------
-      const int bl = bbp::pos_bit(kp, kp - 1);
-      const int hol = (h & bl) ? 1 : 0;
-      const int vil = (h & bbp::pos_bit(kp, kp - 2)) ? 1 : 0;
-      const float l00 = coef(kp - 1, vil, hol, 0, hol), l01 = coef(kp - 1, vil, 1 - hol, 0, hol);
-      const float l10 = coef(kp - 1, vil, hol, 1, hol), l11 = coef(kp - 1, vil, 1 - hol, 1, hol);
-      const int vchkl = (cd.flags & 8) ? 0 : hol;
-      const int al = (h ^ bl) << 2;
-      float ss;
-      switch (cd.bot_kind) {
-        case bbp::CAP_NONE: ss = pass2_rows<bbp::CAP_NONE>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_LT: ss = pass2_rows<bbp::CAP_F_LT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_EQ: ss = pass2_rows<bbp::CAP_F_EQ>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_F_GT: ss = pass2_rows<bbp::CAP_F_GT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_B_GT: ss = pass2_rows<bbp::CAP_B_GT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        case bbp::CAP_B_EQ: ss = pass2_rows<bbp::CAP_B_EQ>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-        default:            ss = pass2_rows<bbp::CAP_B_LT>(cd, B, A, mb, h, kp, al, vchkl, l00, l01, l10, l11, Ptn, Pso, Psn, lsn, wid); break;
-      }
-      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-      if (lane == 0) red[wid] = ss;
-    }
-    __syncthreads();
-    float tot = 0.0f;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) tot += red[w];
-    const float nrm = sqrtf(tot);
-    scale = (nrm > 0.0f) ? 1.0f / nrm : 0.0f;
-    logscale += (double)logf(nrm);
-    Ps = Psn;
-  }
-  if (wid == 0) {
-    const float fin = (lane < H) ? A[lane] * scale : 0.0f;
-    if (mode == 1) {
-      // closing contraction with the message from the receiver side (or the grid edge)
-      double w = 0.0;
-      if (s.msg_close >= 0) w = (double)mbase[s.msg_close * MSTRIDE + lane] * (double)fin;
-      else if (lane == 0) w = fin;
-      w = wave_sum_d(w);
-      if (lane == 0) lnW[job * nblocks + s.block] = (w > 0.0) ? logscale + log(w) : NAN;
-    } else {
-      // normalised new message, damping against the old one, distance term
-      float* mo = msgs + job * M * MSTRIDE + s.msg_out * MSTRIDE;
-      const float old = (lane < H) ? mo[lane] : 0.0f;
-      const double n2 = wave_sum_d((double)fin * fin);
-      const float inv = (float)(1.0 / sqrt(n2));
-      const float dm = (1.0f - eta) * (fin * inv) + eta * old;
-      const double dd = wave_sum_d((double)dm * dm);
-      const double od = wave_sum_d((double)old * old);
-      const double c = wave_sum_d((double)dm * old);
-      const float fm = dm * (float)(1.0 / sqrt(dd));
-      if (lane < H) mo[lane] = fm;
-      if (lane == 0) terms[job * M + s.msg_out] = 2.0 - 2.0 * (c * c) / (dd * od);
-    }
-  }
-}
 
 __global__ void delta_kernel(const double* __restrict__ terms, int M, int64_t jobs, int32_t* __restrict__ conv,
                              int32_t* __restrict__ iters, double* __restrict__ delta, double delta0, int fixed) {
@@ -542,11 +197,52 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 }
 
 // --------------------------------------------------------------------------------------------------
+unsigned sweep_groups(int64_t jobs) { return (unsigned)((jobs + SWEEP_WAVES - 1) / SWEEP_WAVES); }
+
+// A run of sweeps of one class inside a device sweep list: one kernel launch.
+struct ClassRun {
+  int cls, first, count;
+  double flops;   // algorithmic flops of these sweeps for one job
+};
+
+// Sort a sweep list by class (the sweeps of one list are independent) and cut it into launches.
+std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
+  std::stable_sort(v.begin(), v.end(),
+                   [](const SweepDesc& a, const SweepDesc& b) { return bbp::sweep_class(a) < bbp::sweep_class(b); });
+  std::vector<ClassRun> runs;
+  for (int i = 0; i < (int)v.size(); ++i) {
+    const int c = bbp::sweep_class(v[i]);
+    if (runs.empty() || runs.back().cls != c) runs.push_back({c, i, 0, 0.0});
+    runs.back().count += 1;
+    runs.back().flops += v[i].flops;
+  }
+  return runs;
+}
+
+}  // namespace
+
+hipError_t bbp::launch_sweeps(int cls, unsigned count, hipStream_t st, const SweepArgs& a) {
+  const bool single = cls & 1, bot = (cls >> 1) & 1, top = (cls >> 2) & 1;
+  const int kt = (cls >> 3) + 1;
+  const dim3 grid(sweep_groups(a.jobs), count);
+  switch (kt) {
+    case 1: return launch_sweeps_k1(top, bot, single, grid, st, a);
+    case 2: return launch_sweeps_k2(top, bot, single, grid, st, a);
+    case 3: return launch_sweeps_k3(top, bot, single, grid, st, a);
+    case 4: return launch_sweeps_k4(top, bot, single, grid, st, a);
+    case 5: return launch_sweeps_k5(top, bot, single, grid, st, a);
+    case 6: return launch_sweeps_k6(top, bot, single, grid, st, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+namespace {
+
 struct DevPlan {
   bbp::Plan plan;
-  bbp::ColumnDesc* cols = nullptr;
   SweepDesc* round[2] = {nullptr, nullptr};
   SweepDesc* bethe = nullptr;
+  std::vector<ClassRun> runs[3];   // rounds 0, 1 and the closing sweeps
   int32_t* edge_len = nullptr;
   int32_t* pairs = nullptr;
   int device = -1;
@@ -589,15 +285,13 @@ int device_plan(int d, const bbp_opts* o, DevPlan** out) {
   dp->plan = host_plan(d, o);
   dp->device = dev;
   const bbp::Plan& p = dp->plan;
-  for (int c = 0; c < 2; ++c) {
-    HIP_TRY(hipMalloc(&dp->round[c], sizeof(SweepDesc) * std::max<size_t>(1, p.round[c].size())));
-    if (!p.round[c].empty())
-      HIP_TRY(hipMemcpy(dp->round[c], p.round[c].data(), sizeof(SweepDesc) * p.round[c].size(), hipMemcpyHostToDevice));
+  for (int c = 0; c < 3; ++c) {
+    std::vector<SweepDesc> v = (c < 2) ? p.round[c] : p.bethe;
+    dp->runs[c] = by_class(v);
+    SweepDesc*& dst = (c < 2) ? dp->round[c] : dp->bethe;
+    HIP_TRY(hipMalloc(&dst, sizeof(SweepDesc) * std::max<size_t>(1, v.size())));
+    if (!v.empty()) HIP_TRY(hipMemcpy(dst, v.data(), sizeof(SweepDesc) * v.size(), hipMemcpyHostToDevice));
   }
-  HIP_TRY(hipMalloc(&dp->cols, sizeof(bbp::ColumnDesc) * p.columns.size()));
-  HIP_TRY(hipMemcpy(dp->cols, p.columns.data(), sizeof(bbp::ColumnDesc) * p.columns.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc(&dp->bethe, sizeof(SweepDesc) * p.bethe.size()));
-  HIP_TRY(hipMemcpy(dp->bethe, p.bethe.data(), sizeof(SweepDesc) * p.bethe.size(), hipMemcpyHostToDevice));
   std::vector<int32_t> el(p.edge_len.begin(), p.edge_len.end());
   if (el.empty()) el.push_back(0);
   HIP_TRY(hipMalloc(&dp->edge_len, sizeof(int32_t) * el.size()));
@@ -787,7 +481,6 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
     return BBP_OK;
   };
   std::vector<int> kinds;   // kind of the interval ending at each mark: 0 other, 1 update, 2 bethe
-  std::vector<double> iv_flops;
 
   if ((rc = mark())) return rc;
   labels_kernel<<<dim3((unsigned)batch), dim3(256), 0, st>>>(syndromes_dev, d, batch, labels);
@@ -795,33 +488,44 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
   HIP_TRY(hipGetLastError());
   if ((rc = mark())) return rc;
   kinds.push_back(0);
-  iv_flops.push_back(0.0);
+  bbp::SweepArgs sa;
+  sa.d = d;
+  sa.labels = labels;
+  sa.msgs = msgs;
+  sa.M = P.M;
+  sa.terms = terms;
+  sa.conv = conv;
+  sa.p0 = pi0;
+  sa.p1 = sa.p2 = sa.p3 = pe;
+  sa.eta = (float)opts->damping;
+  sa.lnW = lnw;
+  sa.nblocks = P.nblocks;
+  sa.jobs = jobs;
+  std::vector<std::pair<int, const ClassRun*>> upd;   // (iteration, run) of each update interval
   for (int it = 0; it < opts->max_iter; ++it) {
     for (int c = 0; c < 2; ++c) {
-      if (P.round[c].empty()) continue;
-      update_kernel<<<dim3((unsigned)jobs, (unsigned)P.round[c].size()), dim3(NT), 0, st>>>(
-          dp->round[c], dp->cols, d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 0, lnw,
-          P.nblocks);
-      HIP_TRY(hipGetLastError());
-      if ((rc = mark())) return rc;
-      kinds.push_back(1);
-      double f = 0.0;
-      for (auto& s : P.round[c]) f += s.flops;
-      iv_flops.push_back(f);
+      for (const ClassRun& r : dp->runs[c]) {
+        sa.sweeps = dp->round[c] + r.first;
+        sa.mode = 0;
+        HIP_TRY(bbp::launch_sweeps(r.cls, (unsigned)r.count, st, sa));
+        if ((rc = mark())) return rc;
+        kinds.push_back(1);
+        upd.emplace_back(it, &r);
+      }
     }
     delta_kernel<<<dim3((unsigned)((jobs + 255) / 256)), dim3(256), 0, st>>>(terms, P.M, jobs, conv, iters, delta,
                                                                             opts->delta0, opts->fixed_iters);
     HIP_TRY(hipGetLastError());
     if ((rc = mark())) return rc;
     kinds.push_back(0);
-    iv_flops.push_back(0.0);
   }
-  update_kernel<<<dim3((unsigned)jobs, (unsigned)P.bethe.size()), dim3(NT), 0, st>>>(
-      dp->bethe, dp->cols, d, labels, msgs, P.M, terms, conv, pi0, pe, pe, pe, (float)opts->damping, 1, lnw, P.nblocks);
-  HIP_TRY(hipGetLastError());
+  for (const ClassRun& r : dp->runs[2]) {
+    sa.sweeps = dp->bethe + r.first;
+    sa.mode = 1;
+    HIP_TRY(bbp::launch_sweeps(r.cls, (unsigned)r.count, st, sa));
+  }
   if ((rc = mark())) return rc;
   kinds.push_back(2);
-  iv_flops.push_back(0.0);
   finalize_kernel<<<dim3((unsigned)batch), dim3(256), 0, st>>>(
       lnw, P.nblocks, msgs, P.M, dp->pairs, (int)(P.pair_ids.size() / 2), labels, d, delta, iters, opts->delta1,
       opts->rule, loglik_dev, delta_dev, iters_dev, coset_dev, correction_dev);
@@ -831,25 +535,48 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
                            hipMemcpyDeviceToDevice, st));
   if ((rc = mark())) return rc;
   kinds.push_back(0);
-  iv_flops.push_back(0.0);
 
   if (timing) {
     HIP_TRY(hipStreamSynchronize(st));
     std::memset(timing, 0, sizeof(*timing));
-    // flops actually executed: per-job active iterations
+    // flops actually executed: a job runs the updates of iteration `it` iff it ran more than `it` iterations
     std::vector<int32_t> it_host((size_t)jobs);
     HIP_TRY(hipMemcpy(it_host.data(), iters, sizeof(int32_t) * jobs, hipMemcpyDeviceToHost));
-    double job_iters = 0.0;
-    for (auto v : it_host) job_iters += v;
+    std::vector<double> active((size_t)opts->max_iter + 1, 0.0);
+    for (auto v : it_host) active[std::min<int32_t>(std::max<int32_t>(v, 0), opts->max_iter)] += 1.0;
+    for (int k = opts->max_iter - 1; k >= 0; --k) active[k] += active[k + 1];   // jobs with iters >= k
+    std::map<int, std::tuple<double, int, double>> per_class;   // class -> (ms, launches, flops)
+    size_t u = 0;
     for (size_t k = 1; k < evs.size(); ++k) {
       float ms = 0.0f;
       HIP_TRY(hipEventElapsedTime(&ms, evs[k - 1], evs[k]));
       const int kind = kinds[k - 1];
-      if (kind == 1) { timing->update_ms += ms; timing->update_launches += 1; }
-      else if (kind == 2) timing->bethe_ms += ms;
-      else timing->other_ms += ms;
+      if (kind == 1) {
+        const int it = upd[u].first;
+        const ClassRun* r = upd[u].second;
+        ++u;
+        const double fl = active[it + 1] * r->flops;
+        timing->update_ms += ms;
+        timing->update_launches += 1;
+        timing->update_flops += fl;
+        auto& pc = per_class[r->cls];
+        std::get<0>(pc) += ms;
+        std::get<1>(pc) += 1;
+        std::get<2>(pc) += fl;
+      } else if (kind == 2) {
+        timing->bethe_ms += ms;
+      } else {
+        timing->other_ms += ms;
+      }
     }
-    timing->update_flops = job_iters * P.flops_iter;
+    timing->top_class = -1;
+    for (auto& kv : per_class)
+      if (std::get<0>(kv.second) > timing->top_ms) {
+        timing->top_class = kv.first;
+        timing->top_ms = std::get<0>(kv.second);
+        timing->top_launches = std::get<1>(kv.second);
+        timing->top_flops = std::get<2>(kv.second);
+      }
     for (auto e : evs) (void)hipEventDestroy(e);
   }
   return BBP_OK;

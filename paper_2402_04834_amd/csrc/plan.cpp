@@ -349,36 +349,6 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       p.bethe.push_back(s);
       p.flops_bethe += s.flops;
     }
-  // per-column descriptors of every sweep
-  auto add_columns = [&](SweepDesc& s) {
-    s.col_off = (int32_t)p.columns.size();
-    for (int t = 0; t < s.kt; ++t) {
-      Column col;
-      make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, s.kt, s.kp, p.L, t, s.msg_top >= 0, s.msg_bot >= 0);
-      ColumnDesc cd;
-      std::memset(&cd, 0, sizeof(cd));
-      cd.top_kind = col.top.kind; cd.top_Pold = col.top.Pold; cd.top_Pnew = col.top.Pnew; cd.top_R2 = col.top.R2;
-      cd.bot_kind = col.bot.kind; cd.bot_Pold = col.bot.Pold; cd.bot_Pnew = col.bot.Pnew; cd.bot_R2 = col.bot.R2;
-      cd.flags = (col.q0 ? 1 : 0) | (col.up_absent0 ? 2 : 0) | (col.qlast ? 4 : 0) | (col.dn_absent_last ? 8 : 0) |
-                 (col.single ? 16 : 0);
-      cd.nmid = col.nmid;
-      cd.mids = col.m0 | (col.m1 << 4) | (col.m2 << 8);
-      cd.in_absent = col.in_absent;
-      cd.out_absent = col.out_absent;
-      for (int i = 0; i < s.kp; ++i) {
-        int r, c, a_up, a_in, a_dn, a_out;
-        frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, t, i, r, c);
-        site_flags(s.frame, p.L, r, c, a_up, a_in, a_dn, a_out);
-        const int qubit = ((r + c) & 1) == 0;
-        const int swap = ((r & 1) != 0) != (s.frame >= FRAME_S);
-        cd.site[i] = (r - s.r0) | ((c - s.c0) << 4) | (qubit << 8) | (swap << 9) | (a_up << 10) | (a_in << 11) |
-                     (a_dn << 12) | (a_out << 13);
-      }
-      p.columns.push_back(cd);
-    }
-  };
-  for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) add_columns(s);
-  for (auto& s : p.bethe) add_columns(s);
   for (int e = 0; e < p.M; ++e)
     if (p.edge_src[e] < p.edge_dst[e]) {
       p.pair_ids.push_back(e);

@@ -18,27 +18,9 @@ struct SweepDesc {
   int32_t msg_close;            // Bethe: message from the receiver side, -1 if none
   int32_t block;                // block index (row-major)
   float flops;                  // algorithmic flops of this sweep
-  int32_t col_off;              // index of this sweep's first column descriptor
-  int32_t pad;
+  int32_t pad[2];
 };
 static_assert(sizeof(SweepDesc) == 64, "SweepDesc layout");
-
-// Per-column constants of a sweep (the uniform part of sweep.hpp's Column), precomputed on the host.
-struct ColumnDesc {
-  int32_t top_kind, top_Pold, top_Pnew, top_R2;
-  int32_t bot_kind, bot_Pold, bot_Pnew, bot_R2;
-  int32_t flags;       // bit 0: site 0 qubit; 1: site 0 up-leg absent; 2: last site qubit;
-                       // 3: last site down-leg absent; 4: single position (kp == 1)
-  int32_t nmid;        // middle qubits
-  int32_t mids;        // their positions, 4 bits each
-  int32_t in_absent, out_absent;
-  int32_t pad[3];
-  // per position i: block-local row r - r0 in bits 0..3 and column c - c0 in bits 4..7, qubit flag bit 8,
-  // orientation swap bit 9, absent legs (up, in, down, out) bits 10..13
-  int32_t site[6];
-  int32_t pad2[10];
-};
-static_assert(sizeof(ColumnDesc) == 128, "ColumnDesc layout");
 
 struct Plan {
   int d = 0, L = 0, kr = 0, kc = 0, chi = 0;
@@ -48,7 +30,6 @@ struct Plan {
   std::vector<SweepDesc> round[2];                            // colour (I+J)%2 == 0 sends first
   std::vector<SweepDesc> bethe;                               // one closing sweep per block
   std::vector<int32_t> pair_ids;                              // undirected edges: (u->v, v->u) ids
-  std::vector<ColumnDesc> columns;                            // all sweeps' column descriptors
   int max_msg_len = 0;
   bool exact = false;        // no boundary state can exceed chi: truncation is the identity
   int max_rank = 0;          // largest generic Schmidt rank found across cuts that could bind

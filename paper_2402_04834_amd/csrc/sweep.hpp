@@ -1,5 +1,6 @@
-// sweep.hpp -- one column step of an in-block sweep, shared by the GPU kernel and the host validation
-// hook so that both execute the same index arithmetic.
+// sweep.hpp -- one column step of an in-block sweep in the check-pass-through formulation, evaluated
+// sequentially on the host (float64) by the validation hook bbp_reference_update_host. The GPU kernels
+// (wave_sweep.hpp) execute the same formulation with one wavefront per sweep.
 //
 // Structure used. Every bond of the coset network joins a qubit and a check, and a check is a COPY tensor,
 // so a bond always carries the value of the check it touches. In a column of the sweep the sites alternate

@@ -1,0 +1,137 @@
+// sweep_kernel.hip -- block-sweep kernels for sweeps of BBP_KT steps (this file is compiled once per
+// length, BBP_KT = 1..6). One wavefront runs one (job, sweep); the sweep itself is in wave_sweep.hpp.
+//   mode 0: BP update of message s.msg_out (Sec. III.D): the new message is normalised (remark 3), damped
+//           against the old one (remark 7) and the distance term of the convergence test stored (remark 4);
+//   mode 1: closing sweep of block s.block, W_v of the Bethe estimate (Lemma 3.1).
+// Grid: x = groups of SWEEP_WAVES jobs, y = sweep of the launch's list.
+#include <hip/hip_runtime.h>
+
+#include "sweep_launch.hpp"
+#include "wave_sweep.hpp"
+
+#ifndef BBP_KT
+#error "compile with -DBBP_KT=<sweep length 1..6>"
+#endif
+
+namespace bbp {
+namespace {
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// entry index of a K-leg dense message with its legs in reverse order
+__device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
+
+template <int KT, bool TOP, bool BOT, bool SINGLE>
+__global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void sweep_kernel(SweepArgs a) {
+  const int lane = (int)__lane_id();
+  const int64_t job = (int64_t)blockIdx.x * SWEEP_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (job >= a.jobs) return;
+  if (a.mode == 0 && a.conv[job]) return;
+  const SweepDesc s = a.sweeps[blockIdx.y];
+  const int L = 2 * a.d - 1, kp = s.kp, H = 1 << kp;
+  const bool valid = lane < H;
+
+  wave::Ctx c;
+  c.h = lane;
+  c.kp = kp;
+  c.kt = KT;
+  c.frame = s.frame;
+  c.r0 = s.r0;
+  c.c0 = s.c0;
+  c.kr = s.kr;
+  c.kc = s.kc;
+  c.L = L;
+  c.p0 = a.p0;
+  c.p1 = a.p1;
+  c.p2 = a.p2;
+  c.p3 = a.p3;
+  c.logscale = 0.0;
+  const uint8_t* lab = a.labels + job * L * L;
+  int lb = 0;
+  if (lane < KT * kp) {
+    const int t = lane / kp, i = lane - t * kp;
+    int r, cc;
+    frame_site(s.frame, s.r0, s.c0, s.kr, s.kc, t, i, r, cc);
+    lb = lab[r * L + cc];
+  }
+  c.labv = __int_as_float(lb);
+  // side messages: a sweep toward W or N walks them from their last leg, so read them leg-reversed
+  const bool fwd = (s.frame == FRAME_E || s.frame == FRAME_S);
+  const float* mbase = a.msgs + job * a.M * MSTRIDE;
+  const int sl = fwd ? lane : reverse_legs(lane, KT);
+  const bool in_msg = lane < (1 << KT);
+  c.mtv = (TOP && in_msg) ? mbase[s.msg_top * MSTRIDE + sl] : 0.0f;
+  c.mbv = (BOT && in_msg) ? mbase[s.msg_bot * MSTRIDE + sl] : 0.0f;
+
+  // message index of this lane's configuration: position i is lane bit pbit(i), message bit kp-1-i
+  int mi = 0;
+  for (int i = 0; i < kp; ++i)
+    if (lane & wave::pbit(kp, i)) mi |= 1 << (kp - 1 - i);
+
+  float x0;
+  if (s.msg_init >= 0) {
+    x0 = valid ? mbase[s.msg_init * MSTRIDE + mi] : 0.0f;
+  } else {
+    // the sweep starts at the grid edge: checks whose in-leg leaves the grid are free variables
+    int ia = 0;
+    for (int i = 0; i < kp; ++i) {
+      const wave::SiteInfo si = wave::site_info(c, 0, i);
+      if (!si.qubit && (si.absent & 2)) ia |= wave::pbit(kp, i);
+    }
+    x0 = ((lane & ~ia) == 0) ? 1.0f : 0.0f;
+  }
+
+  float fin = wave::sweep<KT, TOP, BOT, SINGLE>(x0, c);
+  fin = valid ? fin : 0.0f;
+
+  if (a.mode == 1) {
+    // closing contraction with the message from the receiver side (or the grid edge)
+    double w = 0.0;
+    if (s.msg_close >= 0) w = valid ? (double)mbase[s.msg_close * MSTRIDE + mi] * (double)fin : 0.0;
+    else if (lane == 0) w = fin;
+    w = wave_sum_d(w);
+    if (lane == 0) a.lnW[job * a.nblocks + s.block] = (w > 0.0) ? c.logscale + log(w) : NAN;
+  } else {
+    // normalised new message, damping against the old one, distance term
+    float* mo = a.msgs + job * a.M * MSTRIDE + s.msg_out * MSTRIDE;
+    const float old = valid ? mo[mi] : 0.0f;
+    const double n2 = wave_sum_d((double)fin * fin);
+    const float inv = (float)(1.0 / sqrt(n2));
+    const float dm = (1.0f - a.eta) * (fin * inv) + a.eta * old;
+    const double dd = wave_sum_d((double)dm * dm);
+    const double od = wave_sum_d((double)old * old);
+    const double cr = wave_sum_d((double)dm * old);
+    const float fm = dm * (float)(1.0 / sqrt(dd));
+    if (valid) mo[mi] = fm;
+    if (lane == 0) a.terms[job * a.M + s.msg_out] = 2.0 - 2.0 * (cr * cr) / (dd * od);
+  }
+}
+
+}  // namespace
+
+#define BBP_CAT2(a, b) a##b
+#define BBP_CAT(a, b) BBP_CAT2(a, b)
+
+namespace {
+template <bool SINGLE>
+void launch_one(bool top, bool bot, dim3 grid, hipStream_t st, const SweepArgs& a) {
+  const dim3 block(SWEEP_WAVES * 64);
+  if (top && bot) sweep_kernel<BBP_KT, true, true, SINGLE><<<grid, block, 0, st>>>(a);
+  else if (top) sweep_kernel<BBP_KT, true, false, SINGLE><<<grid, block, 0, st>>>(a);
+  else if (bot) sweep_kernel<BBP_KT, false, true, SINGLE><<<grid, block, 0, st>>>(a);
+  else sweep_kernel<BBP_KT, false, false, SINGLE><<<grid, block, 0, st>>>(a);
+}
+}  // namespace
+
+hipError_t BBP_CAT(launch_sweeps_k, BBP_KT)(bool top, bool bot, bool single, dim3 grid, hipStream_t st,
+                                            const SweepArgs& a) {
+  if (single) launch_one<true>(top, bot, grid, st, a);
+  else launch_one<false>(top, bot, grid, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace bbp
