@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (a known-size reference dispatch "
+                         "for hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this decoder runs on one GPU; only --gpus 1 is supported", file=sys.stderr)
@@ -78,6 +81,14 @@ def main():
 
     import paper_2402_04834_amd as bbp
     from paper_2402_04834_amd import _lib, workload
+
+    if a.calibrate_copy > 0:
+        n = a.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     d, p, block, chi, max_iter = 17, 0.10, 6, 32, 20
     _, syn = workload.make_batch(d, p, a.batch, workload="d17")

@@ -107,8 +107,8 @@ typedef struct bbp_timing {
   double other_ms;           /* labels, init, convergence, decision */
   double update_flops;       /* algorithmic flops of the update launches actually executed */
   /* The sweep-kernel instantiation with the largest summed duration in the BP rounds. Its class code is
-   * ((steps - 1) * 4 + top * 2 + bottom) * 2 + single: sweep length 1..6, side messages present at the
-   * top / bottom end of the columns, one position across the sweep. */
+   * (((steps - 1) * 4 + top * 2 + bottom) * 2 + single) * 2 + q00: sweep length 1..6, side messages
+   * present at the top / bottom end of the columns, one position across the sweep, first site a qubit. */
   int32_t top_class;
   int32_t top_launches;
   double top_ms;

@@ -222,16 +222,15 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
 }  // namespace
 
 hipError_t bbp::launch_sweeps(int cls, unsigned count, hipStream_t st, const SweepArgs& a) {
-  const bool single = cls & 1, bot = (cls >> 1) & 1, top = (cls >> 2) & 1;
-  const int kt = (cls >> 3) + 1;
+  const int variant = cls & 15, kt = (cls >> 4) + 1;
   const dim3 grid(sweep_groups(a.jobs), count);
   switch (kt) {
-    case 1: return launch_sweeps_k1(top, bot, single, grid, st, a);
-    case 2: return launch_sweeps_k2(top, bot, single, grid, st, a);
-    case 3: return launch_sweeps_k3(top, bot, single, grid, st, a);
-    case 4: return launch_sweeps_k4(top, bot, single, grid, st, a);
-    case 5: return launch_sweeps_k5(top, bot, single, grid, st, a);
-    case 6: return launch_sweeps_k6(top, bot, single, grid, st, a);
+    case 1: return launch_sweeps_k1(variant, grid, st, a);
+    case 2: return launch_sweeps_k2(variant, grid, st, a);
+    case 3: return launch_sweeps_k3(variant, grid, st, a);
+    case 4: return launch_sweeps_k4(variant, grid, st, a);
+    case 5: return launch_sweeps_k5(variant, grid, st, a);
+    case 6: return launch_sweeps_k6(variant, grid, st, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -495,8 +494,8 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
   sa.M = P.M;
   sa.terms = terms;
   sa.conv = conv;
-  sa.p0 = pi0;
-  sa.p1 = sa.p2 = sa.p3 = pe;
+  sa.p00 = pi0;
+  sa.pe = pe;
   sa.eta = (float)opts->damping;
   sa.lnW = lnw;
   sa.nblocks = P.nblocks;

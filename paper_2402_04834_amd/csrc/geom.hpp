@@ -25,6 +25,17 @@ namespace bbp {
 
 enum : int { FRAME_E = 0, FRAME_W = 1, FRAME_S = 2, FRAME_N = 3 };
 
+// Geometry flags of a block sweep, uniform over its steps (qubits and checks alternate along both axes,
+// and the orientation of the qubits of a step alternates with the step).
+enum : int {
+  GEO_Q00 = 1,        // the first site of the first step is a qubit
+  GEO_SWAP0 = 2,      // orientation flag (qubit_coef's `swap`) of the qubits of the first step
+  GEO_TOP_EDGE = 4,   // the up-leg of the first position leaves the grid
+  GEO_BOT_EDGE = 8,   // the down-leg of the last position leaves the grid
+  GEO_IN_EDGE = 16,   // the in-legs of the first step leave the grid
+  GEO_OUT_EDGE = 32,  // the out-legs of the last step leave the grid
+};
+
 // Grid site visited at sweep step t, position i of a block with origin (r0, c0) and size kr x kc.
 BBP_HD void frame_site(int frame, int r0, int c0, int kr, int kc, int t, int i, int& r, int& c) {
   switch (frame) {

@@ -333,6 +333,18 @@ Plan make_plan(int d, int kr, int kc, int chi) {
     }
     s.msg_close = (out < 0) ? msg(I, J, I + DI[frame], J + DJ[frame]) : -1;
     s.block = I * p.nJ + J;
+    // geometry flags, uniform over the sweep's steps
+    int r, c, a_up, a_in, a_dn, a_out;
+    frame_site(frame, s.r0, s.c0, s.kr, s.kc, 0, 0, r, c);
+    site_flags(frame, p.L, r, c, a_up, a_in, a_dn, a_out);
+    s.geo = ((((r + c) & 1) == 0) ? GEO_Q00 : 0) | ((ew ? (c & 1) : !(r & 1)) ? GEO_SWAP0 : 0) |
+            (a_up ? GEO_TOP_EDGE : 0) | (a_in ? GEO_IN_EDGE : 0);
+    frame_site(frame, s.r0, s.c0, s.kr, s.kc, 0, s.kp - 1, r, c);
+    site_flags(frame, p.L, r, c, a_up, a_in, a_dn, a_out);
+    if (a_dn) s.geo |= GEO_BOT_EDGE;
+    frame_site(frame, s.r0, s.c0, s.kr, s.kc, s.kt - 1, 0, r, c);
+    site_flags(frame, p.L, r, c, a_up, a_in, a_dn, a_out);
+    if (a_out) s.geo |= GEO_OUT_EDGE;
     return s;
   };
   for (int e = 0; e < p.M; ++e) {

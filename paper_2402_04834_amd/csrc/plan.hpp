@@ -18,7 +18,8 @@ struct SweepDesc {
   int32_t msg_close;            // Bethe: message from the receiver side, -1 if none
   int32_t block;                // block index (row-major)
   float flops;                  // algorithmic flops of this sweep
-  int32_t pad[2];
+  int32_t geo;                  // GEO_* flags (geom.hpp)
+  int32_t pad;
 };
 static_assert(sizeof(SweepDesc) == 64, "SweepDesc layout");
 

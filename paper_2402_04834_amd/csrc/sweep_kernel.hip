@@ -24,7 +24,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // entry index of a K-leg dense message with its legs in reverse order
 __device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
 
-template <int KT, bool TOP, bool BOT, bool SINGLE>
+template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
 __global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
@@ -38,18 +38,10 @@ void sweep_kernel(SweepArgs a) {
   wave::Ctx c;
   c.h = lane;
   c.kp = kp;
-  c.kt = KT;
-  c.frame = s.frame;
-  c.r0 = s.r0;
-  c.c0 = s.c0;
-  c.kr = s.kr;
-  c.kc = s.kc;
-  c.L = L;
-  c.p0 = a.p0;
-  c.p1 = a.p1;
-  c.p2 = a.p2;
-  c.p3 = a.p3;
-  c.logscale = 0.0;
+  c.geo = s.geo;
+  c.p00 = a.p00;
+  c.pe = a.pe;
+  c.exp2 = 0;
   const uint8_t* lab = a.labels + job * L * L;
   int lb = 0;
   if (lane < KT * kp) {
@@ -67,25 +59,21 @@ void sweep_kernel(SweepArgs a) {
   c.mtv = (TOP && in_msg) ? mbase[s.msg_top * MSTRIDE + sl] : 0.0f;
   c.mbv = (BOT && in_msg) ? mbase[s.msg_bot * MSTRIDE + sl] : 0.0f;
 
-  // message index of this lane's configuration: position i is lane bit pbit(i), message bit kp-1-i
+  // message index of this lane's configuration: position i is lane bit pshift(i), message bit kp-1-i
   int mi = 0;
   for (int i = 0; i < kp; ++i)
-    if (lane & wave::pbit(kp, i)) mi |= 1 << (kp - 1 - i);
+    if (lane & (1 << wave::pshift(kp, i))) mi |= 1 << (kp - 1 - i);
 
   float x0;
   if (s.msg_init >= 0) {
     x0 = valid ? mbase[s.msg_init * MSTRIDE + mi] : 0.0f;
   } else {
     // the sweep starts at the grid edge: checks whose in-leg leaves the grid are free variables
-    int ia = 0;
-    for (int i = 0; i < kp; ++i) {
-      const wave::SiteInfo si = wave::site_info(c, 0, i);
-      if (!si.qubit && (si.absent & 2)) ia |= wave::pbit(kp, i);
-    }
+    const int ia = (s.geo & GEO_IN_EDGE) ? wave::check_lanes(c, Q00) : 0;
     x0 = ((lane & ~ia) == 0) ? 1.0f : 0.0f;
   }
 
-  float fin = wave::sweep<KT, TOP, BOT, SINGLE>(x0, c);
+  float fin = wave::sweep<KT, TOP, BOT, SINGLE, Q00>(x0, c);
   fin = valid ? fin : 0.0f;
 
   if (a.mode == 1) {
@@ -94,7 +82,7 @@ void sweep_kernel(SweepArgs a) {
     if (s.msg_close >= 0) w = valid ? (double)mbase[s.msg_close * MSTRIDE + mi] * (double)fin : 0.0;
     else if (lane == 0) w = fin;
     w = wave_sum_d(w);
-    if (lane == 0) a.lnW[job * a.nblocks + s.block] = (w > 0.0) ? c.logscale + log(w) : NAN;
+    if (lane == 0) a.lnW[job * a.nblocks + s.block] = (w > 0.0) ? c.exp2 * 0.69314718055994530942 + log(w) : NAN;
   } else {
     // normalised new message, damping against the old one, distance term
     float* mo = a.msgs + job * a.M * MSTRIDE + s.msg_out * MSTRIDE;
@@ -117,20 +105,33 @@ void sweep_kernel(SweepArgs a) {
 #define BBP_CAT(a, b) BBP_CAT2(a, b)
 
 namespace {
-template <bool SINGLE>
-void launch_one(bool top, bool bot, dim3 grid, hipStream_t st, const SweepArgs& a) {
-  const dim3 block(SWEEP_WAVES * 64);
-  if (top && bot) sweep_kernel<BBP_KT, true, true, SINGLE><<<grid, block, 0, st>>>(a);
-  else if (top) sweep_kernel<BBP_KT, true, false, SINGLE><<<grid, block, 0, st>>>(a);
-  else if (bot) sweep_kernel<BBP_KT, false, true, SINGLE><<<grid, block, 0, st>>>(a);
-  else sweep_kernel<BBP_KT, false, false, SINGLE><<<grid, block, 0, st>>>(a);
+template <int V>
+void launch_variant(dim3 grid, hipStream_t st, const SweepArgs& a) {
+  sweep_kernel<BBP_KT, (V >> 3) & 1, (V >> 2) & 1, (V >> 1) & 1, V & 1><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
 }
 }  // namespace
 
-hipError_t BBP_CAT(launch_sweeps_k, BBP_KT)(bool top, bool bot, bool single, dim3 grid, hipStream_t st,
-                                            const SweepArgs& a) {
-  if (single) launch_one<true>(top, bot, grid, st, a);
-  else launch_one<false>(top, bot, grid, st, a);
+// variant = ((top * 2 + bottom) * 2 + single) * 2 + q00
+hipError_t BBP_CAT(launch_sweeps_k, BBP_KT)(int variant, dim3 grid, hipStream_t st, const SweepArgs& a) {
+  switch (variant) {
+    case 0: launch_variant<0>(grid, st, a); break;
+    case 1: launch_variant<1>(grid, st, a); break;
+    case 2: launch_variant<2>(grid, st, a); break;
+    case 3: launch_variant<3>(grid, st, a); break;
+    case 4: launch_variant<4>(grid, st, a); break;
+    case 5: launch_variant<5>(grid, st, a); break;
+    case 6: launch_variant<6>(grid, st, a); break;
+    case 7: launch_variant<7>(grid, st, a); break;
+    case 8: launch_variant<8>(grid, st, a); break;
+    case 9: launch_variant<9>(grid, st, a); break;
+    case 10: launch_variant<10>(grid, st, a); break;
+    case 11: launch_variant<11>(grid, st, a); break;
+    case 12: launch_variant<12>(grid, st, a); break;
+    case 13: launch_variant<13>(grid, st, a); break;
+    case 14: launch_variant<14>(grid, st, a); break;
+    case 15: launch_variant<15>(grid, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

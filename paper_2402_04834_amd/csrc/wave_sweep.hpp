@@ -14,14 +14,21 @@
 // middle position i, so every qubit transform pairs lanes at a compile-time distance: 1 and 2 by DPP
 // quad permutes, 4 / 8 / 16 by ds_swizzle, 32 by ds_bpermute. The cap indices of the state -- n for the
 // top side message, s for the bottom one -- are register indices. The cap dimensions at each column are
-// fixed by the sweep length and direction (bond j of a K-site message carries 2^min(j, K-j) values in the
-// open-leg reading), so the whole sweep is instantiated per (sweep length, direction, caps present), and
-// every register index is a compile-time constant. No LDS, no barriers: a workgroup holds independent
-// sweeps, one per wavefront.
+// fixed by the sweep length (bond j of a K-site message carries 2^min(j, K-j) values in the open-leg
+// reading), and qubits and checks alternate along both axes, so with the sweep length, the caps present
+// and the kind of the first site as template parameters every register index and every qubit/check
+// decision is a compile-time constant. No LDS, no barriers: a workgroup holds independent sweeps.
 //
 // Side-message caps: psi over the old cap index, phi over the new one and the emitted vertical bond v (see
 // Cap below). Any placement of the dense core along the message gives the same exact contraction; a sweep
 // that runs against the message's leg order reads the message with its legs reversed.
+//
+// Noise: i.i.d. depolarizing; a qubit tensor entry is p00 = 1 - p when its label flipped by the adjacent
+// bond parities is the identity and pe = p/3 otherwise.
+//
+// Scaling: after every column but the last the state is rescaled by an exact power of two chosen from its
+// norm (the exponent is accumulated), and the factor is folded into the first qubit transform of the next
+// column, so normalisation costs one multiply-add per state entry and a wave reduction.
 #pragma once
 #include <utility>
 
@@ -59,15 +66,19 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+__device__ __forceinline__ float wave_sum(float v) {
+  sfor<6>([&](auto k) { v += xchg<(1 << k)>(v); });
+  return v;
+}
+
 // ------------------------------------------------------------------------------------------- cap shapes
 enum : int { K_NONE = 0, K_LT, K_EQ, K_GT };
 
 constexpr int cdim(int K, int j) { return 1 << ((j < K - j) ? j : K - j); }
 
-// Cap at step T of a KT-step sweep. A sweep that walks a side message from its last site is run on the
-// message with its legs reversed, so every cap walks its message from the first site: steps before the
-// middle site D append the emitted bond as the low bit of the cap index, the middle site contracts with the
-// dense message entry m[(a, v, np)], later steps strip the emitted bond from the high bit.
+// Cap at step T of a KT-step sweep, walked from the message's first site: steps before the middle site
+// D append the emitted bond as the low bit of the cap index, the middle site contracts with the dense
+// message entry m[(a, v, np)], later steps strip the emitted bond from the high bit.
 template <bool PRESENT, int KT, int T>
 struct Cap {
   static constexpr int D = KT / 2;
@@ -75,6 +86,7 @@ struct Cap {
   static constexpr int PN = PRESENT ? cdim(KT, T + 1) : 1;
   static constexpr int R2 = 1 << (KT - D - 1);
   static constexpr int kind = !PRESENT ? K_NONE : (T < D ? K_LT : T == D ? K_EQ : K_GT);
+  static constexpr int idx(int a, int v, int np) { return (2 * a + v) * R2 + np; }   // entry of m (K_EQ)
 };
 
 // phi[NP][V] = sum_a op[a][V][NP] psi[a]; g(a) reads psi[a] (a compile-time), m(idx) reads the dense side
@@ -91,64 +103,90 @@ __device__ __forceinline__ float phi(G&& g, Msg&& m) {
     return g(std::integral_constant<int, V * C::PN + NP>{});
   } else {
     float acc = 0.0f;
-    sfor<C::PO>([&](auto a) { acc += m(std::integral_constant<int, (2 * a + V) * C::R2 + NP>{}) * g(a); });
+    sfor<C::PO>([&](auto a) { acc += m(std::integral_constant<int, C::idx(a, V, NP)>{}) * g(a); });
+    return acc;
+  }
+}
+
+// phi[NP][0] over g0 plus phi[NP][1] over g1, without adding structural zeros (routing caps).
+template <class C, int NP, class G0, class G1, class Msg>
+__device__ __forceinline__ float phi2(G0&& g0, G1&& g1, Msg&& m) {
+  if constexpr (C::kind == K_NONE) {
+    return g0(std::integral_constant<int, 0>{});
+  } else if constexpr (C::kind == K_LT) {
+    if constexpr (NP & 1) return g1(std::integral_constant<int, (NP >> 1)>{});
+    else return g0(std::integral_constant<int, (NP >> 1)>{});
+  } else if constexpr (C::kind == K_GT) {
+    return g0(std::integral_constant<int, NP>{}) + g1(std::integral_constant<int, C::PN + NP>{});
+  } else {
+    float acc = 0.0f;
+    sfor<C::PO>([&](auto a) {
+      acc += m(std::integral_constant<int, C::idx(a, 0, NP)>{}) * g0(a);
+      acc += m(std::integral_constant<int, C::idx(a, 1, NP)>{}) * g1(a);
+    });
     return acc;
   }
 }
 
 // ------------------------------------------------------------------------------------- sweep context
 struct Ctx {
-  int h;                       // lane = crossing-bond configuration (lane-bit layout above)
-  int kp, kt;                  // positions across the sweep, sweep steps
-  int frame, r0, c0, kr, kc, L;
-  float labv;                  // lane l < kt*kp: coset label of the site at (step l / kp, position l % kp)
-  float mtv, mbv;              // lane l: entry l of the top / bottom side message (0 if absent)
-  float p0, p1, p2, p3;        // noise table {I, Z, X, Y} indexed x*2 + z
-  double logscale;             // accumulated log of the normalisations
+  int h;                // lane = crossing-bond configuration (lane-bit layout above)
+  int kp;               // positions across the sweep
+  int geo;              // GEO_* flags
+  float labv;           // lane l < kt*kp: coset label of the site at (step l / kp, position l % kp)
+  float mtv, mbv;       // lane l: entry l of the top / bottom side message (legs in sweep order)
+  float p00, pe;        // depolarizing entries
+  int exp2;             // accumulated power-of-two scale (state values are true values * 2^-exp2)
 };
 
-// lane bit of position i
-__device__ __forceinline__ int pbit(int kp, int i) { return i == 0 ? 1 : (i == kp - 1 ? 2 : (1 << (i + 1))); }
+__device__ __forceinline__ int bit(int h, int b) { return (h >> b) & 1; }
+// lane-bit index of position i
+__device__ __forceinline__ int pshift(int kp, int i) { return i == 0 ? 0 : (i == kp - 1 ? 1 : i + 1); }
 
-struct SiteInfo {
-  int qubit, label, swap, absent;   // absent: legs (up, in, down, out) that leave the grid, bits 0..3
+struct QC {
+  float cs, cf;   // coefficient of the lane's own value and of the partner lane's (crossing bit flipped)
 };
 
-__device__ __forceinline__ SiteInfo site_info(const Ctx& c, int t, int i) {
-  int r, cc;
-  frame_site(c.frame, c.r0, c.c0, c.kr, c.kc, t, i, r, cc);
-  int a_up, a_in, a_dn, a_out;
-  const int au = (r == 0), al = (cc == 0), ad = (r == c.L - 1), ar = (cc == c.L - 1);
-  switch (c.frame) {
-    case FRAME_E: a_up = au; a_in = al; a_dn = ad; a_out = ar; break;
-    case FRAME_W: a_up = au; a_in = ar; a_dn = ad; a_out = al; break;
-    case FRAME_S: a_up = al; a_in = au; a_dn = ar; a_out = ad; break;
-    default:      a_up = al; a_in = ad; a_dn = ar; a_out = au; break;
+// Coefficients of a qubit with coset label lb and orientation swap for a lane whose vertical bond parity
+// is pv and output crossing bit ho; scaled by sc. The noise entry is p00 iff the label flipped by the
+// parities is the identity: the component the crossing parity acts on must equal it (0 for the lane's own
+// value, 1 for the partner's) and the other component must equal pv.
+__device__ __forceinline__ QC qcoef(const Ctx& c, int lb, int swap, int pv, int ho, bool in_abs, bool out_abs,
+                                    float sc) {
+  const int lx = lb & 1, lz = (lb >> 1) & 1;
+  const int A = swap ? lx : lz, B = swap ? lz : lx;
+  const bool m = (pv == B);
+  const float hi = c.p00 * sc, lo = c.pe * sc;
+  QC q;
+  q.cs = (m && A == 0) ? hi : lo;
+  q.cf = (m && A == 1) ? hi : lo;
+  if (in_abs) {   // the input crossing bit must be 0
+    q.cs = ho ? 0.0f : q.cs;
+    q.cf = ho ? q.cf : 0.0f;
   }
-  SiteInfo s;
-  s.qubit = ((r + cc) & 1) == 0;
-  s.absent = a_up | (a_in << 1) | (a_dn << 2) | (a_out << 3);
-  s.swap = ((r & 1) != 0) != (c.frame >= FRAME_S);
-  s.label = s.qubit ? (__float_as_int(readlane_f(c.labv, t * c.kp + i)) & 3) : 0;
-  return s;
+  if (out_abs) {   // the output crossing bit must be 0
+    q.cs = ho ? 0.0f : q.cs;
+    q.cf = ho ? 0.0f : q.cf;
+  }
+  return q;
 }
 
-__device__ __forceinline__ float coef(const Ctx& c, const SiteInfo& s, int vi, int hi, int vo, int ho) {
-  return qubit_coef(s.label, s.swap, s.absent, c.p0, c.p1, c.p2, c.p3, vi, hi, vo, ho);
+__device__ __forceinline__ int label_at(const Ctx& c, int t, int i) {
+  return __float_as_int(readlane_f(c.labv, t * c.kp + i)) & 3;
 }
 
-// lane mask of the checks of step t whose out-leg leaves the grid (their variable is summed)
-__device__ __forceinline__ int out_absent_mask(const Ctx& c, int t) {
+// lane mask of the checks of a column (q0t: its site 0 is a qubit)
+__device__ __forceinline__ int check_lanes(const Ctx& c, bool q0t) {
   int m = 0;
-  for (int i = 0; i < c.kp; ++i) {
-    const SiteInfo s = site_info(c, t, i);
-    if (!s.qubit && (s.absent & 8)) m |= pbit(c.kp, i);
-  }
+  for (int i = 0; i < c.kp; ++i)
+    if (!(q0t ^ (i & 1))) m |= 1 << pshift(c.kp, i);
   return m;
 }
 
+// Sum over the variables of the checks whose out-leg leaves the grid (lane bits oa): the result sits at
+// those bits = 0.
 template <int N>
-__device__ __forceinline__ void project_out_absent(float (&Y)[N], const Ctx& c, int oa) {
+__device__ __forceinline__ void project_out_edge(float (&Y)[N], const Ctx& c, int oa) {
   for (int b = 1; b < 64; b <<= 1) {
     if (!(oa & b)) continue;
     const bool zero = (c.h & b) != 0;
@@ -160,137 +198,215 @@ __device__ __forceinline__ void project_out_absent(float (&Y)[N], const Ctx& c, 
 }
 
 // --------------------------------------------------------------------------------- column, kp >= 2
-template <int KT, bool TOP, bool BOT, int T>
+template <int KT, bool TOP, bool BOT, bool Q00, int T>
 __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
-                                             float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN],
-                                             Ctx& c) {
+                                             float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx& c,
+                                             float sc) {
   using CT = Cap<TOP, KT, T>;
   using CB = Cap<BOT, KT, T>;
   constexpr int PTO = CT::PO, PTN = CT::PN, PSO = CB::PO, PSN = CB::PN;
+  constexpr bool Q0 = Q00 ^ (T & 1);   // site 0 of this column is a qubit
   const int h = c.h, kp = c.kp;
+  const int swap = ((c.geo & GEO_SWAP0) ? 1 : 0) ^ (T & 1);
+  const bool in_abs = (T == 0) && (c.geo & GEO_IN_EDGE);
+  const bool out_abs = (T == KT - 1) && (c.geo & GEO_OUT_EDGE);
+  const bool last_q = Q0 ^ ((kp - 1) & 1);   // the last position is a qubit
+  // the pending scale goes into the first qubit transform of the column
+  const float sc0 = Q0 ? sc : 1.0f;
+  const float sc1 = (!Q0 && kp >= 3) ? sc : 1.0f;
+  const float scl = (!Q0 && kp == 2) ? sc : 1.0f;
   auto mt = [&](auto idx) { return readlane_f(c.mtv, idx); };
   auto mb = [&](auto idx) { return readlane_f(c.mbv, idx); };
 
-  // top cap + site 0 (lane bit 0)
+  // ---- top cap + site 0 (lane bit 0)
   float Z[PTN * PSO];
-  const SiteInfo s0 = site_info(c, T, 0);
-  if (s0.qubit) {
-    const int ho = h & 1, vo = (h >> 1 + (kp > 2 ? 1 : 0)) & 1;   // position 1: lane bit 1 if kp == 2, else 2
-    const float cs0 = coef(c, s0, 0, ho, vo, ho), cf0 = coef(c, s0, 0, ho ^ 1, vo, ho);
-    const float cs1 = coef(c, s0, 1, ho, vo, ho), cf1 = coef(c, s0, 1, ho ^ 1, vo, ho);
-    sfor<PSO>([&](auto s) {
-      float Y0[PTO], Y1[PTO];
+  if constexpr (Q0) {
+    const int lb = label_at(c, T, 0);
+    const int ho = bit(h, 0), vo = bit(h, pshift(kp, 1));
+    const QC q0 = qcoef(c, lb, swap, vo, ho, in_abs, out_abs, sc0);
+    QC q1 = qcoef(c, lb, swap, vo ^ 1, ho, in_abs, out_abs, sc0);
+    if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = 0.0f;
+    if constexpr (CT::kind == K_EQ) {
+      // old cap index outermost: the message entries of one a are uniform (scalar) operands, and X[a][.]
+      // is dead once its partner values are formed
       sfor<PTO>([&](auto a) {
-        const float x = X[a * PSO + s], xf = xchg<1>(x);
-        Y0[a] = cs0 * x + cf0 * xf;
-        Y1[a] = cs1 * x + cf1 * xf;
+        sfor<PSO>([&](auto s) {
+          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          const float y0 = q0.cs * x + q0.cf * xf, y1 = q1.cs * x + q1.cf * xf;
+          sfor<PTN>([&](auto n) {
+            float& z = Z[n * PSO + s];
+            const float t = mt(std::integral_constant<int, CT::idx(a, 0, n)>{}) * y0;
+            z = (a == 0) ? t : z + t;
+            z += mt(std::integral_constant<int, CT::idx(a, 1, n)>{}) * y1;
+          });
+        });
       });
-      sfor<PTN>([&](auto n) {
-        Z[n * PSO + s] = phi<CT, n, 0>([&](auto a) { return Y0[a]; }, mt) +
-                         phi<CT, n, 1>([&](auto a) { return Y1[a]; }, mt);
+    } else {
+      sfor<PSO>([&](auto s) {
+        float y0[PTO], y1[PTO];
+        sfor<PTO>([&](auto a) {
+          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          y0[a] = q0.cs * x + q0.cf * xf;
+          y1[a] = (CT::kind != K_NONE) ? q1.cs * x + q1.cf * xf : 0.0f;
+        });
+        sfor<PTN>([&](auto n) {
+          Z[n * PSO + s] = phi2<CT, n>([&](auto a) { return y0[a]; }, [&](auto a) { return y1[a]; }, mt);
+        });
       });
-    });
+    }
   } else {
-    const bool v1 = !(s0.absent & 1) && (h & 1);
-    sfor<PSO>([&](auto s) {
-      sfor<PTN>([&](auto n) {
-        const float z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
-        const float z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
-        Z[n * PSO + s] = v1 ? z1 : z0;
+    const bool v1 = !(c.geo & GEO_TOP_EDGE) && bit(h, 0);
+    if constexpr (CT::kind == K_EQ) {
+      sfor<PTO>([&](auto a) {
+        float ms[PTN];
+        sfor<PTN>([&](auto n) {
+          // both entries read unconditionally: a lane read cannot sit under a lane-dependent branch
+          const float m0 = mt(std::integral_constant<int, CT::idx(a, 0, n)>{});
+          const float m1 = mt(std::integral_constant<int, CT::idx(a, 1, n)>{});
+          ms[n] = v1 ? m1 : m0;
+        });
+        sfor<PSO>([&](auto s) {
+          sfor<PTN>([&](auto n) {
+            const float t = ms[n] * X[a * PSO + s];
+            Z[n * PSO + s] = (a == 0) ? t : Z[n * PSO + s] + t;
+          });
+        });
       });
-    });
+    } else {
+      sfor<PSO>([&](auto s) {
+        sfor<PTN>([&](auto n) {
+          const float z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
+          const float z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
+          Z[n * PSO + s] = v1 ? z1 : z0;
+        });
+      });
+    }
   }
 
-  // middle qubits (positions 1 .. kp-2, lane bits 2 .. kp-1)
+  // ---- middle qubits (positions 1 .. kp-2, lane bits 2 .. kp-1)
   sfor<4>([&](auto j) {
     constexpr int i = j + 1;
-    constexpr int bit = 1 << (i + 1);
-    if (i <= kp - 2) {
-      const SiteInfo si = site_info(c, T, i);
-      if (si.qubit) {
-        const int vi = (h >> (i == 1 ? 0 : i)) & 1;                    // position i-1
-        const int vo = (i + 1 == kp - 1) ? ((h >> 1) & 1) : ((h >> (i + 2)) & 1);   // position i+1
-        const int ho = (h >> (i + 1)) & 1;
-        const float cs = coef(c, si, vi, ho, vo, ho), cf = coef(c, si, vi, ho ^ 1, vo, ho);
-        sfor<PTN * PSO>([&](auto e) { Z[e] = cs * Z[e] + cf * xchg<bit>(Z[e]); });
+    if constexpr (Q0 ^ (i & 1)) {
+      if (i <= kp - 2) {
+        const int lb = label_at(c, T, i);
+        const int vi = bit(h, i == 1 ? 0 : i);
+        const int vo = (i + 1 == kp - 1) ? bit(h, 1) : bit(h, i + 2);
+        const QC q = qcoef(c, lb, swap, vi ^ vo, bit(h, i + 1), in_abs, out_abs, i == 1 ? sc1 : 1.0f);
+        sfor<PTN * PSO>([&](auto e) { Z[e] = q.cs * Z[e] + q.cf * xchg<(2 << i)>(Z[e]); });
       }
     }
   });
 
-  // bottom cap + last site (lane bit 1)
-  const SiteInfo sl = site_info(c, T, kp - 1);
-  if (sl.qubit) {
-    const int ho = (h >> 1) & 1, vi = (h >> (kp > 2 ? kp - 1 : 0)) & 1;   // position kp-2
-    const float cs0 = coef(c, sl, vi, ho, 0, ho), cf0 = coef(c, sl, vi, ho ^ 1, 0, ho);
-    const float cs1 = coef(c, sl, vi, ho, 1, ho), cf1 = coef(c, sl, vi, ho ^ 1, 1, ho);
-    sfor<PTN>([&](auto n) {
-      float Y0[PSO], Y1[PSO];
+  // ---- bottom cap + last site (lane bit 1)
+  if (last_q) {
+    const int lb = label_at(c, T, kp - 1);
+    const int ho = bit(h, 1), vi = bit(h, pshift(kp, kp - 2));
+    const QC q0 = qcoef(c, lb, swap, vi, ho, in_abs, out_abs, scl);
+    QC q1 = qcoef(c, lb, swap, vi ^ 1, ho, in_abs, out_abs, scl);
+    if (c.geo & GEO_BOT_EDGE) q1.cs = q1.cf = 0.0f;
+    if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
-        const float z = Z[n * PSO + b], zf = xchg<2>(z);
-        Y0[b] = cs0 * z + cf0 * zf;
-        Y1[b] = cs1 * z + cf1 * zf;
+        sfor<PTN>([&](auto n) {
+          const float z = Z[n * PSO + b], zf = xchg<2>(z);
+          const float y0 = q0.cs * z + q0.cf * zf, y1 = q1.cs * z + q1.cf * zf;
+          sfor<PSN>([&](auto sp) {
+            float& y = Y[n * PSN + sp];
+            const float t = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{}) * y0;
+            y = (b == 0) ? t : y + t;
+            y += mb(std::integral_constant<int, CB::idx(b, 1, sp)>{}) * y1;
+          });
+        });
       });
-      sfor<PSN>([&](auto sp) {
-        Y[n * PSN + sp] = phi<CB, sp, 0>([&](auto b) { return Y0[b]; }, mb) +
-                          phi<CB, sp, 1>([&](auto b) { return Y1[b]; }, mb);
+    } else {
+      sfor<PTN>([&](auto n) {
+        float y0[PSO], y1[PSO];
+        sfor<PSO>([&](auto b) {
+          const float z = Z[n * PSO + b], zf = xchg<2>(z);
+          y0[b] = q0.cs * z + q0.cf * zf;
+          y1[b] = (CB::kind != K_NONE) ? q1.cs * z + q1.cf * zf : 0.0f;
+        });
+        sfor<PSN>([&](auto sp) {
+          Y[n * PSN + sp] = phi2<CB, sp>([&](auto b) { return y0[b]; }, [&](auto b) { return y1[b]; }, mb);
+        });
       });
-    });
+    }
   } else {
-    const bool v1 = !(sl.absent & 4) && (h & 2);
-    sfor<PTN>([&](auto n) {
-      sfor<PSN>([&](auto sp) {
-        const float y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
-        const float y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
-        Y[n * PSN + sp] = v1 ? y1 : y0;
+    const bool v1 = !(c.geo & GEO_BOT_EDGE) && bit(h, 1);
+    if constexpr (CB::kind == K_EQ) {
+      sfor<PSO>([&](auto b) {
+        float ms[PSN];
+        sfor<PSN>([&](auto sp) {
+          const float m0 = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{});
+          const float m1 = mb(std::integral_constant<int, CB::idx(b, 1, sp)>{});
+          ms[sp] = v1 ? m1 : m0;
+        });
+        sfor<PTN>([&](auto n) {
+          sfor<PSN>([&](auto sp) {
+            const float t = ms[sp] * Z[n * PSO + b];
+            Y[n * PSN + sp] = (b == 0) ? t : Y[n * PSN + sp] + t;
+          });
+        });
       });
-    });
+    } else {
+      sfor<PTN>([&](auto n) {
+        sfor<PSN>([&](auto sp) {
+          const float y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
+          const float y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
+          Y[n * PSN + sp] = v1 ? y1 : y0;
+        });
+      });
+    }
   }
-  if (T == KT - 1) {
-    const int oa = out_absent_mask(c, T);
-    if (oa) project_out_absent(Y, c, oa);
-  }
+  if (out_abs) project_out_edge(Y, c, check_lanes(c, Q0));
 }
 
 // --------------------------------------------------------------------------------- column, kp == 1
 // The single site of the column meets both caps: a qubit sums both emitted bonds (the bottom one is kept
 // as an extra index between the two cap steps), a check emits its own variable on both.
-template <int KT, bool TOP, bool BOT, int T>
-__device__ __forceinline__ void column_single(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
-                                              float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx& c) {
+template <int KT, bool TOP, bool BOT, bool Q00, int T>
+__device__ __forceinline__ void column_single(const float (&Xin)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
+                                              float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx& c,
+                                              float sc) {
   using CT = Cap<TOP, KT, T>;
   using CB = Cap<BOT, KT, T>;
   constexpr int PTO = CT::PO, PTN = CT::PN, PSO = CB::PO, PSN = CB::PN;
-  const int h = c.h;
+  constexpr bool Q0 = Q00 ^ (T & 1);
+  const int h = c.h, ho = h & 1;
+  const int swap = ((c.geo & GEO_SWAP0) ? 1 : 0) ^ (T & 1);
+  const bool in_abs = (T == 0) && (c.geo & GEO_IN_EDGE);
+  const bool out_abs = (T == KT - 1) && (c.geo & GEO_OUT_EDGE);
   auto mt = [&](auto idx) { return readlane_f(c.mtv, idx); };
   auto mb = [&](auto idx) { return readlane_f(c.mbv, idx); };
-  const SiteInfo s0 = site_info(c, T, 0);
-  const int ho = h & 1;
-  if (s0.qubit) {
+  float X[PTO * PSO];
+  sfor<PTO * PSO>([&](auto e) { X[e] = Xin[e] * sc; });
+  if constexpr (Q0) {
+    const int lb = label_at(c, T, 0);
     float Z[2][PTN * PSO];   // [emitted bottom bond][np][s]
     sfor<2>([&](auto vb) {
-      const float cs0 = coef(c, s0, 0, ho, vb, ho), cf0 = coef(c, s0, 0, ho ^ 1, vb, ho);
-      const float cs1 = coef(c, s0, 1, ho, vb, ho), cf1 = coef(c, s0, 1, ho ^ 1, vb, ho);
+      QC q0 = qcoef(c, lb, swap, vb, ho, in_abs, out_abs, 1.0f);       // emitted top bond 0
+      QC q1 = qcoef(c, lb, swap, vb ^ 1, ho, in_abs, out_abs, 1.0f);   // emitted top bond 1
+      if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = 0.0f;
+      if (vb == 1 && (c.geo & GEO_BOT_EDGE)) q0.cs = q0.cf = q1.cs = q1.cf = 0.0f;
       sfor<PSO>([&](auto s) {
-        float Y0[PTO], Y1[PTO];
+        float y0[PTO], y1[PTO];
         sfor<PTO>([&](auto a) {
           const float x = X[a * PSO + s], xf = xchg<1>(x);
-          Y0[a] = cs0 * x + cf0 * xf;
-          Y1[a] = cs1 * x + cf1 * xf;
+          y0[a] = q0.cs * x + q0.cf * xf;
+          y1[a] = q1.cs * x + q1.cf * xf;
         });
         sfor<PTN>([&](auto n) {
-          Z[vb][n * PSO + s] = phi<CT, n, 0>([&](auto a) { return Y0[a]; }, mt) +
-                               phi<CT, n, 1>([&](auto a) { return Y1[a]; }, mt);
+          Z[vb][n * PSO + s] = phi2<CT, n>([&](auto a) { return y0[a]; }, [&](auto a) { return y1[a]; }, mt);
         });
       });
     });
     sfor<PTN>([&](auto n) {
       sfor<PSN>([&](auto sp) {
-        Y[n * PSN + sp] = phi<CB, sp, 0>([&](auto b) { return Z[0][n * PSO + b]; }, mb) +
-                          phi<CB, sp, 1>([&](auto b) { return Z[1][n * PSO + b]; }, mb);
+        Y[n * PSN + sp] =
+            phi2<CB, sp>([&](auto b) { return Z[0][n * PSO + b]; }, [&](auto b) { return Z[1][n * PSO + b]; }, mb);
       });
     });
   } else {
-    const bool vt = !(s0.absent & 1) && ho, vb = !(s0.absent & 4) && ho;
+    const bool vt = !(c.geo & GEO_TOP_EDGE) && ho, vb = !(c.geo & GEO_BOT_EDGE) && ho;
     float Z[PTN * PSO];
     sfor<PSO>([&](auto s) {
       sfor<PTN>([&](auto n) {
@@ -306,46 +422,42 @@ __device__ __forceinline__ void column_single(const float (&X)[Cap<TOP, KT, T>::
         Y[n * PSN + sp] = vb ? y1 : y0;
       });
     });
-  }
-  if (T == KT - 1) {
-    const int oa = out_absent_mask(c, T);
-    if (oa) project_out_absent(Y, c, oa);
+    if (out_abs) project_out_edge(Y, c, 1);
   }
 }
 
 // ------------------------------------------------------------------------------------------ the sweep
-__device__ __forceinline__ float wave_sum(float v) {
-  sfor<6>([&](auto k) { v += xchg<(1 << k)>(v); });
-  return v;
+// Power-of-two rescale of a state with squared norm ss: returns the factor to apply and accumulates its
+// exponent.
+__device__ __forceinline__ float pow2_scale(float ss, Ctx& c) {
+  const int e = (ss > 0.0f && ss < INFINITY) ? (__builtin_amdgcn_frexp_expf(ss) >> 1) : 0;
+  c.exp2 += e;
+  return __builtin_amdgcn_ldexpf(1.0f, -e);
 }
 
-template <int N>
-__device__ __forceinline__ void normalise(float (&Y)[N], Ctx& c) {
-  float ss = 0.0f;
-  sfor<N>([&](auto e) { ss += Y[e] * Y[e]; });
-  ss = wave_sum(ss);
-  const float nrm = sqrtf(ss);
-  const float inv = (nrm > 0.0f) ? 1.0f / nrm : 0.0f;
-  c.logscale += (double)logf(nrm);
-  sfor<N>([&](auto e) { Y[e] *= inv; });
+// Absorb columns T .. KT-1 into the state X (pending scale sc); returns the final state of this lane.
+template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, int T>
+__device__ __forceinline__ float run(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO], Ctx& c,
+                                     float sc) {
+  constexpr int NY = Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN;
+  float Y[NY];
+  if constexpr (SINGLE) column_single<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
+  else column_multi<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
+  if constexpr (T + 1 < KT) {
+    float ss = 0.0f;
+    sfor<NY>([&](auto e) { ss += Y[e] * Y[e]; });
+    return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
+  } else {
+    return Y[0];
+  }
 }
 
-// Absorb columns T .. KT-1 into the state X; returns the final (one-value-per-lane) state.
-template <int KT, bool TOP, bool BOT, bool SINGLE, int T>
-__device__ __forceinline__ float run(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO], Ctx& c) {
-  float Y[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN];
-  if constexpr (SINGLE) column_single<KT, TOP, BOT, T>(X, Y, c);
-  else column_multi<KT, TOP, BOT, T>(X, Y, c);
-  normalise(Y, c);
-  if constexpr (T + 1 < KT) return run<KT, TOP, BOT, SINGLE, T + 1>(Y, c);
-  else return Y[0];
-}
-
-// The whole sweep from the entering state x0 (one value per lane); SINGLE: one position across (kp == 1).
-template <int KT, bool TOP, bool BOT, bool SINGLE>
+// The whole sweep from the entering state x0 (one value per lane). SINGLE: one position across (kp == 1);
+// Q00: the first site of the first column is a qubit.
+template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
 __device__ __forceinline__ float sweep(float x0, Ctx& c) {
   const float X[1] = {x0};
-  return run<KT, TOP, BOT, SINGLE, 0>(X, c);
+  return run<KT, TOP, BOT, SINGLE, Q00, 0>(X, c, 1.0f);
 }
 
 }  // namespace wave
