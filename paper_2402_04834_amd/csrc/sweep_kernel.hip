@@ -84,18 +84,17 @@ void sweep_kernel(SweepArgs a) {
     w = wave_sum_d(w);
     if (lane == 0) a.lnW[job * a.nblocks + s.block] = (w > 0.0) ? c.exp2 * 0.69314718055994530942 + log(w) : NAN;
   } else {
-    // normalised new message, damping against the old one, distance term
+    // normalised new message, damping against the old one (unit norm), distance term. With unit vectors
+    // a, b: 2 - 2<a,b>^2 = |a - b|^2 |a + b|^2 / 2, which has no cancellation near convergence in FP32.
     float* mo = a.msgs + job * a.M * MSTRIDE + s.msg_out * MSTRIDE;
     const float old = valid ? mo[mi] : 0.0f;
-    const double n2 = wave_sum_d((double)fin * fin);
-    const float inv = (float)(1.0 / sqrt(n2));
-    const float dm = (1.0f - a.eta) * (fin * inv) + a.eta * old;
-    const double dd = wave_sum_d((double)dm * dm);
-    const double od = wave_sum_d((double)old * old);
-    const double cr = wave_sum_d((double)dm * old);
-    const float fm = dm * (float)(1.0 / sqrt(dd));
+    const float fn = fin * __builtin_amdgcn_rsqf(wave::wave_sum(fin * fin));
+    const float dm = (1.0f - a.eta) * fn + a.eta * old;
+    const float fm = dm * __builtin_amdgcn_rsqf(wave::wave_sum(dm * dm));
+    const float dif = fm - old, sum = fm + old;
+    const float dd = wave::wave_sum(dif * dif), ss = wave::wave_sum(sum * sum);
     if (valid) mo[mi] = fm;
-    if (lane == 0) a.terms[job * a.M + s.msg_out] = 2.0 - 2.0 * (cr * cr) / (dd * od);
+    if (lane == 0) a.terms[job * a.M + s.msg_out] = 0.5 * (double)dd * (double)ss;
   }
 }
 

@@ -26,9 +26,11 @@
 // Noise: i.i.d. depolarizing; a qubit tensor entry is p00 = 1 - p when its label flipped by the adjacent
 // bond parities is the identity and pe = p/3 otherwise.
 //
-// Scaling: after every column but the last the state is rescaled by an exact power of two chosen from its
-// norm (the exponent is accumulated), and the factor is folded into the first qubit transform of the next
-// column, so normalisation costs one multiply-add per state entry and a wave reduction.
+// Scaling: after every second column (odd steps, never the last) the state is rescaled by an exact power of
+// two chosen from its norm (the exponent is accumulated), and the factor is folded into the first qubit
+// transform of the next column, so normalisation costs one multiply-add per state entry and a wave
+// reduction. Entries are non-negative, so two columns shrink a unit state by at most the product of their
+// smallest coefficients and message entries, far above the FP32 range limit.
 #pragma once
 #include <utility>
 
@@ -292,7 +294,10 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
         const int vi = bit(h, i == 1 ? 0 : i);
         const int vo = (i + 1 == kp - 1) ? bit(h, 1) : bit(h, i + 2);
         const QC q = qcoef(c, lb, swap, vi ^ vo, bit(h, i + 1), in_abs, out_abs, i == 1 ? sc1 : 1.0f);
-        sfor<PTN * PSO>([&](auto e) { Z[e] = q.cs * Z[e] + q.cf * xchg<(2 << i)>(Z[e]); });
+        sfor<PTN * PSO>([&](auto e) {
+          const float zx = xchg<(2 << i)>(Z[e]);
+          Z[e] = __builtin_fmaf(q.cf, zx, q.cs * Z[e]);
+        });
       }
     }
   });
@@ -444,9 +449,13 @@ __device__ __forceinline__ float run(const float (&X)[Cap<TOP, KT, T>::PO * Cap<
   if constexpr (SINGLE) column_single<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
   else column_multi<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
   if constexpr (T + 1 < KT) {
-    float ss = 0.0f;
-    sfor<NY>([&](auto e) { ss += Y[e] * Y[e]; });
-    return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
+    if constexpr (T & 1) {
+      float ss = 0.0f;
+      sfor<NY>([&](auto e) { ss += Y[e] * Y[e]; });
+      return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
+    } else {
+      return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, 1.0f);
+    }
   } else {
     return Y[0];
   }
