@@ -12,6 +12,9 @@
 #ifndef BBP_KT
 #error "compile with -DBBP_KT=<sweep length 1..6>"
 #endif
+#ifndef BBP_WAVES_PER_EU
+#define BBP_WAVES_PER_EU 3   // register budget: at least this many wavefronts per SIMD (no spills)
+#endif
 
 namespace bbp {
 namespace {
@@ -25,7 +28,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 __device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
 
 template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
-__global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BBP_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
   const int64_t job = (int64_t)blockIdx.x * SWEEP_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

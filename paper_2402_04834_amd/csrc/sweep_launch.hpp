@@ -9,7 +9,12 @@
 
 namespace bbp {
 
-constexpr int SWEEP_WAVES = 4;   // independent sweeps (wavefronts) per workgroup
+#ifndef BBP_SWEEP_WAVES
+#define BBP_SWEEP_WAVES 1
+#endif
+// independent sweeps (wavefronts) per workgroup: one, so that the wavefront of a converged job, or one
+// that finishes early, frees its slot at once
+constexpr int SWEEP_WAVES = BBP_SWEEP_WAVES;
 constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
 
 struct SweepArgs {

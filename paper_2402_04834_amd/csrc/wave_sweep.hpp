@@ -26,6 +26,11 @@
 // Noise: i.i.d. depolarizing; a qubit tensor entry is p00 = 1 - p when its label flipped by the adjacent
 // bond parities is the identity and pe = p/3 otherwise.
 //
+// Middle-site caps with four new cap values (sweeps of 5 and 6 steps) contract on the matrix cores: the
+// message entries are the same for every lane, so lane 4b+i supplies entry (a, v, i) and lane h = 4b+j
+// its own state value; each v_mfma_f32_4x4x1f32 is one step a of the sum for all four new cap values,
+// which land in the lane's four accumulator registers. FP32 products and FP32 accumulation throughout.
+//
 // Scaling: after every second column (odd steps, never the last) the state is rescaled by an exact power of
 // two chosen from its norm (the exponent is accumulated), and the factor is folded into the first qubit
 // transform of the next column, so normalisation costs one multiply-add per state entry and a wave
@@ -67,6 +72,17 @@ __device__ __forceinline__ float xchg_rt(float x, int m) {
 __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
+
+// value of x in lane l (ds_bpermute)
+__device__ __forceinline__ float lane_get(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(l << 2, __float_as_int(x)));
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One rank-1 step of 16 independent 4x4 products (v_mfma_f32_4x4x1f32): lanes 4b..4b+3 form block b;
+// lane 4b+i supplies a (row i), lane 4b+j supplies b (column j) and holds acc[i] = D[i][j].
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 acc) { return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 0, 0, 0); }
 
 __device__ __forceinline__ float wave_sum(float v) {
   sfor<6>([&](auto k) { v += xchg<(1 << k)>(v); });
@@ -228,7 +244,22 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     const QC q0 = qcoef(c, lb, swap, vo, ho, in_abs, out_abs, sc0);
     QC q1 = qcoef(c, lb, swap, vo ^ 1, ho, in_abs, out_abs, sc0);
     if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = 0.0f;
-    if constexpr (CT::kind == K_EQ) {
+    if constexpr (CT::kind == K_EQ && PTN == 4) {
+      float mA[PTO][2];
+      sfor<PTO>([&](auto a) {
+        mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
+        mA[a][1] = lane_get(c.mtv, CT::idx(a, 1, 0) + (h & 3));
+      });
+      sfor<PSO>([&](auto s) {
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PTO>([&](auto a) {
+          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          acc = mfma4(mA[a][0], q0.cs * x + q0.cf * xf, acc);
+          acc = mfma4(mA[a][1], q1.cs * x + q1.cf * xf, acc);
+        });
+        sfor<4>([&](auto n) { Z[n * PSO + s] = acc[(int)n]; });
+      });
+    } else if constexpr (CT::kind == K_EQ) {
       // old cap index outermost: the message entries of one a are uniform (scalar) operands, and X[a][.]
       // is dead once its partner values are formed
       sfor<PTO>([&](auto a) {
@@ -258,7 +289,22 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     }
   } else {
     const bool v1 = !(c.geo & GEO_TOP_EDGE) && bit(h, 0);
-    if constexpr (CT::kind == K_EQ) {
+    if constexpr (CT::kind == K_EQ && PTN == 4) {
+      float mA[PTO][2];
+      sfor<PTO>([&](auto a) {
+        mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
+        mA[a][1] = lane_get(c.mtv, CT::idx(a, 1, 0) + (h & 3));
+      });
+      sfor<PSO>([&](auto s) {
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PTO>([&](auto a) {
+          const float x = X[a * PSO + s];
+          acc = mfma4(mA[a][0], v1 ? 0.0f : x, acc);
+          acc = mfma4(mA[a][1], v1 ? x : 0.0f, acc);
+        });
+        sfor<4>([&](auto n) { Z[n * PSO + s] = acc[(int)n]; });
+      });
+    } else if constexpr (CT::kind == K_EQ) {
       sfor<PTO>([&](auto a) {
         float ms[PTN];
         sfor<PTN>([&](auto n) {
@@ -309,7 +355,22 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     const QC q0 = qcoef(c, lb, swap, vi, ho, in_abs, out_abs, scl);
     QC q1 = qcoef(c, lb, swap, vi ^ 1, ho, in_abs, out_abs, scl);
     if (c.geo & GEO_BOT_EDGE) q1.cs = q1.cf = 0.0f;
-    if constexpr (CB::kind == K_EQ) {
+    if constexpr (CB::kind == K_EQ && PSN == 4) {
+      float mB[PSO][2];
+      sfor<PSO>([&](auto b) {
+        mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
+        mB[b][1] = lane_get(c.mbv, CB::idx(b, 1, 0) + (h & 3));
+      });
+      sfor<PTN>([&](auto n) {
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PSO>([&](auto b) {
+          const float z = Z[n * PSO + b], zf = xchg<2>(z);
+          acc = mfma4(mB[b][0], q0.cs * z + q0.cf * zf, acc);
+          acc = mfma4(mB[b][1], q1.cs * z + q1.cf * zf, acc);
+        });
+        sfor<4>([&](auto sp) { Y[n * PSN + sp] = acc[(int)sp]; });
+      });
+    } else if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
         sfor<PTN>([&](auto n) {
           const float z = Z[n * PSO + b], zf = xchg<2>(z);
@@ -337,7 +398,22 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     }
   } else {
     const bool v1 = !(c.geo & GEO_BOT_EDGE) && bit(h, 1);
-    if constexpr (CB::kind == K_EQ) {
+    if constexpr (CB::kind == K_EQ && PSN == 4) {
+      float mB[PSO][2];
+      sfor<PSO>([&](auto b) {
+        mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
+        mB[b][1] = lane_get(c.mbv, CB::idx(b, 1, 0) + (h & 3));
+      });
+      sfor<PTN>([&](auto n) {
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PSO>([&](auto b) {
+          const float z = Z[n * PSO + b];
+          acc = mfma4(mB[b][0], v1 ? 0.0f : z, acc);
+          acc = mfma4(mB[b][1], v1 ? z : 0.0f, acc);
+        });
+        sfor<4>([&](auto sp) { Y[n * PSN + sp] = acc[(int)sp]; });
+      });
+    } else if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
         float ms[PSN];
         sfor<PSN>([&](auto sp) {
