@@ -21,6 +21,24 @@ sys.path.insert(0, ROOT)
 METRIC = "syndromes decoded/s at d=17, chi=32 (1 GPU); agreement vs FP64 oracle"
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk (packed dual FMA)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "d17_p010_k6_chi32.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "sweep_kernel_d17_b4096_traffic.txt")
+
+
+def traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counter summary (each
+    scaled by what the counter reads for a 1 GiB copy), or None when no summary covers it or the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC):
+        return None
+    t = json.load(open(TRAFFIC))
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    k = t["kernels"].get(kernel)
+    if h.hexdigest() != t["source_sha256"] or k is None:
+        return None
+    return 1024.0 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"])
 
 
 def cpu_baseline(d, p, block, chi, max_iter):
@@ -122,6 +140,7 @@ def main():
     # dominant kernel: the sweep instantiation with the largest summed time
     cls, (dom_ms, dom_launches, dom_flops) = max(top.items(), key=lambda kv: kv[1][0])
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    kname = _lib.sweep_kernel_name(cls)
     all_achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
     iters = out["iters"].double().mean().item()
     line = dict(
@@ -133,8 +152,8 @@ def main():
                     d=d, p=p, batch=a.batch, block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
                     damping=0.1, parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None,
-                      kernel=_lib.sweep_kernel_name(cls), avg_launch_ms=dom_ms / max(dom_launches, 1),
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic(kname),
+                      kernel=kname, avg_launch_ms=dom_ms / max(dom_launches, 1),
                       flops_per_launch=dom_flops / max(dom_launches, 1), launches=dom_launches,
                       all_sweep_kernels=dict(achieved=all_achieved, frac=all_achieved / PEAK_FP32_TFLOPS,
                                              ms_per_step=upd_ms / a.steps, launches_per_step=launches / a.steps)),

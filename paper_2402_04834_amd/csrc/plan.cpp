@@ -247,30 +247,55 @@ int analyse_sweep(const Plan& p, const SweepDesc& s, Rng& rng) {
   return worst;
 }
 
+// Algorithmic flops of one block sweep in the check-pass-through formulation (a multiply-add counts 2):
+// per column, with PT / PS the top / bottom cap dimensions before (o) and after (n) the column and H the
+// crossing-bond configurations,
+//   end qubit (site 0 against the top cap, last site against the bottom cap): each emitted-bond value v
+//     the cap uses needs y_v = T(own) x + T(partner) x' (2 multiply-adds) per input entry -- both v for a
+//     cap that appends the bond or contracts the dense core, one for a cap that strips it (plus one add
+//     per output), only v = 0 without a cap;
+//   dense-core contraction (middle site of a side message): sum over (old cap index, v) per output entry,
+//     with both v for a qubit, the check's own v for a check;
+//   middle qubit: 2 multiply-adds per state entry; checks and the routing caps move data only.
+// The closing work (normalisation, damping and distance term, or the closing overlap) is 10 flops per
+// configuration. Normalisation inside the sweep (a range device) is not counted.
 double sweep_flops(const Plan& p, const SweepDesc& s) {
-  // algorithmic flops of the column passes of sweep.hpp: a qubit between two checks is a 2x2 transform
-  // (2 multiply-adds per state entry), a qubit at an end of the column also sums over the emitted cap leg
-  // (4 multiply-adds per entry), the middle site of a side message contracts the cap index (one
-  // multiply-add per old cap value), the normalisation costs 3 flops per entry; copies cost nothing
-  const int H = 1 << s.kp;
+  (void)p;
+  const int kt = s.kt, kp = s.kp, D = kt / 2;
+  const double H = (double)(1 << kp);
+  auto cdim = [](int K, int j) { return (double)(1 << std::min(j, K - j)); };
+  const bool top = s.msg_top >= 0, bot = s.msg_bot >= 0, q00 = (s.geo & GEO_Q00) != 0;
   double f = 0.0;
-  int Ps = 1;
-  for (int t = 0; t < s.kt; ++t) {
-    Column col;
-    make_column(col, s.frame, s.r0, s.c0, s.kr, s.kc, s.kt, s.kp, p.L, t, s.msg_top >= 0, s.msg_bot >= 0);
-    const double mid = (double)col.top.Pnew * H * Ps;
-    const double outn = (double)col.top.Pnew * H * col.bot.Pnew;
-    const bool teq = (col.top.kind == CAP_F_EQ || col.top.kind == CAP_B_EQ);
-    const bool beq = (col.bot.kind == CAP_F_EQ || col.bot.kind == CAP_B_EQ);
-    if (col.q0 || col.single) f += 8.0 * mid;
-    if (teq) f += 2.0 * col.top.Pold * mid * ((col.q0 || col.single) ? 2.0 : 1.0);
-    f += 4.0 * col.nmid * mid;
-    if (col.qlast && !col.single) f += 8.0 * outn;
-    if (beq) f += 2.0 * col.bot.Pold * outn * ((col.qlast || col.single) ? 2.0 : 1.0);
-    f += 3.0 * outn;
-    Ps = col.bot.Pnew;
+  for (int t = 0; t < kt; ++t) {
+    const bool q0 = q00 ^ (t & 1), ql = q0 ^ (((kp - 1) & 1) != 0);
+    const int kind = t < D ? 1 : (t == D ? 2 : 3);   // 1 append, 2 dense core, 3 strip
+    const double PTo = top ? cdim(kt, t) : 1, PTn = top ? cdim(kt, t + 1) : 1;
+    const double PSo = bot ? cdim(kt, t) : 1, PSn = bot ? cdim(kt, t + 1) : 1;
+    const double in = PTo * PSo * H, z = PTn * PSo * H, out = PTn * PSn * H;
+    // top cap + site 0
+    if (q0) {
+      if (!top) f += 4.0 * in;
+      else if (kind == 1) f += 8.0 * in;
+      else if (kind == 3) f += 4.0 * in + z;
+      else f += 8.0 * in + 4.0 * PTo * z;
+    } else if (top && kind == 2) {
+      f += 2.0 * PTo * z;
+    }
+    // middle qubits: positions 1 .. kp-2 of the qubit parity
+    int nmid = 0;
+    for (int i = 1; i <= kp - 2; ++i) nmid += (q0 ^ ((i & 1) != 0)) ? 1 : 0;
+    f += 4.0 * nmid * z;
+    // bottom cap + last site (for one position across, the single site counts once, at the top)
+    if (kp > 1 && ql) {
+      if (!bot) f += 4.0 * z;
+      else if (kind == 1) f += 8.0 * z;
+      else if (kind == 3) f += 4.0 * z + out;
+      else f += 8.0 * z + 4.0 * PSo * out;
+    } else if (bot && kind == 2) {
+      f += 2.0 * PSo * out;
+    }
   }
-  f += 10.0 * H;      // final normalisation, damping and distance term, or the closing overlap
+  f += 10.0 * H;
   return f;
 }
 
