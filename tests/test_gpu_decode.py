@@ -31,12 +31,12 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _gpu_decode(dev, d, p, syn, **kw):
+def _gpu_decode(dev, d, p, syn, messages=True, **kw):
     import torch
     import paper_2402_04834_amd as bbp
     opts = bbp.default_opts(**kw)
     st = torch.from_numpy(np.ascontiguousarray(syn)).to(dev)
-    out = bbp.decode_device(d, p, st, opts, messages=True)
+    out = bbp.decode_device(d, p, st, opts, messages=messages)
     torch.cuda.synchronize()
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items() if k != "workspace"}
 
@@ -71,6 +71,7 @@ def _decisions_agree(gpu_coset, ref_ll, ref_coset, ref_delta, delta1):
     (7, 0.12, 4, 16, 6, 0.5, 12),       # ragged 4x4 blocks ([4, 4, 4, 1]), damping 0.5
     (7, 0.08, 6, 32, 5, 0.1, 8),        # 6x6 blocks with a 1-wide remainder
     (9, 0.10, 6, 32, 4, 0.1, 4),        # 6x6 blocks with a 5-wide remainder, both caps of dimension 8
+    (11, 0.09, 6, 32, 3, 0.1, 2),       # 4x4 grid of blocks [6, 6, 6, 3]: every cap pattern of the d=17 workload
 ])
 def test_fixed_iterations_parity(dev, d, p, k, chi, iters, eta, count):
     _say(f"[parity] d={d} p={p} k={k} chi={chi} iters={iters} eta={eta} count={count}")
@@ -145,3 +146,34 @@ def test_batch_of_one_and_ragged_batches_are_independent(dev):
         one = _gpu_decode(dev, d, p, syn[i:i + 1], block=6, chi=32, max_iter=4)
         np.testing.assert_array_equal(one["loglik"][0], full["loglik"][i])
         np.testing.assert_array_equal(one["coset"][0], full["coset"][i])
+
+
+def test_full_size_d17_against_oracle_fixture(dev):
+    """The benchmark workload in the benchmark's launch configuration (d=17, p=0.10, 4096 syndromes, 6x6
+    blocks, chi=32, <= 20 iterations with early exit), checked on the syndromes of the committed oracle
+    fixture (tests/golden/d17_p010_k6_chi32.json, written by make_oracle_fixtures.py from oracle/ only)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "d17_p010_k6_chi32.json")
+    g = json.load(open(path))
+    meta = g["meta"]
+    assert (meta["d"], meta["block"], meta["chi"], meta["max_iter"]) == (17, 6, 32, 20)
+    _say(f"[full size] d=17 batch=4096, {len(g['records'])} oracle records")
+    _, syn = workload.make_batch(17, meta["p"], 4096, workload=meta["workload"], p_index=meta["p_index"])
+    got = _gpu_decode(dev, 17, meta["p"], syn, messages=False, block=6, chi=32, max_iter=20,
+                      damping=meta["eta"], delta0=meta["delta0"], delta1=meta["delta1"])
+    idx = np.array([r["index"] for r in g["records"]])
+    ref_ll = np.array([r["loglik"] for r in g["records"]])
+    ref_dl = np.array([r["delta"] for r in g["records"]])
+    ref_it = np.array([r["iters"] for r in g["records"]])
+    ref_cs = np.array([r["coset"] for r in g["records"]])
+    it, ll = got["iters"][idx], got["loglik"][idx]
+    near = np.abs(np.log(np.maximum(ref_dl, 1e-30) / meta["delta0"])) < 0.05
+    assert np.all((it == ref_it) | near)
+    same = (it == ref_it) & np.isfinite(ref_ll)
+    assert same.sum() >= 0.95 * same.size
+    np.testing.assert_array_less(np.abs(ll[same] - ref_ll[same]), _ll_tol(ref_ll[same]))
+    _decisions_agree(got["coset"][idx], ref_ll, ref_cs, ref_dl, meta["delta1"])
+    # every syndrome of the batch is decided, with a finite estimate for its decided coset
+    assert np.all(got["coset"] < 4)
+    assert np.all(np.isfinite(got["loglik"][np.arange(4096), got["coset"]]))
