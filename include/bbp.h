@@ -46,10 +46,13 @@ typedef struct bbp_opts {
   int32_t rule;         /* 0 = rule of Alg. 1 / remark 6, 1 = plain argmax of the Bethe estimates */
   int32_t fixed_iters;  /* 1 = always run max_iter iterations (no early exit) */
   int32_t precision;    /* 0 = FP32 block contractions (FP64 convergence distance and Bethe sums) */
-  int32_t reserved;     /* must be 0 */
+  int32_t graph;        /* 1 = capture the decode of a call into a HIP graph on first use and replay it on
+                           later calls with identical arguments (pointers, sizes, options, stream); needs a
+                           stream other than the default stream; ignored when timing is requested */
 } bbp_opts;
 
-/* Defaults of Sec. IV: 6x6 blocks, chi 16, 20 iterations, delta0 1e-4, delta1 1e-2, eta 0.1. */
+/* Defaults of Sec. IV: 6x6 blocks, chi 16, 20 iterations, delta0 1e-4, delta1 1e-2, eta 0.1; eager
+ * launches (graph 0). */
 void bbp_default_opts(bbp_opts* opts);
 
 /* Message for the calling thread's most recent non-zero return; never NULL. */
@@ -75,9 +78,11 @@ void bbp_free_network(bbp_net* net);
  * per coset, and the result of the plan-time rank analysis. `exact_sweeps` is 1 when no boundary MPS
  * inside any block update can exceed bond chi for any input, so that truncation is the identity and the
  * GPU contracts blocks exactly; `flops_per_iter` / `flops_bethe` are the algorithmic FP32 flops of one
- * coset-iteration / of the Bethe sweeps of one coset (qubit tensors 8 flops per output entry, data cap
- * sites 2 per multiply-add, normalisation 2 per entry; copies of COPY tensors and identity cap sites
- * count zero). Errors: BBP_EINVAL for invalid opts.
+ * coset-iteration / of the Bethe sweeps of one coset: the multiply-adds (2 flops each) of the block
+ * contractions -- qubit tensors against their partner configuration and the emitted side-message bonds
+ * they use, and the contractions with the dense middle site of every side message; COPY tensors and the
+ * side-message sites that only route a bond count zero -- plus 10 flops per configuration for the closing
+ * normalisation, damping and distance term. Errors: BBP_EINVAL for invalid opts.
  */
 typedef struct bbp_plan_info {
   int32_t L, n, m;
@@ -138,9 +143,53 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
                       double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
                       uint8_t* correction_dev, float* messages_dev, void* stream, bbp_timing* timing);
 
-/* Host convenience: decode host-side networks (all of one d and p) and return host outputs with the
- * same layouts as bbp_decode_device (correction rows of n bytes). Allocates and frees its own device
- * memory and synchronises. Errors as above. */
+/* ---------------------------------------------------------------------------------------------------
+ * Mixed batches. A group is a batch of syndromes of one distance d and noise rate p, resident in device
+ * memory, with the device arrays that receive its results (layouts as in bbp_decode_device). One call
+ * decodes up to 8 groups together: every colour round launches each block-sweep class once over all
+ * groups, so a mix of distances costs no more launches than its largest member.
+ */
+typedef struct bbp_group {
+  int32_t d;
+  double p;
+  const uint8_t* syndromes_dev;   /* [batch][2d(d-1)] */
+  int64_t batch;
+  double* loglik_dev;             /* [batch][4] */
+  double* delta_dev;              /* [batch][4] */
+  int32_t* iters_dev;             /* [batch][4] */
+  uint8_t* coset_dev;             /* [batch] */
+  uint8_t* correction_dev;        /* [batch][d^2 + (d-1)^2] */
+} bbp_group;
+
+/* Workspace for bbp_decode_groups (the groups' own workspaces laid end to end). Output and syndrome
+ * pointers are not read. Errors: BBP_EINVAL (ngroups outside [1, 8], invalid d, p, batch or opts). */
+int bbp_workspace_size_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, size_t* bytes);
+
+/* Whole decoder (Alg. 1) on the groups, with the semantics of bbp_decode_device per group (results are
+ * identical to decoding each group alone). Errors as bbp_decode_device. */
+int bbp_decode_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, void* workspace,
+                      size_t workspace_bytes, void* stream, bbp_timing* timing);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Launch tuning. The block sweeps of a round can be enqueued with the items of a launch in sweep-major
+ * or job-major order, and spread over 1, 2 or 4 streams (a round's launches are independent). Results do
+ * not depend on the choice. bbp_autotune times every variant on the given batch (a warm-up and two
+ * timed decodes each, on `stream`; it allocates and frees a small device output buffer), keeps the
+ * fastest for (d, block size, chi) on the current device, and returns it; later decodes of that key use
+ * it. bbp_set_tuning sets it directly. Errors: BBP_EINVAL, BBP_ENOMEM, BBP_EHIP. */
+typedef struct bbp_tuning {
+  int32_t order;     /* 0 sweep-major, 1 job-major */
+  int32_t streams;   /* 1, 2 or 4 */
+  double ms;         /* decode time of the chosen variant on the tuning batch (output of bbp_autotune) */
+} bbp_tuning;
+int bbp_autotune(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch, const bbp_opts* opts,
+                 void* workspace, size_t workspace_bytes, void* stream, bbp_tuning* best);
+int bbp_set_tuning(int32_t d, const bbp_opts* opts, const bbp_tuning* tuning);
+
+/* Host convenience: decode host-side networks (up to 8 distinct (d, p) in one call, in any order) and
+ * return host outputs in input order with the layouts of bbp_decode_device; correction rows are n_max
+ * bytes, n_max the largest qubit count in the call, the first n(d) of each row used and the rest 0.
+ * Allocates and frees its own device memory and synchronises. Errors as above. */
 int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts, double* loglik,
                        double* delta, int32_t* iters, uint8_t* coset, uint8_t* correction);
 

@@ -11,10 +11,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BbpError, bbp_opts, bbp_plan_info, bbp_timing, default_opts
+from ._lib import BbpError, bbp_group, bbp_opts, bbp_plan_info, bbp_timing, bbp_tuning, default_opts
 
-__all__ = ["default_opts", "plan_query", "build_network", "workspace_size", "decode_device", "blockbp_decode",
-           "reference_update_host", "BbpError", "bbp_opts", "bbp_timing"]
+__all__ = ["default_opts", "plan_query", "build_network", "workspace_size", "decode_device", "decode_groups",
+           "autotune", "set_tuning", "blockbp_decode", "reference_update_host", "BbpError", "bbp_opts",
+           "bbp_timing", "bbp_tuning"]
 
 
 def plan_query(d: int, opts: bbp_opts) -> bbp_plan_info:
@@ -60,12 +61,24 @@ def workspace_size(d: int, batch: int, opts: bbp_opts) -> int:
     return n.value
 
 
+def _outputs(batch, n, dev):
+    import torch
+    return dict(
+        loglik=torch.empty((batch, 4), dtype=torch.float64, device=dev),
+        delta=torch.empty((batch, 4), dtype=torch.float64, device=dev),
+        iters=torch.empty((batch, 4), dtype=torch.int32, device=dev),
+        coset=torch.empty((batch,), dtype=torch.uint8, device=dev),
+        correction=torch.empty((batch, n), dtype=torch.uint8, device=dev),
+    )
+
+
 def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None, messages: bool = False,
-                  timing: bool = False, stream=None):
+                  timing: bool = False, stream=None, out=None):
     """Decode a batch of syndromes held in a torch uint8 CUDA tensor [batch, m].
     Returns a dict of torch tensors on the same device (loglik, delta, iters, coset, correction and
     optionally messages) plus a bbp_timing when requested. Work is enqueued on torch's current stream
-    (or `stream`)."""
+    (or `stream`). `out` (a dict returned by an earlier call of the same shape) receives the results in
+    place, which keeps the arguments of a graph-mode decode identical between calls."""
     import torch
 
     assert syndromes.is_cuda and syndromes.dtype == torch.uint8 and syndromes.dim() == 2
@@ -76,13 +89,11 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     ws_bytes = workspace_size(d, batch, opts)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
-    out = dict(
-        loglik=torch.empty((batch, 4), dtype=torch.float64, device=dev),
-        delta=torch.empty((batch, 4), dtype=torch.float64, device=dev),
-        iters=torch.empty((batch, 4), dtype=torch.int32, device=dev),
-        coset=torch.empty((batch,), dtype=torch.uint8, device=dev),
-        correction=torch.empty((batch, n), dtype=torch.uint8, device=dev),
-    )
+    if out is None:
+        out = _outputs(batch, n, dev)
+    else:
+        assert out["loglik"].shape == (batch, 4) and out["correction"].shape == (batch, n)
+        out = {k: v for k, v in out.items() if k in ("loglik", "delta", "iters", "coset", "correction")}
     msg_ptr = None
     if messages:
         M = plan_query(d, opts).num_messages
@@ -100,10 +111,61 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     return out
 
 
+def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None):
+    """Decode a mixed batch: `groups` is a list of (d, p, syndromes) with syndromes a torch uint8 CUDA
+    tensor [batch, 2d(d-1)]. Returns (list of per-group output dicts as in decode_device, workspace,
+    bbp_timing or None)."""
+    import torch
+
+    gs = (bbp_group * len(groups))()
+    outs, keep = [], []
+    dev = None
+    for k, (d, p, syn) in enumerate(groups):
+        assert syn.is_cuda and syn.dtype == torch.uint8 and syn.dim() == 2
+        syn = syn.contiguous()
+        keep.append(syn)
+        dev = syn.device
+        b = syn.shape[0]
+        o = _outputs(b, d * d + (d - 1) * (d - 1), dev)
+        outs.append(o)
+        gs[k] = bbp_group(d, p, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),
+                          o["iters"].data_ptr(), o["coset"].data_ptr(), o["correction"].data_ptr())
+    n = C.c_size_t()
+    _lib.check(_lib.lib().bbp_workspace_size_groups(gs, len(groups), C.byref(opts), C.byref(n)))
+    if workspace is None or workspace.numel() < n.value:
+        workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    tm = bbp_timing() if timing else None
+    _lib.check(_lib.lib().bbp_decode_groups(gs, len(groups), C.byref(opts), workspace.data_ptr(),
+                                            workspace.numel(), st, C.byref(tm) if tm is not None else None))
+    return outs, workspace, tm
+
+
+def autotune(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None, stream=None) -> bbp_tuning:
+    """Time the launch variants of the block sweeps on this batch and keep the fastest for (d, opts)."""
+    import torch
+
+    syndromes = syndromes.contiguous()
+    ws_bytes = workspace_size(d, syndromes.shape[0], opts)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=syndromes.device)
+    st = (stream if stream is not None else torch.cuda.current_stream(syndromes.device)).cuda_stream
+    best = bbp_tuning()
+    _lib.check(_lib.lib().bbp_autotune(d, p, syndromes.data_ptr(), syndromes.shape[0], C.byref(opts),
+                                       workspace.data_ptr(), workspace.numel(), st, C.byref(best)))
+    return best
+
+
+def set_tuning(d: int, opts: bbp_opts, order: int, streams: int) -> None:
+    t = bbp_tuning(order, streams, 0.0)
+    _lib.check(_lib.lib().bbp_set_tuning(d, C.byref(opts), C.byref(t)))
+
+
 def blockbp_decode(nets, opts: bbp_opts):
-    """Host convenience: decode a list of Network objects (same d and p); returns numpy outputs."""
+    """Host convenience: decode a list of Network objects (up to 8 distinct (d, p), any order); returns
+    numpy outputs in input order, correction rows of the largest qubit count."""
     batch = len(nets)
-    d, n, _ = nets[0].dims()
+    n = max(x.dims()[1] for x in nets)
     arr = (C.c_void_p * batch)(*[x.handle.value for x in nets])
     ll = np.zeros((batch, 4)); dl = np.zeros((batch, 4)); it = np.zeros((batch, 4), dtype=np.int32)
     cs = np.zeros(batch, dtype=np.uint8); corr = np.zeros((batch, n), dtype=np.uint8)

@@ -22,8 +22,20 @@ class bbp_opts(C.Structure):
     _fields_ = [
         ("block_rows", C.c_int32), ("block_cols", C.c_int32), ("chi", C.c_int32), ("max_iter", C.c_int32),
         ("delta0", C.c_double), ("delta1", C.c_double), ("damping", C.c_double),
-        ("rule", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+        ("rule", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
     ]
+
+
+class bbp_group(C.Structure):
+    _fields_ = [
+        ("d", C.c_int32), ("p", C.c_double), ("syndromes_dev", C.c_void_p), ("batch", C.c_int64),
+        ("loglik_dev", C.c_void_p), ("delta_dev", C.c_void_p), ("iters_dev", C.c_void_p),
+        ("coset_dev", C.c_void_p), ("correction_dev", C.c_void_p),
+    ]
+
+
+class bbp_tuning(C.Structure):
+    _fields_ = [("order", C.c_int32), ("streams", C.c_int32), ("ms", C.c_double)]
 
 
 class bbp_plan_info(C.Structure):
@@ -64,6 +76,13 @@ SIGNATURES = {
     "bbp_decode_device": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(bbp_timing)]),
+    "bbp_workspace_size_groups": (C.c_int, [C.POINTER(bbp_group), C.c_int32, C.POINTER(bbp_opts),
+                                            C.POINTER(C.c_size_t)]),
+    "bbp_decode_groups": (C.c_int, [C.POINTER(bbp_group), C.c_int32, C.POINTER(bbp_opts), C.c_void_p, C.c_size_t,
+                                    C.c_void_p, C.POINTER(bbp_timing)]),
+    "bbp_autotune": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(bbp_opts), C.c_void_p,
+                               C.c_size_t, C.c_void_p, C.POINTER(bbp_tuning)]),
+    "bbp_set_tuning": (C.c_int, [C.c_int32, C.POINTER(bbp_opts), C.POINTER(bbp_tuning)]),
     "bbp_blockbp_decode": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bbp_opts), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "bbp_reference_update_host": (C.c_int, [C.c_int32, C.c_double, C.POINTER(bbp_opts), C.c_void_p, C.c_int32,

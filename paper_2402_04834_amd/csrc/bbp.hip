@@ -221,9 +221,9 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
 
 }  // namespace
 
-hipError_t bbp::launch_sweeps(int cls, unsigned count, hipStream_t st, const SweepArgs& a) {
+hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
   const int variant = cls & 15, kt = (cls >> 4) + 1;
-  const dim3 grid(sweep_groups(a.jobs), count);
+  const dim3 grid(sweep_groups(a.items));
   switch (kt) {
     case 1: return launch_sweeps_k1(variant, grid, st, a);
     case 2: return launch_sweeps_k2(variant, grid, st, a);
@@ -260,6 +260,7 @@ int validate(int32_t d, const bbp_opts* o) {
   if (!(o->damping >= 0.0 && o->damping < 1.0)) return fail(BBP_EINVAL, "damping must be in [0, 1)");
   if (o->rule != 0 && o->rule != 1) return fail(BBP_EINVAL, "rule must be 0 or 1");
   if (o->precision != 0) return fail(BBP_EUNSUPPORTED, "only precision 0 (FP32) is implemented");
+  if (o->graph != 0 && o->graph != 1) return fail(BBP_EINVAL, "graph must be 0 or 1");
   return BBP_OK;
 }
 
@@ -332,6 +333,388 @@ struct Bbp_net_impl {
   std::vector<uint8_t> labels;   // [4][L*L]
 };
 
+// ------------------------------------------------------------------------------------------------
+// Decode of a list of (d, p) groups: every sweep class of a colour round is one launch over all groups.
+
+// Runtime launch variant, chosen by bbp_autotune per (d, blocks, chi, device).
+struct Tune {
+  int order = 0;     // item order inside a launch (SweepArgs::order)
+  int streams = 1;   // streams over which a round's class launches are spread (1, 2 or 4)
+};
+std::map<std::tuple<int, int, int, int, int>, Tune> g_tune;
+
+// Per-device auxiliary streams (default priority) and the events that fork and join them.
+struct Aux {
+  hipStream_t s[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+};
+std::map<int, Aux> g_aux;
+
+int aux_for(int dev, Aux** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_aux.find(dev);
+  if (it == g_aux.end()) {
+    Aux a;
+    for (int i = 0; i < 3; ++i) {
+      HIP_TRY(hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+    it = g_aux.emplace(dev, a).first;
+  }
+  *out = &it->second;
+  return BBP_OK;
+}
+
+struct GroupRun {
+  bbp_group in;
+  DevPlan* dp = nullptr;
+  Layout lay;
+  size_t off = 0;
+  uint8_t* labels = nullptr;
+  float* msgs = nullptr;
+  double *terms = nullptr, *lnw = nullptr, *delta = nullptr;
+  int32_t *conv = nullptr, *iters = nullptr;
+  int64_t jobs = 0;
+};
+
+// Validate the groups, fetch their plans and lay their state out in one workspace.
+int resolve(const bbp_group* groups, int ng, const bbp_opts* opts, std::vector<GroupRun>& gr, size_t* total,
+            bool need_plans) {
+  if (ng < 1 || ng > bbp::MAX_GROUPS) return fail(BBP_EINVAL, "the number of groups must be in [1, 8]");
+  if (!groups) return fail(BBP_EINVAL, "groups is NULL");
+  gr.assign((size_t)ng, GroupRun());
+  size_t off = 0;
+  for (int g = 0; g < ng; ++g) {
+    const bbp_group& G = groups[g];
+    int rc = validate(G.d, opts);
+    if (rc) return rc;
+    if (!(G.p > 0.0 && G.p < 1.0)) return fail(BBP_EINVAL, "p must be in (0, 1)");
+    if (G.batch < 0) return fail(BBP_EINVAL, "batch must be >= 0");
+    if (G.batch > (int64_t)1 << 24) return fail(BBP_EINVAL, "batch too large");
+    gr[g].in = G;
+    gr[g].lay = layout(host_plan(G.d, opts), G.batch);
+    gr[g].off = off;
+    off = align256(off + gr[g].lay.total);
+    gr[g].jobs = 4 * G.batch;
+    if (need_plans) {
+      if ((rc = device_plan(G.d, opts, &gr[g].dp))) return rc;
+      if (!gr[g].dp->plan.gpu_ok) return fail(BBP_EUNSUPPORTED, gr[g].dp->plan.why);
+    }
+  }
+  *total = off;
+  return BBP_OK;
+}
+
+// Timing events, reused across calls (creating two events per launch would slow the enqueue).
+std::map<int, std::vector<hipEvent_t>> g_events;
+
+int timing_event(int dev, size_t i, hipEvent_t* e) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto& v = g_events[dev];
+  while (v.size() <= i) {
+    hipEvent_t x;
+    HIP_TRY(hipEventCreate(&x));
+    v.push_back(x);
+  }
+  *e = v[i];
+  return BBP_OK;
+}
+
+// Per-launch timing record (timing mode only).
+struct Mark {
+  hipEvent_t a, b;
+  int kind;               // 0 other, 1 BP-round sweeps, 2 closing sweeps
+  int it, cls;
+  std::vector<std::pair<int, double>> work;   // (group, per-job flops of the group's sweeps of this class)
+};
+
+// Enqueue the whole decode of the groups on st (and the auxiliary streams of the tune).
+int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, float* messages_dev, hipStream_t st,
+            Aux* aux, std::vector<Mark>* marks) {
+  const int ng = (int)gr.size();
+  // consecutive launches on one stream share their boundary event (an event record is a queue packet)
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  size_t nev = 0;
+  hipEvent_t prev_end = nullptr;
+  hipStream_t prev_stream = nullptr;
+  auto begin_mark = [&](hipStream_t s, int kind, int it, int cls) -> int {
+    if (!marks) return BBP_OK;
+    Mark m;
+    m.kind = kind;
+    m.it = it;
+    m.cls = cls;
+    int rc2;
+    if (prev_end && s == prev_stream) {
+      m.a = prev_end;
+    } else {
+      if ((rc2 = timing_event(dev, nev++, &m.a))) return rc2;
+      HIP_TRY(hipEventRecord(m.a, s));
+    }
+    if ((rc2 = timing_event(dev, nev++, &m.b))) return rc2;
+    marks->push_back(m);
+    return BBP_OK;
+  };
+  auto end_mark = [&](hipStream_t s) -> int {
+    if (!marks) return BBP_OK;
+    HIP_TRY(hipEventRecord(marks->back().b, s));
+    prev_end = marks->back().b;
+    prev_stream = s;
+    return BBP_OK;
+  };
+  int rc;
+  for (auto& g : gr) {
+    if (g.in.batch == 0) continue;
+    if ((rc = begin_mark(st, 0, -1, -1))) return rc;
+    labels_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(g.in.syndromes_dev, g.in.d, g.in.batch, g.labels);
+    init_kernel<<<dim3((unsigned)g.jobs), dim3(256), 0, st>>>(g.msgs, g.dp->edge_len, g.dp->plan.M, g.jobs, g.conv,
+                                                              g.iters);
+    HIP_TRY(hipGetLastError());
+    if ((rc = end_mark(st))) return rc;
+  }
+  const int S = std::max(1, std::min(tn.streams, 4));
+  auto streams_of = [&](int i) -> hipStream_t { return (i % S) == 0 ? st : aux->s[(i % S) - 1]; };
+  // one colour round (list 0 / 1) or the closing sweeps (list 2): one launch per class over all groups
+  auto round = [&](int list, int it) -> int {
+    std::map<int, std::vector<std::pair<int, const ClassRun*>>> cls;
+    for (int g = 0; g < ng; ++g)
+      if (gr[g].in.batch > 0)
+        for (const ClassRun& r : gr[g].dp->runs[list]) cls[r.cls].push_back({g, &r});
+    if (cls.empty()) return BBP_OK;
+    // largest launches first, so that the small ones fill in behind them
+    std::vector<std::pair<double, int>> order;
+    for (auto& kv : cls) {
+      double w = 0.0;
+      for (auto& gr_r : kv.second) w += (double)gr[gr_r.first].jobs * gr_r.second->flops;
+      order.push_back({-w, kv.first});
+    }
+    std::sort(order.begin(), order.end());
+    if (S > 1) {
+      HIP_TRY(hipEventRecord(aux->fork, st));
+      for (int i = 1; i < S; ++i) HIP_TRY(hipStreamWaitEvent(aux->s[i - 1], aux->fork, 0));
+    }
+    for (size_t li = 0; li < order.size(); ++li) {
+      const int c = order[li].second;
+      const auto& members = cls[c];
+      bbp::SweepArgs sa;
+      std::memset(&sa, 0, sizeof(sa));
+      sa.ngroups = (int)members.size();
+      sa.mode = (list == 2) ? 1 : 0;
+      sa.order = tn.order;
+      sa.eta = (float)opts->damping;
+      int64_t items = 0;
+      for (int k = 0; k < sa.ngroups; ++k) {
+        const GroupRun& g = gr[members[k].first];
+        const ClassRun& r = *members[k].second;
+        bbp::SweepGroup& G = sa.g[k];
+        G.sweeps = ((list == 2) ? g.dp->bethe : g.dp->round[list]) + r.first;
+        G.labels = g.labels;
+        G.msgs = g.msgs;
+        G.terms = g.terms;
+        G.conv = g.conv;
+        G.lnW = g.lnw;
+        G.jobs = g.jobs;
+        G.item0 = items;
+        G.count = r.count;
+        G.d = g.in.d;
+        G.M = g.dp->plan.M;
+        G.nblocks = g.dp->plan.nblocks;
+        G.p00 = 1.0f - (float)g.in.p;
+        G.pe = (float)g.in.p / 3.0f;
+        items += g.jobs * (int64_t)r.count;
+      }
+      sa.items = items;
+      hipStream_t s = streams_of((int)li);
+      if ((rc = begin_mark(s, list == 2 ? 2 : 1, it, c))) return rc;
+      if (marks)
+        for (auto& m : members) marks->back().work.push_back({m.first, m.second->flops});
+      HIP_TRY(bbp::launch_sweeps(c, s, sa));
+      if ((rc = end_mark(s))) return rc;
+    }
+    if (S > 1) {
+      for (int i = 1; i < S; ++i) {
+        HIP_TRY(hipEventRecord(aux->join[i - 1], aux->s[i - 1]));
+        HIP_TRY(hipStreamWaitEvent(st, aux->join[i - 1], 0));
+      }
+      prev_end = nullptr;
+    }
+    return BBP_OK;
+  };
+  for (int it = 0; it < opts->max_iter; ++it) {
+    for (int c = 0; c < 2; ++c)
+      if ((rc = round(c, it))) return rc;
+    for (auto& g : gr) {
+      if (g.in.batch == 0) continue;
+      if ((rc = begin_mark(st, 0, it, -1))) return rc;
+      delta_kernel<<<dim3((unsigned)((g.jobs + 255) / 256)), dim3(256), 0, st>>>(
+          g.terms, g.dp->plan.M, g.jobs, g.conv, g.iters, g.delta, opts->delta0, opts->fixed_iters);
+      HIP_TRY(hipGetLastError());
+      if ((rc = end_mark(st))) return rc;
+    }
+  }
+  if ((rc = round(2, opts->max_iter))) return rc;
+  for (auto& g : gr) {
+    if (g.in.batch == 0) continue;
+    const bbp::Plan& P = g.dp->plan;
+    if ((rc = begin_mark(st, 0, -1, -1))) return rc;
+    finalize_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(
+        g.lnw, P.nblocks, g.msgs, P.M, g.dp->pairs, (int)(P.pair_ids.size() / 2), g.labels, g.in.d, g.delta, g.iters,
+        opts->delta1, opts->rule, g.in.loglik_dev, g.in.delta_dev, g.in.iters_dev, g.in.coset_dev,
+        g.in.correction_dev);
+    HIP_TRY(hipGetLastError());
+    if ((rc = end_mark(st))) return rc;
+  }
+  if (messages_dev)
+    HIP_TRY(hipMemcpyAsync(messages_dev, gr[0].msgs, (size_t)gr[0].jobs * gr[0].dp->plan.M * MSTRIDE * sizeof(float),
+                           hipMemcpyDeviceToDevice, st));
+  return BBP_OK;
+}
+
+// Fill `timing` from the marks of a finished decode.
+int collect_timing(std::vector<GroupRun>& gr, const bbp_opts* opts, std::vector<Mark>& marks, bbp_timing* timing) {
+  std::memset(timing, 0, sizeof(*timing));
+  // flops actually executed: a job runs the updates of iteration `it` iff it ran more than `it` iterations
+  std::vector<std::vector<double>> active(gr.size());
+  for (size_t g = 0; g < gr.size(); ++g) {
+    active[g].assign((size_t)opts->max_iter + 1, 0.0);
+    if (gr[g].in.batch == 0) continue;
+    std::vector<int32_t> it_host((size_t)gr[g].jobs);
+    HIP_TRY(hipMemcpy(it_host.data(), gr[g].iters, sizeof(int32_t) * gr[g].jobs, hipMemcpyDeviceToHost));
+    for (auto v : it_host) active[g][std::min<int32_t>(std::max<int32_t>(v, 0), opts->max_iter)] += 1.0;
+    for (int k = opts->max_iter - 1; k >= 0; --k) active[g][k] += active[g][k + 1];   // jobs with iters >= k
+  }
+  std::map<int, std::tuple<double, int, double>> per_class;   // class -> (ms, launches, flops)
+  for (auto& m : marks) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b));
+    if (m.kind == 1) {
+      double fl = 0.0;
+      for (auto& w : m.work) fl += active[w.first][m.it + 1] * w.second;
+      timing->update_ms += ms;
+      timing->update_launches += 1;
+      timing->update_flops += fl;
+      auto& pc = per_class[m.cls];
+      std::get<0>(pc) += ms;
+      std::get<1>(pc) += 1;
+      std::get<2>(pc) += fl;
+    } else if (m.kind == 2) {
+      timing->bethe_ms += ms;
+    } else {
+      timing->other_ms += ms;
+    }
+  }
+  timing->top_class = -1;
+  for (auto& kv : per_class)
+    if (std::get<0>(kv.second) > timing->top_ms) {
+      timing->top_class = kv.first;
+      timing->top_ms = std::get<0>(kv.second);
+      timing->top_launches = std::get<1>(kv.second);
+      timing->top_flops = std::get<2>(kv.second);
+    }
+  return BBP_OK;
+}
+
+// Instantiated graphs of whole decodes, keyed by every argument that the captured work depends on.
+std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
+
+template <class T>
+uint64_t u64(T v) {
+  uint64_t r = 0;
+  std::memcpy(&r, &v, std::min(sizeof(T), sizeof(r)));
+  return r;
+}
+
+int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* workspace, size_t workspace_bytes,
+                  float* messages_dev, void* stream, bbp_timing* timing, const Tune* force) {
+  std::vector<GroupRun> gr;
+  size_t total = 0;
+  int rc = resolve(groups, ng, opts, gr, &total, true);
+  if (rc) return rc;
+  if (total > 0 && !workspace) return fail(BBP_EINVAL, "workspace is NULL");
+  if (workspace_bytes < total) return fail(BBP_EINVAL, "workspace too small");
+  bool any = false;
+  for (auto& g : gr) {
+    if (g.in.batch == 0) continue;
+    any = true;
+    if (!g.in.syndromes_dev || !g.in.loglik_dev || !g.in.delta_dev || !g.in.iters_dev || !g.in.coset_dev ||
+        !g.in.correction_dev)
+      return fail(BBP_EINVAL, "a required pointer is NULL");
+    char* ws = (char*)workspace + g.off;
+    g.labels = (uint8_t*)(ws + g.lay.labels);
+    g.msgs = (float*)(ws + g.lay.msgs);
+    g.terms = (double*)(ws + g.lay.terms);
+    g.lnw = (double*)(ws + g.lay.lnw);
+    g.conv = (int32_t*)(ws + g.lay.conv);
+    g.iters = (int32_t*)(ws + g.lay.iters);
+    g.delta = (double*)(ws + g.lay.delta);
+  }
+  if (!any) return BBP_OK;
+  if (messages_dev && (ng != 1)) return fail(BBP_EINVAL, "messages are returned for one group only");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Tune tn;
+  if (force) {
+    tn = *force;
+  } else {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune.find(std::make_tuple(gr[0].in.d, opts->block_rows, opts->block_cols, opts->chi, dev));
+    if (it != g_tune.end()) tn = it->second;
+  }
+  Aux* aux = nullptr;
+  if (tn.streams > 1 && (rc = aux_for(dev, &aux))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+
+  if (timing) {
+    std::vector<Mark> marks;
+    rc = enqueue(gr, opts, tn, messages_dev, st, aux, &marks);
+    if (rc == BBP_OK) {
+      if (hipStreamSynchronize(st) != hipSuccess) rc = fail(BBP_EHIP, "stream synchronisation failed");
+      else rc = collect_timing(gr, opts, marks, timing);
+    }
+    return rc;
+  }
+  if (!opts->graph) return enqueue(gr, opts, tn, messages_dev, st, aux, nullptr);
+
+  // graph mode: capture the decode once per argument set, replay it afterwards
+  if (!st) return fail(BBP_EINVAL, "graph mode needs a stream other than the default stream");
+  std::vector<uint64_t> key = {(uint64_t)dev, (uint64_t)ng, u64(workspace), (uint64_t)workspace_bytes,
+                               u64(messages_dev), u64(st), (uint64_t)tn.order, (uint64_t)tn.streams};
+  const bbp_opts o = *opts;
+  key.insert(key.end(), {(uint64_t)o.block_rows, (uint64_t)o.block_cols, (uint64_t)o.chi, (uint64_t)o.max_iter,
+                         u64(o.delta0), u64(o.delta1), u64(o.damping), (uint64_t)o.rule, (uint64_t)o.fixed_iters,
+                         (uint64_t)o.precision});
+  for (auto& g : gr)
+    key.insert(key.end(), {(uint64_t)g.in.d, u64(g.in.p), u64(g.in.syndromes_dev), (uint64_t)g.in.batch,
+                           u64(g.in.loglik_dev), u64(g.in.delta_dev), u64(g.in.iters_dev), u64(g.in.coset_dev),
+                           u64(g.in.correction_dev)});
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(gr, opts, tn, messages_dev, st, aux, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(BBP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(BBP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_graphs[key] = exec;
+  }
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return BBP_OK;
+}
+
 }  // namespace
 
 struct bbp_net {
@@ -353,6 +736,7 @@ void bbp_default_opts(bbp_opts* o) {
   o->rule = 0;
   o->fixed_iters = 0;
   o->precision = 0;
+  o->graph = 0;
 }
 
 const char* bbp_last_error(void) { return g_err.c_str(); }
@@ -438,193 +822,205 @@ int bbp_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* b
   return BBP_OK;
 }
 
+int bbp_workspace_size_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(BBP_EINVAL, "bytes is NULL");
+  std::vector<GroupRun> gr;
+  return resolve(groups, ngroups, opts, gr, bytes, false);
+}
+
+int bbp_decode_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, void* workspace,
+                      size_t workspace_bytes, void* stream, bbp_timing* timing) {
+  return decode_groups(groups, ngroups, opts, workspace, workspace_bytes, nullptr, stream, timing, nullptr);
+}
+
 int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch, const bbp_opts* opts,
                       void* workspace, size_t workspace_bytes, double* loglik_dev, double* delta_dev,
                       int32_t* iters_dev, uint8_t* coset_dev, uint8_t* correction_dev, float* messages_dev,
                       void* stream, bbp_timing* timing) {
+  bbp_group g;
+  g.d = d;
+  g.p = p;
+  g.syndromes_dev = syndromes_dev;
+  g.batch = batch;
+  g.loglik_dev = loglik_dev;
+  g.delta_dev = delta_dev;
+  g.iters_dev = iters_dev;
+  g.coset_dev = coset_dev;
+  g.correction_dev = correction_dev;
+  return decode_groups(&g, 1, opts, workspace, workspace_bytes, messages_dev, stream, timing, nullptr);
+}
+
+int bbp_set_tuning(int32_t d, const bbp_opts* opts, const bbp_tuning* t) {
   int rc = validate(d, opts);
   if (rc) return rc;
-  if (!(p > 0.0 && p < 1.0)) return fail(BBP_EINVAL, "p must be in (0, 1)");
-  if (batch < 0) return fail(BBP_EINVAL, "batch must be >= 0");
-  if (batch == 0) return BBP_OK;
-  if (batch > (int64_t)1 << 24) return fail(BBP_EINVAL, "batch too large");
-  if (!syndromes_dev || !workspace || !loglik_dev || !delta_dev || !iters_dev || !coset_dev || !correction_dev)
-    return fail(BBP_EINVAL, "a required pointer is NULL");
-  DevPlan* dp = nullptr;
-  rc = device_plan(d, opts, &dp);
-  if (rc) return rc;
-  const bbp::Plan& P = dp->plan;
-  if (!P.gpu_ok) return fail(BBP_EUNSUPPORTED, P.why);
-  const Layout lay = layout(P, batch);
-  if (workspace_bytes < lay.total) return fail(BBP_EINVAL, "workspace too small");
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  uint8_t* labels = (uint8_t*)(ws + lay.labels);
-  float* msgs = (float*)(ws + lay.msgs);
-  double* terms = (double*)(ws + lay.terms);
-  double* lnw = (double*)(ws + lay.lnw);
-  int32_t* conv = (int32_t*)(ws + lay.conv);
-  int32_t* iters = (int32_t*)(ws + lay.iters);
-  double* delta = (double*)(ws + lay.delta);
-  const int64_t jobs = batch * 4;
-  const float eps = (float)p;
-  const float pi0 = 1.0f - eps, pe = eps / 3.0f;
-
-  std::vector<hipEvent_t> evs;
-  auto mark = [&]() -> int {
-    if (!timing) return BBP_OK;
-    hipEvent_t e;
-    HIP_TRY(hipEventCreate(&e));
-    HIP_TRY(hipEventRecord(e, st));
-    evs.push_back(e);
-    return BBP_OK;
-  };
-  std::vector<int> kinds;   // kind of the interval ending at each mark: 0 other, 1 update, 2 bethe
-
-  if ((rc = mark())) return rc;
-  labels_kernel<<<dim3((unsigned)batch), dim3(256), 0, st>>>(syndromes_dev, d, batch, labels);
-  init_kernel<<<dim3((unsigned)jobs), dim3(256), 0, st>>>(msgs, dp->edge_len, P.M, jobs, conv, iters);
-  HIP_TRY(hipGetLastError());
-  if ((rc = mark())) return rc;
-  kinds.push_back(0);
-  bbp::SweepArgs sa;
-  sa.d = d;
-  sa.labels = labels;
-  sa.msgs = msgs;
-  sa.M = P.M;
-  sa.terms = terms;
-  sa.conv = conv;
-  sa.p00 = pi0;
-  sa.pe = pe;
-  sa.eta = (float)opts->damping;
-  sa.lnW = lnw;
-  sa.nblocks = P.nblocks;
-  sa.jobs = jobs;
-  std::vector<std::pair<int, const ClassRun*>> upd;   // (iteration, run) of each update interval
-  for (int it = 0; it < opts->max_iter; ++it) {
-    for (int c = 0; c < 2; ++c) {
-      for (const ClassRun& r : dp->runs[c]) {
-        sa.sweeps = dp->round[c] + r.first;
-        sa.mode = 0;
-        HIP_TRY(bbp::launch_sweeps(r.cls, (unsigned)r.count, st, sa));
-        if ((rc = mark())) return rc;
-        kinds.push_back(1);
-        upd.emplace_back(it, &r);
-      }
-    }
-    delta_kernel<<<dim3((unsigned)((jobs + 255) / 256)), dim3(256), 0, st>>>(terms, P.M, jobs, conv, iters, delta,
-                                                                            opts->delta0, opts->fixed_iters);
-    HIP_TRY(hipGetLastError());
-    if ((rc = mark())) return rc;
-    kinds.push_back(0);
-  }
-  for (const ClassRun& r : dp->runs[2]) {
-    sa.sweeps = dp->bethe + r.first;
-    sa.mode = 1;
-    HIP_TRY(bbp::launch_sweeps(r.cls, (unsigned)r.count, st, sa));
-  }
-  if ((rc = mark())) return rc;
-  kinds.push_back(2);
-  finalize_kernel<<<dim3((unsigned)batch), dim3(256), 0, st>>>(
-      lnw, P.nblocks, msgs, P.M, dp->pairs, (int)(P.pair_ids.size() / 2), labels, d, delta, iters, opts->delta1,
-      opts->rule, loglik_dev, delta_dev, iters_dev, coset_dev, correction_dev);
-  HIP_TRY(hipGetLastError());
-  if (messages_dev)
-    HIP_TRY(hipMemcpyAsync(messages_dev, msgs, (size_t)jobs * P.M * MSTRIDE * sizeof(float),
-                           hipMemcpyDeviceToDevice, st));
-  if ((rc = mark())) return rc;
-  kinds.push_back(0);
-
-  if (timing) {
-    HIP_TRY(hipStreamSynchronize(st));
-    std::memset(timing, 0, sizeof(*timing));
-    // flops actually executed: a job runs the updates of iteration `it` iff it ran more than `it` iterations
-    std::vector<int32_t> it_host((size_t)jobs);
-    HIP_TRY(hipMemcpy(it_host.data(), iters, sizeof(int32_t) * jobs, hipMemcpyDeviceToHost));
-    std::vector<double> active((size_t)opts->max_iter + 1, 0.0);
-    for (auto v : it_host) active[std::min<int32_t>(std::max<int32_t>(v, 0), opts->max_iter)] += 1.0;
-    for (int k = opts->max_iter - 1; k >= 0; --k) active[k] += active[k + 1];   // jobs with iters >= k
-    std::map<int, std::tuple<double, int, double>> per_class;   // class -> (ms, launches, flops)
-    size_t u = 0;
-    for (size_t k = 1; k < evs.size(); ++k) {
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, evs[k - 1], evs[k]));
-      const int kind = kinds[k - 1];
-      if (kind == 1) {
-        const int it = upd[u].first;
-        const ClassRun* r = upd[u].second;
-        ++u;
-        const double fl = active[it + 1] * r->flops;
-        timing->update_ms += ms;
-        timing->update_launches += 1;
-        timing->update_flops += fl;
-        auto& pc = per_class[r->cls];
-        std::get<0>(pc) += ms;
-        std::get<1>(pc) += 1;
-        std::get<2>(pc) += fl;
-      } else if (kind == 2) {
-        timing->bethe_ms += ms;
-      } else {
-        timing->other_ms += ms;
-      }
-    }
-    timing->top_class = -1;
-    for (auto& kv : per_class)
-      if (std::get<0>(kv.second) > timing->top_ms) {
-        timing->top_class = kv.first;
-        timing->top_ms = std::get<0>(kv.second);
-        timing->top_launches = std::get<1>(kv.second);
-        timing->top_flops = std::get<2>(kv.second);
-      }
-    for (auto e : evs) (void)hipEventDestroy(e);
-  }
+  if (!t || (t->order != 0 && t->order != 1) || (t->streams != 1 && t->streams != 2 && t->streams != 4))
+    return fail(BBP_EINVAL, "tuning must have order 0 or 1 and 1, 2 or 4 streams");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Tune tn;
+  tn.order = t->order;
+  tn.streams = t->streams;
+  g_tune[std::make_tuple(d, opts->block_rows, opts->block_cols, opts->chi, dev)] = tn;
   return BBP_OK;
+}
+
+int bbp_autotune(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch, const bbp_opts* opts,
+                 void* workspace, size_t workspace_bytes, void* stream, bbp_tuning* best) {
+  int rc = validate(d, opts);
+  if (rc) return rc;
+  if (!best) return fail(BBP_EINVAL, "best is NULL");
+  if (batch < 1) return fail(BBP_EINVAL, "autotuning needs a batch of at least one syndrome");
+  const int n = d * d + (d - 1) * (d - 1);
+  void* out = nullptr;
+  const size_t outb = (size_t)batch * (4 * 8 + 4 * 8 + 4 * 4 + 1 + n) + 64;
+  if (hipMalloc(&out, outb) != hipSuccess) return fail(BBP_ENOMEM, "device allocation failed");
+  bbp_group g;
+  g.d = d;
+  g.p = p;
+  g.syndromes_dev = syndromes_dev;
+  g.batch = batch;
+  g.loglik_dev = (double*)out;
+  g.delta_dev = g.loglik_dev + batch * 4;
+  g.iters_dev = (int32_t*)(g.delta_dev + batch * 4);
+  g.coset_dev = (uint8_t*)(g.iters_dev + batch * 4);
+  g.correction_dev = g.coset_dev + batch;
+  bbp_opts o = *opts;
+  o.graph = 0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Tune pick;
+  double best_ms = -1.0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(BBP_EHIP, "event");
+  const int orders[2] = {0, 1}, streams[3] = {1, 2, 4};
+  for (int oi = 0; oi < 2 && rc == BBP_OK; ++oi)
+    for (int si = 0; si < 3 && rc == BBP_OK; ++si) {
+      Tune tn;
+      tn.order = orders[oi];
+      tn.streams = streams[si];
+      rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, nullptr, st, nullptr, &tn);   // warm-up
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(BBP_EHIP, "event record"); break; }
+      for (int rep = 0; rep < 2 && rc == BBP_OK; ++rep)
+        rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, nullptr, st, nullptr, &tn);
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(BBP_EHIP, "timing failed");
+        break;
+      }
+      if (best_ms < 0.0 || ms / 2.0 < best_ms) {
+        best_ms = ms / 2.0;
+        pick = tn;
+      }
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(out);
+  if (rc) return rc;
+  best->order = pick.order;
+  best->streams = pick.streams;
+  best->ms = best_ms;
+  return bbp_set_tuning(d, opts, best);
 }
 
 int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts, double* loglik, double* delta,
                        int32_t* iters, uint8_t* coset, uint8_t* correction) {
   if (batch <= 0) return batch == 0 ? BBP_OK : fail(BBP_EINVAL, "batch must be >= 0");
-  if (!nets || !nets[0]) return fail(BBP_EINVAL, "nets is NULL");
+  if (!nets) return fail(BBP_EINVAL, "nets is NULL");
   if (!loglik || !delta || !iters || !coset || !correction) return fail(BBP_EINVAL, "a required pointer is NULL");
-  const int d = nets[0]->impl.d;
-  const double p = nets[0]->impl.p;
-  for (int64_t i = 0; i < batch; ++i)
-    if (!nets[i] || nets[i]->impl.d != d || nets[i]->impl.p != p)
-      return fail(BBP_EINVAL, "all networks of one call must share d and p");
-  const int m = 2 * d * (d - 1), n = d * d + (d - 1) * (d - 1);
+  // group the networks by (d, p), keeping each group's members in input order
+  std::vector<std::pair<int, double>> keys;
+  std::vector<std::vector<int64_t>> members;
+  int nmax = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (!nets[i]) return fail(BBP_EINVAL, "a network is NULL");
+    const int d = nets[i]->impl.d;
+    const double p = nets[i]->impl.p;
+    nmax = std::max(nmax, d * d + (d - 1) * (d - 1));
+    size_t k = 0;
+    while (k < keys.size() && !(keys[k].first == d && keys[k].second == p)) ++k;
+    if (k == keys.size()) {
+      if ((int)keys.size() == bbp::MAX_GROUPS) return fail(BBP_EINVAL, "at most 8 distinct (d, p) per call");
+      keys.push_back({d, p});
+      members.emplace_back();
+    }
+    members[k].push_back(i);
+  }
+  const int ng = (int)keys.size();
+  std::vector<bbp_group> groups((size_t)ng);
+  std::vector<std::vector<uint8_t>> syn((size_t)ng);
+  size_t out_bytes = 0, syn_bytes = 0;
+  std::vector<size_t> out_off((size_t)ng), syn_off((size_t)ng);
+  for (int g = 0; g < ng; ++g) {
+    const int d = keys[g].first, m = 2 * d * (d - 1), n = d * d + (d - 1) * (d - 1);
+    const int64_t b = (int64_t)members[g].size();
+    syn[g].resize((size_t)b * m);
+    for (int64_t j = 0; j < b; ++j)
+      std::memcpy(&syn[g][(size_t)j * m], nets[members[g][j]]->impl.syndrome.data(), m);
+    syn_off[g] = syn_bytes;
+    syn_bytes = align256(syn_bytes + syn[g].size());
+    out_off[g] = out_bytes;
+    out_bytes = align256(out_bytes + (size_t)b * (4 * 8 + 4 * 8 + 4 * 4 + 1 + n));
+    groups[g].d = d;
+    groups[g].p = keys[g].second;
+    groups[g].batch = b;
+  }
   size_t wsb = 0;
-  int rc = bbp_workspace_size(d, batch, opts, &wsb);
+  int rc = bbp_workspace_size_groups(groups.data(), ng, opts, &wsb);
   if (rc) return rc;
-  std::vector<uint8_t> syn((size_t)batch * m);
-  for (int64_t i = 0; i < batch; ++i) std::memcpy(&syn[(size_t)i * m], nets[i]->impl.syndrome.data(), m);
   void *ws = nullptr, *dsyn = nullptr, *dout = nullptr;
-  const size_t outb = (size_t)batch * (4 * 8 + 4 * 8 + 4 * 4 + 1 + n);
   auto cleanup = [&]() { if (ws) (void)hipFree(ws); if (dsyn) (void)hipFree(dsyn); if (dout) (void)hipFree(dout); };
-  if (hipMalloc(&ws, wsb) != hipSuccess || hipMalloc(&dsyn, syn.size()) != hipSuccess ||
-      hipMalloc(&dout, outb) != hipSuccess) {
+  if (hipMalloc(&ws, std::max<size_t>(wsb, 256)) != hipSuccess || hipMalloc(&dsyn, syn_bytes) != hipSuccess ||
+      hipMalloc(&dout, out_bytes) != hipSuccess) {
     cleanup();
     return fail(BBP_ENOMEM, "device allocation failed");
   }
-  char* o = (char*)dout;
-  double* dl = (double*)o;
-  double* dd = dl + batch * 4;
-  int32_t* di = (int32_t*)(dd + batch * 4);
-  uint8_t* dc = (uint8_t*)(di + batch * 4);
-  uint8_t* dcorr = dc + batch;
-  if (hipMemcpy(dsyn, syn.data(), syn.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    cleanup();
-    return fail(BBP_EHIP, "copy of syndromes failed");
+  for (int g = 0; g < ng; ++g) {
+    const int64_t b = groups[g].batch;
+    char* o = (char*)dout + out_off[g];
+    groups[g].syndromes_dev = (const uint8_t*)((char*)dsyn + syn_off[g]);
+    groups[g].loglik_dev = (double*)o;
+    groups[g].delta_dev = groups[g].loglik_dev + b * 4;
+    groups[g].iters_dev = (int32_t*)(groups[g].delta_dev + b * 4);
+    groups[g].coset_dev = (uint8_t*)(groups[g].iters_dev + b * 4);
+    groups[g].correction_dev = groups[g].coset_dev + b;
+    if (hipMemcpy((void*)groups[g].syndromes_dev, syn[g].data(), syn[g].size(), hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail(BBP_EHIP, "copy of syndromes failed");
+    }
   }
-  rc = bbp_decode_device(d, p, (const uint8_t*)dsyn, batch, opts, ws, wsb, dl, dd, di, dc, dcorr, nullptr, nullptr,
-                         nullptr);
-  if (rc == BBP_OK) {
-    if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(loglik, dl, batch * 4 * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(delta, dd, batch * 4 * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(iters, di, batch * 4 * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(coset, dc, batch, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(correction, dcorr, (size_t)batch * n, hipMemcpyDeviceToHost) != hipSuccess)
-      rc = fail(BBP_EHIP, "decode or copy back failed");
+  bbp_opts o = *opts;
+  o.graph = 0;
+  rc = decode_groups(groups.data(), ng, &o, ws, wsb, nullptr, nullptr, nullptr, nullptr);
+  if (rc == BBP_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(BBP_EHIP, "decode failed");
+  std::memset(correction, 0, (size_t)batch * nmax);
+  for (int g = 0; g < ng && rc == BBP_OK; ++g) {
+    const int d = groups[g].d, n = d * d + (d - 1) * (d - 1);
+    const int64_t b = groups[g].batch;
+    std::vector<double> ll((size_t)b * 4), dl((size_t)b * 4);
+    std::vector<int32_t> it((size_t)b * 4);
+    std::vector<uint8_t> cs((size_t)b), corr((size_t)b * n);
+    if (hipMemcpy(ll.data(), groups[g].loglik_dev, b * 32, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(dl.data(), groups[g].delta_dev, b * 32, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(it.data(), groups[g].iters_dev, b * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(cs.data(), groups[g].coset_dev, b, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(corr.data(), groups[g].correction_dev, (size_t)b * n, hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = fail(BBP_EHIP, "copy back failed");
+      break;
+    }
+    for (int64_t j = 0; j < b; ++j) {
+      const int64_t i = members[g][j];
+      for (int k = 0; k < 4; ++k) {
+        loglik[i * 4 + k] = ll[j * 4 + k];
+        delta[i * 4 + k] = dl[j * 4 + k];
+        iters[i * 4 + k] = it[j * 4 + k];
+      }
+      coset[i] = cs[j];
+      std::memcpy(correction + (size_t)i * nmax, &corr[(size_t)j * n], n);
+    }
   }
   cleanup();
   return rc;

@@ -3,7 +3,7 @@
 //   mode 0: BP update of message s.msg_out (Sec. III.D): the new message is normalised (remark 3), damped
 //           against the old one (remark 7) and the distance term of the convergence test stored (remark 4);
 //   mode 1: closing sweep of block s.block, W_v of the Bethe estimate (Lemma 3.1).
-// Grid: x = groups of SWEEP_WAVES jobs, y = sweep of the launch's list.
+// Grid: x = items / SWEEP_WAVES; item = one (job, sweep) of one (d, p) group of the launch.
 #include <hip/hip_runtime.h>
 
 #include "sweep_launch.hpp"
@@ -31,21 +31,34 @@ template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
 __global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BBP_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
-  const int64_t job = (int64_t)blockIdx.x * SWEEP_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (job >= a.jobs) return;
-  if (a.mode == 0 && a.conv[job]) return;
-  const SweepDesc s = a.sweeps[blockIdx.y];
-  const int L = 2 * a.d - 1, kp = s.kp, H = 1 << kp;
+  const int64_t item = (int64_t)blockIdx.x * SWEEP_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= a.items) return;
+  int gi = 0;
+  for (int k = 1; k < a.ngroups; ++k)
+    if (item >= a.g[k].item0) gi = k;
+  const SweepGroup& G = a.g[gi];
+  const int64_t local = item - G.item0;
+  int64_t job, sw;
+  if (a.order == 0) {
+    sw = local / G.jobs;
+    job = local - sw * G.jobs;
+  } else {
+    job = local / G.count;
+    sw = local - job * G.count;
+  }
+  if (a.mode == 0 && G.conv[job]) return;
+  const SweepDesc s = G.sweeps[sw];
+  const int L = 2 * G.d - 1, kp = s.kp, H = 1 << kp;
   const bool valid = lane < H;
 
   wave::Ctx c;
   c.h = lane;
   c.kp = kp;
   c.geo = s.geo;
-  c.p00 = a.p00;
-  c.pe = a.pe;
+  c.p00 = G.p00;
+  c.pe = G.pe;
   c.exp2 = 0;
-  const uint8_t* lab = a.labels + job * L * L;
+  const uint8_t* lab = G.labels + job * L * L;
   int lb = 0;
   if (lane < KT * kp) {
     const int t = lane / kp, i = lane - t * kp;
@@ -56,7 +69,7 @@ void sweep_kernel(SweepArgs a) {
   c.labv = __int_as_float(lb);
   // side messages: a sweep toward W or N walks them from their last leg, so read them leg-reversed
   const bool fwd = (s.frame == FRAME_E || s.frame == FRAME_S);
-  const float* mbase = a.msgs + job * a.M * MSTRIDE;
+  const float* mbase = G.msgs + job * G.M * MSTRIDE;
   const int sl = fwd ? lane : reverse_legs(lane, KT);
   const bool in_msg = lane < (1 << KT);
   c.mtv = (TOP && in_msg) ? mbase[s.msg_top * MSTRIDE + sl] : 0.0f;
@@ -85,11 +98,11 @@ void sweep_kernel(SweepArgs a) {
     if (s.msg_close >= 0) w = valid ? (double)mbase[s.msg_close * MSTRIDE + mi] * (double)fin : 0.0;
     else if (lane == 0) w = fin;
     w = wave_sum_d(w);
-    if (lane == 0) a.lnW[job * a.nblocks + s.block] = (w > 0.0) ? c.exp2 * 0.69314718055994530942 + log(w) : NAN;
+    if (lane == 0) G.lnW[job * G.nblocks + s.block] = (w > 0.0) ? c.exp2 * 0.69314718055994530942 + log(w) : NAN;
   } else {
     // normalised new message, damping against the old one (unit norm), distance term. With unit vectors
     // a, b: 2 - 2<a,b>^2 = |a - b|^2 |a + b|^2 / 2, which has no cancellation near convergence in FP32.
-    float* mo = a.msgs + job * a.M * MSTRIDE + s.msg_out * MSTRIDE;
+    float* mo = G.msgs + job * G.M * MSTRIDE + s.msg_out * MSTRIDE;
     const float old = valid ? mo[mi] : 0.0f;
     const float fn = fin * __builtin_amdgcn_rsqf(wave::wave_sum(fin * fin));
     const float dm = (1.0f - a.eta) * fn + a.eta * old;
@@ -97,7 +110,7 @@ void sweep_kernel(SweepArgs a) {
     const float dif = fm - old, sum = fm + old;
     const float dd = wave::wave_sum(dif * dif), ss = wave::wave_sum(sum * sum);
     if (valid) mo[mi] = fm;
-    if (lane == 0) a.terms[job * a.M + s.msg_out] = 0.5 * (double)dd * (double)ss;
+    if (lane == 0) G.terms[job * G.M + s.msg_out] = 0.5 * (double)dd * (double)ss;
   }
 }
 

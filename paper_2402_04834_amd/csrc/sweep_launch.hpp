@@ -17,20 +17,30 @@ namespace bbp {
 constexpr int SWEEP_WAVES = BBP_SWEEP_WAVES;
 constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
 
-struct SweepArgs {
-  const SweepDesc* sweeps;   // this launch's sweeps (all of one class: length, caps present)
-  int d;
+constexpr int MAX_GROUPS = 8;   // (d, p) groups of one mixed batch
+
+// One (d, p) group of a sweep launch: its sweeps of the launch's class and its job state.
+struct SweepGroup {
+  const SweepDesc* sweeps;   // the group's sweeps of this class (count of them)
   const uint8_t* labels;     // [job][L*L] coset labels
   float* msgs;               // [job][M][MSTRIDE] dense messages, position 0 most significant
-  int M;
   double* terms;             // [job][M] distance terms of the last update
   const int32_t* conv;       // [job] converged flags
-  float p00, pe;             // depolarizing noise entries: 1 - p and p / 3
-  float eta;                 // damping
-  int mode;                  // 0: message update, 1: closing sweep (W_v)
-  double* lnW;               // [job][nblocks] (mode 1)
-  int nblocks;
+  double* lnW;               // [job][nblocks] (closing sweeps)
   int64_t jobs;
+  int64_t item0;             // first item of the group in the launch
+  int32_t count;             // sweeps of this class in the group
+  int32_t d, M, nblocks;
+  float p00, pe;             // depolarizing noise entries: 1 - p and p / 3
+};
+
+struct SweepArgs {
+  SweepGroup g[MAX_GROUPS];
+  int64_t items;             // sum over groups of jobs * count: one wavefront each
+  int32_t ngroups;
+  int32_t mode;              // 0: message update, 1: closing sweep (W_v)
+  int32_t order;             // item order inside a group: 0 sweep-major (item = sweep * jobs + job), 1 job-major
+  float eta;                 // damping
 };
 
 // Class of a sweep: the kernel instantiation that runs it -- length, caps present, one position across,
@@ -40,8 +50,8 @@ inline int sweep_class(const SweepDesc& s) {
          ((s.geo & GEO_Q00) ? 1 : 0);
 }
 
-// Launch the sweeps a.sweeps[0 .. count) of class `cls` for a.jobs jobs on stream st.
-hipError_t launch_sweeps(int cls, unsigned count, hipStream_t st, const SweepArgs& a);
+// Launch the a.items (job, sweep) items of class `cls` on stream st.
+hipError_t launch_sweeps(int cls, hipStream_t st, const SweepArgs& a);
 
 // per-length launchers (one translation unit each); variant = class code modulo 16
 hipError_t launch_sweeps_k1(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
