@@ -144,14 +144,17 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
                       uint8_t* correction_dev, float* messages_dev, void* stream, bbp_timing* timing);
 
 /* ---------------------------------------------------------------------------------------------------
- * Mixed batches. A group is a batch of syndromes of one distance d and noise rate p, resident in device
- * memory, with the device arrays that receive its results (layouts as in bbp_decode_device). One call
+ * Mixed batches. A group is a batch of syndromes of one distance d (and bond dimension chi), each with its
+ * noise rate p, resident in device memory, with the device arrays that receive its results (layouts as in
+ * bbp_decode_device). One call
  * decodes up to 8 groups together: every colour round launches each block-sweep class once over all
  * groups, so a mix of distances costs no more launches than its largest member.
  */
 typedef struct bbp_group {
   int32_t d;
-  double p;
+  int32_t chi;                    /* this group's bond dimension chi; 0 = opts->chi */
+  double p;                       /* noise rate of every syndrome of the group, unless p_dev is given */
+  const double* p_dev;            /* optional [batch] device array: each syndrome's own p in (0, 1) */
   const uint8_t* syndromes_dev;   /* [batch][2d(d-1)] */
   int64_t batch;
   double* loglik_dev;             /* [batch][4] */

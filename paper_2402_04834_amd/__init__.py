@@ -111,24 +111,35 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     return out
 
 
-def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None):
-    """Decode a mixed batch: `groups` is a list of (d, p, syndromes) with syndromes a torch uint8 CUDA
-    tensor [batch, 2d(d-1)]. Returns (list of per-group output dicts as in decode_device, workspace,
-    bbp_timing or None)."""
+def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None, outs=None):
+    """Decode a mixed batch: `groups` is a list of (d, p, syndromes) or (d, p, syndromes, chi) with
+    syndromes a torch uint8 CUDA tensor [batch, 2d(d-1)], p a float or a float64 CUDA tensor [batch] of
+    per-syndrome noise rates, and chi the group's bond dimension (default opts.chi). Returns (list of
+    per-group output dicts as in decode_device, workspace, bbp_timing or None). `outs` (from an earlier
+    call with the same groups) receives the results in place, keeping graph-mode arguments identical."""
     import torch
 
     gs = (bbp_group * len(groups))()
+    outs_in = outs
     outs, keep = [], []
     dev = None
-    for k, (d, p, syn) in enumerate(groups):
+    for k, grp in enumerate(groups):
+        d, p, syn = grp[:3]
+        chi = grp[3] if len(grp) > 3 else 0
         assert syn.is_cuda and syn.dtype == torch.uint8 and syn.dim() == 2
         syn = syn.contiguous()
         keep.append(syn)
         dev = syn.device
         b = syn.shape[0]
-        o = _outputs(b, d * d + (d - 1) * (d - 1), dev)
+        p_ptr, p_val = None, p
+        if torch.is_tensor(p):
+            assert p.is_cuda and p.dtype == torch.float64 and p.shape == (b,)
+            p = p.contiguous()
+            keep.append(p)
+            p_ptr, p_val = p.data_ptr(), 0.0
+        o = outs_in[k] if outs_in is not None else _outputs(b, d * d + (d - 1) * (d - 1), dev)
         outs.append(o)
-        gs[k] = bbp_group(d, p, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),
+        gs[k] = bbp_group(d, chi, p_val, p_ptr, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),
                           o["iters"].data_ptr(), o["coset"].data_ptr(), o["correction"].data_ptr())
     n = C.c_size_t()
     _lib.check(_lib.lib().bbp_workspace_size_groups(gs, len(groups), C.byref(opts), C.byref(n)))

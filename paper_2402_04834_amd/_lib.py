@@ -28,7 +28,8 @@ class bbp_opts(C.Structure):
 
 class bbp_group(C.Structure):
     _fields_ = [
-        ("d", C.c_int32), ("p", C.c_double), ("syndromes_dev", C.c_void_p), ("batch", C.c_int64),
+        ("d", C.c_int32), ("chi", C.c_int32), ("p", C.c_double), ("p_dev", C.c_void_p),
+        ("syndromes_dev", C.c_void_p), ("batch", C.c_int64),
         ("loglik_dev", C.c_void_p), ("delta_dev", C.c_void_p), ("iters_dev", C.c_void_p),
         ("coset_dev", C.c_void_p), ("correction_dev", C.c_void_p),
     ]

@@ -369,6 +369,7 @@ int aux_for(int dev, Aux** out) {
 
 struct GroupRun {
   bbp_group in;
+  bbp_opts opts;   // the call's options with this group's chi
   DevPlan* dp = nullptr;
   Layout lay;
   size_t off = 0;
@@ -388,18 +389,22 @@ int resolve(const bbp_group* groups, int ng, const bbp_opts* opts, std::vector<G
   size_t off = 0;
   for (int g = 0; g < ng; ++g) {
     const bbp_group& G = groups[g];
-    int rc = validate(G.d, opts);
+    if (!opts) return fail(BBP_EINVAL, "opts is NULL");
+    if (G.chi < 0) return fail(BBP_EINVAL, "group chi must be >= 0");
+    gr[g].opts = *opts;
+    if (G.chi > 0) gr[g].opts.chi = G.chi;
+    int rc = validate(G.d, &gr[g].opts);
     if (rc) return rc;
-    if (!(G.p > 0.0 && G.p < 1.0)) return fail(BBP_EINVAL, "p must be in (0, 1)");
+    if (!G.p_dev && !(G.p > 0.0 && G.p < 1.0)) return fail(BBP_EINVAL, "p must be in (0, 1)");
     if (G.batch < 0) return fail(BBP_EINVAL, "batch must be >= 0");
     if (G.batch > (int64_t)1 << 24) return fail(BBP_EINVAL, "batch too large");
     gr[g].in = G;
-    gr[g].lay = layout(host_plan(G.d, opts), G.batch);
+    gr[g].lay = layout(host_plan(G.d, &gr[g].opts), G.batch);
     gr[g].off = off;
     off = align256(off + gr[g].lay.total);
     gr[g].jobs = 4 * G.batch;
     if (need_plans) {
-      if ((rc = device_plan(G.d, opts, &gr[g].dp))) return rc;
+      if ((rc = device_plan(G.d, &gr[g].opts, &gr[g].dp))) return rc;
       if (!gr[g].dp->plan.gpu_ok) return fail(BBP_EUNSUPPORTED, gr[g].dp->plan.why);
     }
   }
@@ -523,6 +528,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, flo
         G.nblocks = g.dp->plan.nblocks;
         G.p00 = 1.0f - (float)g.in.p;
         G.pe = (float)g.in.p / 3.0f;
+        G.pdev = g.in.p_dev;
         items += g.jobs * (int64_t)r.count;
       }
       sa.items = items;
@@ -659,7 +665,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     tn = *force;
   } else {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_tune.find(std::make_tuple(gr[0].in.d, opts->block_rows, opts->block_cols, opts->chi, dev));
+    auto it = g_tune.find(std::make_tuple(gr[0].in.d, opts->block_rows, opts->block_cols, gr[0].opts.chi, dev));
     if (it != g_tune.end()) tn = it->second;
   }
   Aux* aux = nullptr;
@@ -686,7 +692,8 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
                          u64(o.delta0), u64(o.delta1), u64(o.damping), (uint64_t)o.rule, (uint64_t)o.fixed_iters,
                          (uint64_t)o.precision});
   for (auto& g : gr)
-    key.insert(key.end(), {(uint64_t)g.in.d, u64(g.in.p), u64(g.in.syndromes_dev), (uint64_t)g.in.batch,
+    key.insert(key.end(), {(uint64_t)g.in.d, (uint64_t)g.opts.chi, u64(g.in.p), u64(g.in.p_dev),
+                           u64(g.in.syndromes_dev), (uint64_t)g.in.batch,
                            u64(g.in.loglik_dev), u64(g.in.delta_dev), u64(g.in.iters_dev), u64(g.in.coset_dev),
                            u64(g.in.correction_dev)});
   hipGraphExec_t exec = nullptr;
@@ -838,6 +845,7 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
                       int32_t* iters_dev, uint8_t* coset_dev, uint8_t* correction_dev, float* messages_dev,
                       void* stream, bbp_timing* timing) {
   bbp_group g;
+  std::memset(&g, 0, sizeof(g));
   g.d = d;
   g.p = p;
   g.syndromes_dev = syndromes_dev;
@@ -876,6 +884,7 @@ int bbp_autotune(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batc
   const size_t outb = (size_t)batch * (4 * 8 + 4 * 8 + 4 * 4 + 1 + n) + 64;
   if (hipMalloc(&out, outb) != hipSuccess) return fail(BBP_ENOMEM, "device allocation failed");
   bbp_group g;
+  std::memset(&g, 0, sizeof(g));
   g.d = d;
   g.p = p;
   g.syndromes_dev = syndromes_dev;
@@ -951,6 +960,7 @@ int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts
   }
   const int ng = (int)keys.size();
   std::vector<bbp_group> groups((size_t)ng);
+  std::memset(groups.data(), 0, sizeof(bbp_group) * groups.size());
   std::vector<std::vector<uint8_t>> syn((size_t)ng);
   size_t out_bytes = 0, syn_bytes = 0;
   std::vector<size_t> out_off((size_t)ng), syn_off((size_t)ng);

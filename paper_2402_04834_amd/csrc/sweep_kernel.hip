@@ -55,8 +55,14 @@ void sweep_kernel(SweepArgs a) {
   c.h = lane;
   c.kp = kp;
   c.geo = s.geo;
-  c.p00 = G.p00;
-  c.pe = G.pe;
+  if (G.pdev) {
+    const float pj = (float)G.pdev[job >> 2];
+    c.p00 = 1.0f - pj;
+    c.pe = pj / 3.0f;
+  } else {
+    c.p00 = G.p00;
+    c.pe = G.pe;
+  }
   c.exp2 = 0;
   const uint8_t* lab = G.labels + job * L * L;
   int lb = 0;

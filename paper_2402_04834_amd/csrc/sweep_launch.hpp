@@ -32,6 +32,7 @@ struct SweepGroup {
   int32_t count;             // sweeps of this class in the group
   int32_t d, M, nblocks;
   float p00, pe;             // depolarizing noise entries: 1 - p and p / 3
+  const double* pdev;        // optional [job / 4] per-syndrome p (overrides p00, pe)
 };
 
 struct SweepArgs {

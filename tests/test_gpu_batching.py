@@ -143,3 +143,54 @@ def test_host_api_mixed_networks_in_input_order(dev):
         assert got["coset"][i] == ref["coset"][0]
         np.testing.assert_array_equal(got["correction"][i, :n], ref["correction"][0])
         assert np.all(got["correction"][i, n:] == 0)
+
+
+def _mixed_workload(count):
+    """The mixed-distance workload: per syndrome d uniform over {9, 13, 17, 21} and p uniform over
+    [0.05, 0.15]; chi 16 for d <= 13 and 32 above. Returns {d: (indices, p array, syndromes)}."""
+    items = workload.mixed_batch(count)
+    groups = {}
+    for i, (d, p, _, s) in enumerate(items):
+        groups.setdefault(d, ([], [], []))
+        groups[d][0].append(i)
+        groups[d][1].append(p)
+        groups[d][2].append(s)
+    return {d: (np.array(ix), np.array(ps), np.stack(ss)) for d, (ix, ps, ss) in sorted(groups.items())}
+
+
+def test_mixed_distance_workload_one_graph(dev):
+    import torch
+    import paper_2402_04834_amd as bbp
+    mix = _mixed_workload(8192)
+    _say("[mixed workload] 8192 syndromes:", {d: len(v[0]) for d, v in mix.items()})
+    opts = bbp.default_opts(block=6, chi=32, max_iter=20, graph=1)
+    chi_of = {9: 16, 13: 16, 17: 32, 21: 32}
+    groups = [(d, torch.from_numpy(ps).to(dev), torch.from_numpy(ss).to(dev), chi_of[d])
+              for d, (ix, ps, ss) in mix.items()]
+    st = torch.cuda.Stream(dev)
+    with torch.cuda.stream(st):
+        outs, ws, _ = bbp.decode_groups(groups, opts, stream=st)
+    st.synchronize()
+    # each group decoded alone (eager) gives identical results
+    eager = bbp.default_opts(block=6, chi=32, max_iter=20)
+    for (d, p_t, s_t, chi), o in zip(groups, outs):
+        _say(f"[mixed workload] d={d} alone")
+        alone, _, _ = bbp.decode_groups([(d, p_t, s_t, chi)], eager)
+        torch.cuda.synchronize()
+        _same(_np(o), _np(alone[0]), f"d={d}")
+        assert np.all(o["coset"].cpu().numpy() < 4)
+    # oracle parity on a sample of the small distances (same p per syndrome, same options)
+    for d, count in ((9, 3), (13, 1)):
+        ix, ps, ss = mix[d]
+        o = outs[list(mix).index(d)]
+        for j in range(count):
+            _say(f"[mixed workload] oracle d={d} syndrome {ix[j]} p={ps[j]:.4f}")
+            ref = blockbp.decode(d, float(ps[j]), ss[j:j + 1], block=(6, 6), chi=chi_of[d], max_iter=20)
+            it = o["iters"].cpu().numpy()[j]
+            near = np.abs(np.log(np.maximum(ref["delta"][0], 1e-30) / 1e-4)) < 0.05
+            assert np.all((it == ref["iters"][0]) | near)
+            same = it == ref["iters"][0]
+            got = o["loglik"].cpu().numpy()[j]
+            np.testing.assert_array_less(np.abs(got[same] - ref["loglik"][0][same]),
+                                         2e-4 + 2e-6 * np.abs(ref["loglik"][0][same]))
+            assert o["coset"].cpu().numpy()[j] == ref["coset"][0]
