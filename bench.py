@@ -70,11 +70,17 @@ def agreement(out, batch):
     ll = out["loglik"].cpu().numpy()
     it = out["iters"].cpu().numpy()
     eq = sum(int(cos[r["index"]] == r["coset"]) for r in recs)
+    every = np.array([abs(ll[r["index"], k] - r["loglik"][k]) for r in recs for k in range(4)
+                      if np.isfinite(r["loglik"][k])])
     diffs = [abs(ll[r["index"], k] - r["loglik"][k]) for r in recs for k in range(4)
              if it[r["index"], k] == r["iters"][k] and np.isfinite(r["loglik"][k])]
     same_it = sum(int(it[r["index"], k] == r["iters"][k]) for r in recs for k in range(4))
+    fin = every[np.isfinite(every)]
     return dict(syndromes=len(recs), decisions_equal=eq, frac=eq / len(recs),
-                cosets_same_iterations=same_it, cosets=4 * len(recs),
+                cosets=4 * len(recs), cosets_same_iterations=same_it,
+                abs_dlnz_all_cosets=dict(max=float(fin.max()), p99=float(np.percentile(fin, 99)),
+                                         median=float(np.median(fin)), nonfinite=int(every.size - fin.size))
+                if fin.size else None,
                 max_abs_dlnz_same_iterations=float(max(diffs)) if diffs else None,
                 median_abs_dlnz_same_iterations=float(np.median(diffs)) if diffs else None,
                 oracle=os.path.relpath(GOLDEN, ROOT))
@@ -87,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, choices=(0, 1), default=0,
+                    help="0: FP32 products (default); 1: products of BF16-rounded inputs, FP32 sums")
     ap.add_argument("--workload", choices=("d17", "mixed"), default="d17",
                     help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -116,7 +124,8 @@ def main():
     _, syn = workload.make_batch(d, p, a.batch, workload="d17")
     dev = torch.device("cuda:0")
     syn_dev = torch.from_numpy(syn).to(dev)
-    opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1)
+    opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1,
+                            precision=a.precision)
     info = bbp.plan_query(d, opts)
     ws = torch.empty(bbp.workspace_size(d, a.batch, opts), dtype=torch.uint8, device=dev)
     # The library's autotuner picks the launch variant for (d, blocks, chi) on this batch (untimed set-up).
@@ -166,11 +175,12 @@ def main():
     line = dict(
         metric=METRIC, value=value, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
         ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32", data="synthetic",
+        dtype=("f32", "bf16-in/f32-acc")[a.precision], data="synthetic",
         config=dict(workload=f"planar surface code d={d}, depolarizing p={p}, {a.batch} seeded syndromes, "
                              f"{block}x{block} blocks, chi={chi}, <= {max_iter} BP iterations, early exit",
                     d=d, p=p, batch=a.batch, block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
-                    damping=0.1, parallelism="single GPU"),
+                    damping=0.1, precision=("FP32 products", "BF16-rounded inputs, FP32 sums")[a.precision],
+                    parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                       frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic(kname),
                       kernel=kname, avg_launch_ms=dom_ms / max(dom_launches, 1),

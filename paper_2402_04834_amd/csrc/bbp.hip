@@ -222,7 +222,7 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
 }  // namespace
 
 hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
-  const int variant = cls & 15, kt = (cls >> 4) + 1;
+  const int variant = (cls & 15) | (a.bf16 ? 16 : 0), kt = (cls >> 4) + 1;
   const dim3 grid(sweep_groups(a.items));
   switch (kt) {
     case 1: return launch_sweeps_k1(variant, grid, st, a);
@@ -259,7 +259,7 @@ int validate(int32_t d, const bbp_opts* o) {
   if (!(o->delta0 <= o->delta1)) return fail(BBP_EINVAL, "delta0 must not exceed delta1");
   if (!(o->damping >= 0.0 && o->damping < 1.0)) return fail(BBP_EINVAL, "damping must be in [0, 1)");
   if (o->rule != 0 && o->rule != 1) return fail(BBP_EINVAL, "rule must be 0 or 1");
-  if (o->precision != 0) return fail(BBP_EUNSUPPORTED, "only precision 0 (FP32) is implemented");
+  if (o->precision != 0 && o->precision != 1) return fail(BBP_EINVAL, "precision must be 0 (FP32) or 1 (BF16 inputs)");
   if (o->graph != 0 && o->graph != 1) return fail(BBP_EINVAL, "graph must be 0 or 1");
   return BBP_OK;
 }
@@ -508,6 +508,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, flo
       sa.ngroups = (int)members.size();
       sa.mode = (list == 2) ? 1 : 0;
       sa.order = tn.order;
+      sa.bf16 = opts->precision == 1 ? 1 : 0;
       sa.eta = (float)opts->damping;
       int64_t items = 0;
       for (int k = 0; k < sa.ngroups; ++k) {

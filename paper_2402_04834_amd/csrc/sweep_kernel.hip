@@ -9,6 +9,9 @@
 #include "sweep_launch.hpp"
 #include "wave_sweep.hpp"
 
+#include <type_traits>
+#include <utility>
+
 #ifndef BBP_KT
 #error "compile with -DBBP_KT=<sweep length 1..6>"
 #endif
@@ -27,7 +30,8 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // entry index of a K-leg dense message with its legs in reverse order
 __device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
 
-template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
+// V = float: FP32 products (precision 0); V = bfin: products of BF16-rounded inputs, FP32 sums (precision 1).
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
 __global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BBP_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
@@ -51,7 +55,7 @@ void sweep_kernel(SweepArgs a) {
   const int L = 2 * G.d - 1, kp = s.kp, H = 1 << kp;
   const bool valid = lane < H;
 
-  wave::Ctx c;
+  wave::Ctx<V> c;
   c.h = lane;
   c.kp = kp;
   c.geo = s.geo;
@@ -78,8 +82,8 @@ void sweep_kernel(SweepArgs a) {
   const float* mbase = G.msgs + job * G.M * MSTRIDE;
   const int sl = fwd ? lane : reverse_legs(lane, KT);
   const bool in_msg = lane < (1 << KT);
-  c.mtv = (TOP && in_msg) ? mbase[s.msg_top * MSTRIDE + sl] : 0.0f;
-  c.mbv = (BOT && in_msg) ? mbase[s.msg_bot * MSTRIDE + sl] : 0.0f;
+  c.mtv = V{(TOP && in_msg) ? mbase[s.msg_top * MSTRIDE + sl] : 0.0f};
+  c.mbv = V{(BOT && in_msg) ? mbase[s.msg_bot * MSTRIDE + sl] : 0.0f};
 
   // message index of this lane's configuration: position i is lane bit pshift(i), message bit kp-1-i
   int mi = 0;
@@ -95,7 +99,7 @@ void sweep_kernel(SweepArgs a) {
     x0 = ((lane & ~ia) == 0) ? 1.0f : 0.0f;
   }
 
-  float fin = wave::sweep<KT, TOP, BOT, SINGLE, Q00>(x0, c);
+  float fin = wave::tof(wave::sweep<V, KT, TOP, BOT, SINGLE, Q00>(V{x0}, c));
   fin = valid ? fin : 0.0f;
 
   if (a.mode == 1) {
@@ -128,32 +132,22 @@ void sweep_kernel(SweepArgs a) {
 namespace {
 template <int V>
 void launch_variant(dim3 grid, hipStream_t st, const SweepArgs& a) {
-  sweep_kernel<BBP_KT, (V >> 3) & 1, (V >> 2) & 1, (V >> 1) & 1, V & 1><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+  constexpr bool TOP = (V >> 3) & 1, BOT = (V >> 2) & 1, SINGLE = (V >> 1) & 1, Q00 = V & 1;
+  if ((V >> 4) & 1) sweep_kernel<wave::bfin, BBP_KT, TOP, BOT, SINGLE, Q00><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+  else sweep_kernel<float, BBP_KT, TOP, BOT, SINGLE, Q00><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+}
+
+template <int... I>
+hipError_t dispatch(int variant, dim3 grid, hipStream_t st, const SweepArgs& a, std::integer_sequence<int, I...>) {
+  bool done = false;
+  ((variant == I ? (launch_variant<I>(grid, st, a), done = true) : false), ...);
+  return done ? hipGetLastError() : hipErrorInvalidValue;
 }
 }  // namespace
 
-// variant = ((top * 2 + bottom) * 2 + single) * 2 + q00
+// variant = (BF16-input products ? 16 : 0) + ((top * 2 + bottom) * 2 + single) * 2 + q00
 hipError_t BBP_CAT(launch_sweeps_k, BBP_KT)(int variant, dim3 grid, hipStream_t st, const SweepArgs& a) {
-  switch (variant) {
-    case 0: launch_variant<0>(grid, st, a); break;
-    case 1: launch_variant<1>(grid, st, a); break;
-    case 2: launch_variant<2>(grid, st, a); break;
-    case 3: launch_variant<3>(grid, st, a); break;
-    case 4: launch_variant<4>(grid, st, a); break;
-    case 5: launch_variant<5>(grid, st, a); break;
-    case 6: launch_variant<6>(grid, st, a); break;
-    case 7: launch_variant<7>(grid, st, a); break;
-    case 8: launch_variant<8>(grid, st, a); break;
-    case 9: launch_variant<9>(grid, st, a); break;
-    case 10: launch_variant<10>(grid, st, a); break;
-    case 11: launch_variant<11>(grid, st, a); break;
-    case 12: launch_variant<12>(grid, st, a); break;
-    case 13: launch_variant<13>(grid, st, a); break;
-    case 14: launch_variant<14>(grid, st, a); break;
-    case 15: launch_variant<15>(grid, st, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return dispatch(variant, grid, st, a, std::make_integer_sequence<int, 32>{});
 }
 
 }  // namespace bbp

@@ -41,6 +41,7 @@ struct SweepArgs {
   int32_t ngroups;
   int32_t mode;              // 0: message update, 1: closing sweep (W_v)
   int32_t order;             // item order inside a group: 0 sweep-major (item = sweep * jobs + job), 1 job-major
+  int32_t bf16;              // 1: products of BF16-rounded inputs (precision mode 1); 0: FP32 products
   float eta;                 // damping
 };
 
@@ -54,7 +55,8 @@ inline int sweep_class(const SweepDesc& s) {
 // Launch the a.items (job, sweep) items of class `cls` on stream st.
 hipError_t launch_sweeps(int cls, hipStream_t st, const SweepArgs& a);
 
-// per-length launchers (one translation unit each); variant = class code modulo 16
+// per-length launchers (one translation unit each); variant = class code modulo 16, plus 16 for the
+// BF16-input kernels
 hipError_t launch_sweeps_k1(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
 hipError_t launch_sweeps_k2(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
 hipError_t launch_sweeps_k3(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);

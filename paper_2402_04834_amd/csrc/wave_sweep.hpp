@@ -37,6 +37,7 @@
 // reduction. Entries are non-negative, so two columns shrink a unit state by at most the product of their
 // smallest coefficients and message entries, far above the FP32 range limit.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "geom.hpp"
@@ -55,23 +56,52 @@ __device__ __forceinline__ void sfor(F&& f) {
   sfor_(f, std::make_integer_sequence<int, N>{});
 }
 
+// Value type of the BF16-input variant (precision mode 1): every product rounds both of its inputs to
+// bfloat16 (round to nearest even) and forms the product exactly in FP32; sums accumulate in FP32. The
+// state itself stays FP32 between operations.
+struct bfin {
+  float v;
+};
+__device__ __forceinline__ float bfr(float x) { return (float)(__bf16)x; }
+__device__ __forceinline__ bfin operator*(bfin a, bfin b) { return bfin{bfr(a.v) * bfr(b.v)}; }
+__device__ __forceinline__ bfin operator+(bfin a, bfin b) { return bfin{a.v + b.v}; }
+__device__ __forceinline__ bfin& operator+=(bfin& a, bfin b) {
+  a.v += b.v;
+  return a;
+}
+
+template <class V>
+__device__ __forceinline__ int vbits(V x) { return __builtin_bit_cast(int, x); }
+template <class V>
+__device__ __forceinline__ V vfrom(int i) { return __builtin_bit_cast(V, i); }
+template <class V>
+__device__ __forceinline__ V splat(float x) { return V{x}; }
+__device__ __forceinline__ float tof(float x) { return x; }
+__device__ __forceinline__ float tof(bfin x) { return x.v; }
+// a * b + c, fused
+__device__ __forceinline__ float fmav(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ bfin fmav(bfin a, bfin b, bfin c) { return bfin{__builtin_fmaf(bfr(a.v), bfr(b.v), c.v)}; }
+
 // value of x in lane (lane ^ M)
-template <int M>
-__device__ __forceinline__ float xchg(float x) {
-  const int xi = __float_as_int(x);
-  if constexpr (M == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true));   // [1,0,3,2]
-  else if constexpr (M == 2) return __int_as_float(__builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, true));  // [2,3,0,1]
-  else if constexpr (M < 32) return __int_as_float(__builtin_amdgcn_ds_swizzle(xi, 0x1F | (M << 10)));
-  else return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)__lane_id()) ^ M) << 2, xi));
+template <int M, class V>
+__device__ __forceinline__ V xchg(V x) {
+  const int xi = vbits(x);
+  if constexpr (M == 1) return vfrom<V>(__builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true));   // [1,0,3,2]
+  else if constexpr (M == 2) return vfrom<V>(__builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, true));  // [2,3,0,1]
+  else if constexpr (M < 32) return vfrom<V>(__builtin_amdgcn_ds_swizzle(xi, 0x1F | (M << 10)));
+  else return vfrom<V>(__builtin_amdgcn_ds_bpermute((((int)__lane_id()) ^ M) << 2, xi));
 }
 
-__device__ __forceinline__ float xchg_rt(float x, int m) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)__lane_id()) ^ m) << 2, __float_as_int(x)));
+template <class V>
+__device__ __forceinline__ V xchg_rt(V x, int m) {
+  return vfrom<V>(__builtin_amdgcn_ds_bpermute((((int)__lane_id()) ^ m) << 2, vbits(x)));
 }
 
-__device__ __forceinline__ float readlane_f(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+template <class V>
+__device__ __forceinline__ V readlane_v(V v, int l) {
+  return vfrom<V>(__builtin_amdgcn_readlane(vbits(v), l));
 }
+__device__ __forceinline__ float readlane_f(float v, int l) { return readlane_v(v, l); }
 
 // value of x in lane l (ds_bpermute)
 __device__ __forceinline__ float lane_get(float x, int l) {
@@ -110,17 +140,18 @@ struct Cap {
 // phi[NP][V] = sum_a op[a][V][NP] psi[a]; g(a) reads psi[a] (a compile-time), m(idx) reads the dense side
 // message at a compile-time index.
 template <class C, int NP, int V, class G, class Msg>
-__device__ __forceinline__ float phi(G&& g, Msg&& m) {
+__device__ __forceinline__ auto phi(G&& g, Msg&& m) {
+  using R = decltype(g(std::integral_constant<int, 0>{}));
   if constexpr (C::kind == K_NONE) {
     if constexpr (V == 0) return g(std::integral_constant<int, 0>{});
-    else return 0.0f;
+    else return splat<R>(0.0f);
   } else if constexpr (C::kind == K_LT) {
     if constexpr (V == (NP & 1)) return g(std::integral_constant<int, (NP >> 1)>{});
-    else return 0.0f;
+    else return splat<R>(0.0f);
   } else if constexpr (C::kind == K_GT) {
     return g(std::integral_constant<int, V * C::PN + NP>{});
   } else {
-    float acc = 0.0f;
+    R acc = splat<R>(0.0f);
     sfor<C::PO>([&](auto a) { acc += m(std::integral_constant<int, C::idx(a, V, NP)>{}) * g(a); });
     return acc;
   }
@@ -128,7 +159,8 @@ __device__ __forceinline__ float phi(G&& g, Msg&& m) {
 
 // phi[NP][0] over g0 plus phi[NP][1] over g1, without adding structural zeros (routing caps).
 template <class C, int NP, class G0, class G1, class Msg>
-__device__ __forceinline__ float phi2(G0&& g0, G1&& g1, Msg&& m) {
+__device__ __forceinline__ auto phi2(G0&& g0, G1&& g1, Msg&& m) {
+  using R = decltype(g0(std::integral_constant<int, 0>{}));
   if constexpr (C::kind == K_NONE) {
     return g0(std::integral_constant<int, 0>{});
   } else if constexpr (C::kind == K_LT) {
@@ -137,7 +169,7 @@ __device__ __forceinline__ float phi2(G0&& g0, G1&& g1, Msg&& m) {
   } else if constexpr (C::kind == K_GT) {
     return g0(std::integral_constant<int, NP>{}) + g1(std::integral_constant<int, C::PN + NP>{});
   } else {
-    float acc = 0.0f;
+    R acc = splat<R>(0.0f);
     sfor<C::PO>([&](auto a) {
       acc += m(std::integral_constant<int, C::idx(a, 0, NP)>{}) * g0(a);
       acc += m(std::integral_constant<int, C::idx(a, 1, NP)>{}) * g1(a);
@@ -147,12 +179,14 @@ __device__ __forceinline__ float phi2(G0&& g0, G1&& g1, Msg&& m) {
 }
 
 // ------------------------------------------------------------------------------------- sweep context
+// V = float (FP32 products) or bfin (BF16-input products).
+template <class V>
 struct Ctx {
   int h;                // lane = crossing-bond configuration (lane-bit layout above)
   int kp;               // positions across the sweep
   int geo;              // GEO_* flags
   float labv;           // lane l < kt*kp: coset label of the site at (step l / kp, position l % kp)
-  float mtv, mbv;       // lane l: entry l of the top / bottom side message (legs in sweep order)
+  V mtv, mbv;           // lane l: entry l of the top / bottom side message (legs in sweep order)
   float p00, pe;        // depolarizing entries
   int exp2;             // accumulated power-of-two scale (state values are true values * 2^-exp2)
 };
@@ -161,21 +195,22 @@ __device__ __forceinline__ int bit(int h, int b) { return (h >> b) & 1; }
 // lane-bit index of position i
 __device__ __forceinline__ int pshift(int kp, int i) { return i == 0 ? 0 : (i == kp - 1 ? 1 : i + 1); }
 
+template <class V>
 struct QC {
-  float cs, cf;   // coefficient of the lane's own value and of the partner lane's (crossing bit flipped)
+  V cs, cf;   // coefficient of the lane's own value and of the partner lane's (crossing bit flipped)
 };
 
 // Coefficients of a qubit with coset label lb and orientation swap for a lane whose vertical bond parity
 // is pv and output crossing bit ho; scaled by sc. The noise entry is p00 iff the label flipped by the
 // parities is the identity: the component the crossing parity acts on must equal it (0 for the lane's own
 // value, 1 for the partner's) and the other component must equal pv.
-__device__ __forceinline__ QC qcoef(const Ctx& c, int lb, int swap, int pv, int ho, bool in_abs, bool out_abs,
-                                    float sc) {
+__device__ __forceinline__ QC<float> qcoef(float p00, float pe, int lb, int swap, int pv, int ho, bool in_abs,
+                                           bool out_abs, float sc) {
   const int lx = lb & 1, lz = (lb >> 1) & 1;
   const int A = swap ? lx : lz, B = swap ? lz : lx;
   const bool m = (pv == B);
-  const float hi = c.p00 * sc, lo = c.pe * sc;
-  QC q;
+  const float hi = p00 * sc, lo = pe * sc;
+  QC<float> q;
   q.cs = (m && A == 0) ? hi : lo;
   q.cf = (m && A == 1) ? hi : lo;
   if (in_abs) {   // the input crossing bit must be 0
@@ -189,12 +224,22 @@ __device__ __forceinline__ QC qcoef(const Ctx& c, int lb, int swap, int pv, int 
   return q;
 }
 
-__device__ __forceinline__ int label_at(const Ctx& c, int t, int i) {
+template <class V>
+__device__ __forceinline__ int label_at(const Ctx<V>& c, int t, int i) {
   return __float_as_int(readlane_f(c.labv, t * c.kp + i)) & 3;
 }
 
+// Coefficients of the qubit at (step t, position i).
+template <class V>
+__device__ __forceinline__ QC<V> qcoefs(const Ctx<V>& c, int t, int i, int swap, int pv, int ho, bool in_abs,
+                                        bool out_abs, V sc) {
+  const QC<float> q = qcoef(c.p00, c.pe, label_at(c, t, i), swap, pv, ho, in_abs, out_abs, tof(sc));
+  return QC<V>{V{q.cs}, V{q.cf}};
+}
+
 // lane mask of the checks of a column (q0t: its site 0 is a qubit)
-__device__ __forceinline__ int check_lanes(const Ctx& c, bool q0t) {
+template <class V>
+__device__ __forceinline__ int check_lanes(const Ctx<V>& c, bool q0t) {
   int m = 0;
   for (int i = 0; i < c.kp; ++i)
     if (!(q0t ^ (i & 1))) m |= 1 << pshift(c.kp, i);
@@ -203,23 +248,23 @@ __device__ __forceinline__ int check_lanes(const Ctx& c, bool q0t) {
 
 // Sum over the variables of the checks whose out-leg leaves the grid (lane bits oa): the result sits at
 // those bits = 0.
-template <int N>
-__device__ __forceinline__ void project_out_edge(float (&Y)[N], const Ctx& c, int oa) {
+template <class V, int N>
+__device__ __forceinline__ void project_out_edge(V (&Y)[N], const Ctx<V>& c, int oa) {
   for (int b = 1; b < 64; b <<= 1) {
     if (!(oa & b)) continue;
     const bool zero = (c.h & b) != 0;
     sfor<N>([&](auto e) {
-      const float o = xchg_rt(Y[e], b);
-      Y[e] = zero ? 0.0f : Y[e] + o;
+      const V o = xchg_rt(Y[e], b);
+      Y[e] = zero ? splat<V>(0.0f) : Y[e] + o;
     });
   }
 }
 
 // --------------------------------------------------------------------------------- column, kp >= 2
-template <int KT, bool TOP, bool BOT, bool Q00, int T>
-__device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
-                                             float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx& c,
-                                             float sc) {
+template <class V, int KT, bool TOP, bool BOT, bool Q00, int T>
+__device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
+                                             V (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx<V>& c,
+                                             V sc) {
   using CT = Cap<TOP, KT, T>;
   using CB = Cap<BOT, KT, T>;
   constexpr int PTO = CT::PO, PTN = CT::PN, PSO = CB::PO, PSN = CB::PN;
@@ -230,21 +275,21 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
   const bool out_abs = (T == KT - 1) && (c.geo & GEO_OUT_EDGE);
   const bool last_q = Q0 ^ ((kp - 1) & 1);   // the last position is a qubit
   // the pending scale goes into the first qubit transform of the column
-  const float sc0 = Q0 ? sc : 1.0f;
-  const float sc1 = (!Q0 && kp >= 3) ? sc : 1.0f;
-  const float scl = (!Q0 && kp == 2) ? sc : 1.0f;
-  auto mt = [&](auto idx) { return readlane_f(c.mtv, idx); };
-  auto mb = [&](auto idx) { return readlane_f(c.mbv, idx); };
+  const V one = splat<V>(1.0f);
+  const V sc0 = Q0 ? sc : one;
+  const V sc1 = (!Q0 && kp >= 3) ? sc : one;
+  const V scl = (!Q0 && kp == 2) ? sc : one;
+  auto mt = [&](auto idx) { return readlane_v(c.mtv, idx); };
+  auto mb = [&](auto idx) { return readlane_v(c.mbv, idx); };
 
   // ---- top cap + site 0 (lane bit 0)
-  float Z[PTN * PSO];
+  V Z[PTN * PSO];
   if constexpr (Q0) {
-    const int lb = label_at(c, T, 0);
     const int ho = bit(h, 0), vo = bit(h, pshift(kp, 1));
-    const QC q0 = qcoef(c, lb, swap, vo, ho, in_abs, out_abs, sc0);
-    QC q1 = qcoef(c, lb, swap, vo ^ 1, ho, in_abs, out_abs, sc0);
-    if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = 0.0f;
-    if constexpr (CT::kind == K_EQ && PTN == 4) {
+    const QC<V> q0 = qcoefs(c, T, 0, swap, vo, ho, in_abs, out_abs, sc0);
+    QC<V> q1 = qcoefs(c, T, 0, swap, vo ^ 1, ho, in_abs, out_abs, sc0);
+    if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = splat<V>(0.0f);
+    if constexpr (std::is_same<V, float>::value && CT::kind == K_EQ && PTN == 4) {
       float mA[PTO][2];
       sfor<PTO>([&](auto a) {
         mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
@@ -253,7 +298,7 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       sfor<PSO>([&](auto s) {
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         sfor<PTO>([&](auto a) {
-          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          const V x = X[a * PSO + s], xf = xchg<1>(x);
           acc = mfma4(mA[a][0], q0.cs * x + q0.cf * xf, acc);
           acc = mfma4(mA[a][1], q1.cs * x + q1.cf * xf, acc);
         });
@@ -264,11 +309,11 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       // is dead once its partner values are formed
       sfor<PTO>([&](auto a) {
         sfor<PSO>([&](auto s) {
-          const float x = X[a * PSO + s], xf = xchg<1>(x);
-          const float y0 = q0.cs * x + q0.cf * xf, y1 = q1.cs * x + q1.cf * xf;
+          const V x = X[a * PSO + s], xf = xchg<1>(x);
+          const V y0 = q0.cs * x + q0.cf * xf, y1 = q1.cs * x + q1.cf * xf;
           sfor<PTN>([&](auto n) {
-            float& z = Z[n * PSO + s];
-            const float t = mt(std::integral_constant<int, CT::idx(a, 0, n)>{}) * y0;
+            V& z = Z[n * PSO + s];
+            const V t = mt(std::integral_constant<int, CT::idx(a, 0, n)>{}) * y0;
             z = (a == 0) ? t : z + t;
             z += mt(std::integral_constant<int, CT::idx(a, 1, n)>{}) * y1;
           });
@@ -276,11 +321,11 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       });
     } else {
       sfor<PSO>([&](auto s) {
-        float y0[PTO], y1[PTO];
+        V y0[PTO], y1[PTO];
         sfor<PTO>([&](auto a) {
-          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          const V x = X[a * PSO + s], xf = xchg<1>(x);
           y0[a] = q0.cs * x + q0.cf * xf;
-          y1[a] = (CT::kind != K_NONE) ? q1.cs * x + q1.cf * xf : 0.0f;
+          y1[a] = (CT::kind != K_NONE) ? q1.cs * x + q1.cf * xf : splat<V>(0.0f);
         });
         sfor<PTN>([&](auto n) {
           Z[n * PSO + s] = phi2<CT, n>([&](auto a) { return y0[a]; }, [&](auto a) { return y1[a]; }, mt);
@@ -289,7 +334,7 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     }
   } else {
     const bool v1 = !(c.geo & GEO_TOP_EDGE) && bit(h, 0);
-    if constexpr (CT::kind == K_EQ && PTN == 4) {
+    if constexpr (std::is_same<V, float>::value && CT::kind == K_EQ && PTN == 4) {
       float mA[PTO][2];
       sfor<PTO>([&](auto a) {
         mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
@@ -306,16 +351,16 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       });
     } else if constexpr (CT::kind == K_EQ) {
       sfor<PTO>([&](auto a) {
-        float ms[PTN];
+        V ms[PTN];
         sfor<PTN>([&](auto n) {
           // both entries read unconditionally: a lane read cannot sit under a lane-dependent branch
-          const float m0 = mt(std::integral_constant<int, CT::idx(a, 0, n)>{});
-          const float m1 = mt(std::integral_constant<int, CT::idx(a, 1, n)>{});
+          const V m0 = mt(std::integral_constant<int, CT::idx(a, 0, n)>{});
+          const V m1 = mt(std::integral_constant<int, CT::idx(a, 1, n)>{});
           ms[n] = v1 ? m1 : m0;
         });
         sfor<PSO>([&](auto s) {
           sfor<PTN>([&](auto n) {
-            const float t = ms[n] * X[a * PSO + s];
+            const V t = ms[n] * X[a * PSO + s];
             Z[n * PSO + s] = (a == 0) ? t : Z[n * PSO + s] + t;
           });
         });
@@ -323,8 +368,8 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     } else {
       sfor<PSO>([&](auto s) {
         sfor<PTN>([&](auto n) {
-          const float z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
-          const float z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
+          const V z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
+          const V z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
           Z[n * PSO + s] = v1 ? z1 : z0;
         });
       });
@@ -336,13 +381,12 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     constexpr int i = j + 1;
     if constexpr (Q0 ^ (i & 1)) {
       if (i <= kp - 2) {
-        const int lb = label_at(c, T, i);
         const int vi = bit(h, i == 1 ? 0 : i);
         const int vo = (i + 1 == kp - 1) ? bit(h, 1) : bit(h, i + 2);
-        const QC q = qcoef(c, lb, swap, vi ^ vo, bit(h, i + 1), in_abs, out_abs, i == 1 ? sc1 : 1.0f);
+        const QC<V> q = qcoefs(c, T, i, swap, vi ^ vo, bit(h, i + 1), in_abs, out_abs, i == 1 ? sc1 : one);
         sfor<PTN * PSO>([&](auto e) {
-          const float zx = xchg<(2 << i)>(Z[e]);
-          Z[e] = __builtin_fmaf(q.cf, zx, q.cs * Z[e]);
+          const V zx = xchg<(2 << i)>(Z[e]);
+          Z[e] = fmav(q.cf, zx, q.cs * Z[e]);
         });
       }
     }
@@ -350,12 +394,11 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
 
   // ---- bottom cap + last site (lane bit 1)
   if (last_q) {
-    const int lb = label_at(c, T, kp - 1);
     const int ho = bit(h, 1), vi = bit(h, pshift(kp, kp - 2));
-    const QC q0 = qcoef(c, lb, swap, vi, ho, in_abs, out_abs, scl);
-    QC q1 = qcoef(c, lb, swap, vi ^ 1, ho, in_abs, out_abs, scl);
-    if (c.geo & GEO_BOT_EDGE) q1.cs = q1.cf = 0.0f;
-    if constexpr (CB::kind == K_EQ && PSN == 4) {
+    const QC<V> q0 = qcoefs(c, T, kp - 1, swap, vi, ho, in_abs, out_abs, scl);
+    QC<V> q1 = qcoefs(c, T, kp - 1, swap, vi ^ 1, ho, in_abs, out_abs, scl);
+    if (c.geo & GEO_BOT_EDGE) q1.cs = q1.cf = splat<V>(0.0f);
+    if constexpr (std::is_same<V, float>::value && CB::kind == K_EQ && PSN == 4) {
       float mB[PSO][2];
       sfor<PSO>([&](auto b) {
         mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
@@ -373,11 +416,11 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     } else if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
         sfor<PTN>([&](auto n) {
-          const float z = Z[n * PSO + b], zf = xchg<2>(z);
-          const float y0 = q0.cs * z + q0.cf * zf, y1 = q1.cs * z + q1.cf * zf;
+          const V z = Z[n * PSO + b], zf = xchg<2>(z);
+          const V y0 = q0.cs * z + q0.cf * zf, y1 = q1.cs * z + q1.cf * zf;
           sfor<PSN>([&](auto sp) {
-            float& y = Y[n * PSN + sp];
-            const float t = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{}) * y0;
+            V& y = Y[n * PSN + sp];
+            const V t = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{}) * y0;
             y = (b == 0) ? t : y + t;
             y += mb(std::integral_constant<int, CB::idx(b, 1, sp)>{}) * y1;
           });
@@ -385,11 +428,11 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       });
     } else {
       sfor<PTN>([&](auto n) {
-        float y0[PSO], y1[PSO];
+        V y0[PSO], y1[PSO];
         sfor<PSO>([&](auto b) {
-          const float z = Z[n * PSO + b], zf = xchg<2>(z);
+          const V z = Z[n * PSO + b], zf = xchg<2>(z);
           y0[b] = q0.cs * z + q0.cf * zf;
-          y1[b] = (CB::kind != K_NONE) ? q1.cs * z + q1.cf * zf : 0.0f;
+          y1[b] = (CB::kind != K_NONE) ? q1.cs * z + q1.cf * zf : splat<V>(0.0f);
         });
         sfor<PSN>([&](auto sp) {
           Y[n * PSN + sp] = phi2<CB, sp>([&](auto b) { return y0[b]; }, [&](auto b) { return y1[b]; }, mb);
@@ -398,7 +441,7 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     }
   } else {
     const bool v1 = !(c.geo & GEO_BOT_EDGE) && bit(h, 1);
-    if constexpr (CB::kind == K_EQ && PSN == 4) {
+    if constexpr (std::is_same<V, float>::value && CB::kind == K_EQ && PSN == 4) {
       float mB[PSO][2];
       sfor<PSO>([&](auto b) {
         mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
@@ -415,15 +458,15 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
       });
     } else if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
-        float ms[PSN];
+        V ms[PSN];
         sfor<PSN>([&](auto sp) {
-          const float m0 = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{});
-          const float m1 = mb(std::integral_constant<int, CB::idx(b, 1, sp)>{});
+          const V m0 = mb(std::integral_constant<int, CB::idx(b, 0, sp)>{});
+          const V m1 = mb(std::integral_constant<int, CB::idx(b, 1, sp)>{});
           ms[sp] = v1 ? m1 : m0;
         });
         sfor<PTN>([&](auto n) {
           sfor<PSN>([&](auto sp) {
-            const float t = ms[sp] * Z[n * PSO + b];
+            const V t = ms[sp] * Z[n * PSO + b];
             Y[n * PSN + sp] = (b == 0) ? t : Y[n * PSN + sp] + t;
           });
         });
@@ -431,8 +474,8 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
     } else {
       sfor<PTN>([&](auto n) {
         sfor<PSN>([&](auto sp) {
-          const float y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
-          const float y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
+          const V y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
+          const V y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
           Y[n * PSN + sp] = v1 ? y1 : y0;
         });
       });
@@ -444,10 +487,10 @@ __device__ __forceinline__ void column_multi(const float (&X)[Cap<TOP, KT, T>::P
 // --------------------------------------------------------------------------------- column, kp == 1
 // The single site of the column meets both caps: a qubit sums both emitted bonds (the bottom one is kept
 // as an extra index between the two cap steps), a check emits its own variable on both.
-template <int KT, bool TOP, bool BOT, bool Q00, int T>
-__device__ __forceinline__ void column_single(const float (&Xin)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
-                                              float (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx& c,
-                                              float sc) {
+template <class V, int KT, bool TOP, bool BOT, bool Q00, int T>
+__device__ __forceinline__ void column_single(const V (&Xin)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
+                                              V (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx<V>& c,
+                                              V sc) {
   using CT = Cap<TOP, KT, T>;
   using CB = Cap<BOT, KT, T>;
   constexpr int PTO = CT::PO, PTN = CT::PN, PSO = CB::PO, PSN = CB::PN;
@@ -456,22 +499,22 @@ __device__ __forceinline__ void column_single(const float (&Xin)[Cap<TOP, KT, T>
   const int swap = ((c.geo & GEO_SWAP0) ? 1 : 0) ^ (T & 1);
   const bool in_abs = (T == 0) && (c.geo & GEO_IN_EDGE);
   const bool out_abs = (T == KT - 1) && (c.geo & GEO_OUT_EDGE);
-  auto mt = [&](auto idx) { return readlane_f(c.mtv, idx); };
-  auto mb = [&](auto idx) { return readlane_f(c.mbv, idx); };
-  float X[PTO * PSO];
-  sfor<PTO * PSO>([&](auto e) { X[e] = Xin[e] * sc; });
+  auto mt = [&](auto idx) { return readlane_v(c.mtv, idx); };
+  auto mb = [&](auto idx) { return readlane_v(c.mbv, idx); };
+  V X[PTO * PSO];
+  sfor<PTO * PSO>([&](auto e) { X[e] = Xin[e] * sc; });   // no qubit transform may follow: scale here
   if constexpr (Q0) {
-    const int lb = label_at(c, T, 0);
-    float Z[2][PTN * PSO];   // [emitted bottom bond][np][s]
+    const V one = splat<V>(1.0f), zero = splat<V>(0.0f);
+    V Z[2][PTN * PSO];   // [emitted bottom bond][np][s]
     sfor<2>([&](auto vb) {
-      QC q0 = qcoef(c, lb, swap, vb, ho, in_abs, out_abs, 1.0f);       // emitted top bond 0
-      QC q1 = qcoef(c, lb, swap, vb ^ 1, ho, in_abs, out_abs, 1.0f);   // emitted top bond 1
-      if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = 0.0f;
-      if (vb == 1 && (c.geo & GEO_BOT_EDGE)) q0.cs = q0.cf = q1.cs = q1.cf = 0.0f;
+      QC<V> q0 = qcoefs(c, T, 0, swap, vb, ho, in_abs, out_abs, one);       // emitted top bond 0
+      QC<V> q1 = qcoefs(c, T, 0, swap, vb ^ 1, ho, in_abs, out_abs, one);   // emitted top bond 1
+      if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = zero;
+      if (vb == 1 && (c.geo & GEO_BOT_EDGE)) q0.cs = q0.cf = q1.cs = q1.cf = zero;
       sfor<PSO>([&](auto s) {
-        float y0[PTO], y1[PTO];
+        V y0[PTO], y1[PTO];
         sfor<PTO>([&](auto a) {
-          const float x = X[a * PSO + s], xf = xchg<1>(x);
+          const V x = X[a * PSO + s], xf = xchg<1>(x);
           y0[a] = q0.cs * x + q0.cf * xf;
           y1[a] = q1.cs * x + q1.cf * xf;
         });
@@ -488,18 +531,18 @@ __device__ __forceinline__ void column_single(const float (&Xin)[Cap<TOP, KT, T>
     });
   } else {
     const bool vt = !(c.geo & GEO_TOP_EDGE) && ho, vb = !(c.geo & GEO_BOT_EDGE) && ho;
-    float Z[PTN * PSO];
+    V Z[PTN * PSO];
     sfor<PSO>([&](auto s) {
       sfor<PTN>([&](auto n) {
-        const float z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
-        const float z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
+        const V z0 = phi<CT, n, 0>([&](auto a) { return X[a * PSO + s]; }, mt);
+        const V z1 = phi<CT, n, 1>([&](auto a) { return X[a * PSO + s]; }, mt);
         Z[n * PSO + s] = vt ? z1 : z0;
       });
     });
     sfor<PTN>([&](auto n) {
       sfor<PSN>([&](auto sp) {
-        const float y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
-        const float y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
+        const V y0 = phi<CB, sp, 0>([&](auto b) { return Z[n * PSO + b]; }, mb);
+        const V y1 = phi<CB, sp, 1>([&](auto b) { return Z[n * PSO + b]; }, mb);
         Y[n * PSN + sp] = vb ? y1 : y0;
       });
     });
@@ -510,39 +553,39 @@ __device__ __forceinline__ void column_single(const float (&Xin)[Cap<TOP, KT, T>
 // ------------------------------------------------------------------------------------------ the sweep
 // Power-of-two rescale of a state with squared norm ss: returns the factor to apply and accumulates its
 // exponent.
-__device__ __forceinline__ float pow2_scale(float ss, Ctx& c) {
+template <class V>
+__device__ __forceinline__ V pow2_scale(float ss, Ctx<V>& c) {
   const int e = (ss > 0.0f && ss < INFINITY) ? (__builtin_amdgcn_frexp_expf(ss) >> 1) : 0;
   c.exp2 += e;
-  return __builtin_amdgcn_ldexpf(1.0f, -e);
+  return V{__builtin_amdgcn_ldexpf(1.0f, -e)};
 }
 
 // Absorb columns T .. KT-1 into the state X (pending scale sc); returns the final state of this lane.
-template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, int T>
-__device__ __forceinline__ float run(const float (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO], Ctx& c,
-                                     float sc) {
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, int T>
+__device__ __forceinline__ V run(const V (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO], Ctx<V>& c, V sc) {
   constexpr int NY = Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN;
-  float Y[NY];
-  if constexpr (SINGLE) column_single<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
-  else column_multi<KT, TOP, BOT, Q00, T>(X, Y, c, sc);
+  V Y[NY];
+  if constexpr (SINGLE) column_single<V, KT, TOP, BOT, Q00, T>(X, Y, c, sc);
+  else column_multi<V, KT, TOP, BOT, Q00, T>(X, Y, c, sc);
   if constexpr (T + 1 < KT) {
     if constexpr (T & 1) {
       float ss = 0.0f;
-      sfor<NY>([&](auto e) { ss += Y[e] * Y[e]; });
-      return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
+      sfor<NY>([&](auto e) { ss += tof(Y[e]) * tof(Y[e]); });
+      return run<V, KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
     } else {
-      return run<KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, 1.0f);
+      return run<V, KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, splat<V>(1.0f));
     }
   } else {
     return Y[0];
   }
 }
 
-// The whole sweep from the entering state x0 (one value per lane). SINGLE: one position across (kp == 1);
-// Q00: the first site of the first column is a qubit.
-template <int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
-__device__ __forceinline__ float sweep(float x0, Ctx& c) {
-  const float X[1] = {x0};
-  return run<KT, TOP, BOT, SINGLE, Q00, 0>(X, c, 1.0f);
+// The whole sweep from the entering state x0 (one value per lane). SINGLE: one position across
+// (kp == 1); Q00: the first site of the first column is a qubit.
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
+__device__ __forceinline__ V sweep(V x0, Ctx<V>& c) {
+  const V X[1] = {x0};
+  return run<V, KT, TOP, BOT, SINGLE, Q00, 0>(X, c, splat<V>(1.0f));
 }
 
 }  // namespace wave
