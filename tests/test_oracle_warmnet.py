@@ -1,0 +1,130 @@
+"""Pins of the warm-start oracle (oracle/warmnet.py): finite-difference gradients on tiny networks,
+the adjointness of im2col / col2im, a 3x3 convolution against its definition, the head's closed form
+without pairwise terms, loss invariances and the input channels."""
+import numpy as np
+import pytest
+
+from oracle import blockbp, warmnet
+from paper_2402_04834_amd import workload
+
+TINY = (3, 4, 2)
+
+
+def _job(d, p=0.1, k=3, seed=0):
+    _, syn = workload.make_batch(d, p, 1, workload="warm", p_index=seed)
+    lab = warmnet.job_labels(d, syn[0])
+    X0 = warmnet.features(d, lab[seed % 4], syn[0], p)
+    return X0, blockbp.Plan(d, k, k), syn[0], lab
+
+
+def test_input_channels():
+    d = 5
+    X0, _, syn, lab = _job(d)
+    kinds = X0[..., 3] + X0[..., 4] + X0[..., 5]
+    assert np.all(kinds == 1.0)
+    assert X0[..., 2].sum() == syn.sum()
+    L = 2 * d - 1
+    for r in range(L):
+        for c in range(L):
+            if (r + c) % 2 == 0:
+                assert X0[r, c, 0] + 2 * X0[r, c, 1] == lab[0, r, c]
+    assert np.all(X0[..., 7] == 1.0) and np.allclose(X0[..., 6], 0.1)
+
+
+def test_im2col_col2im_adjoint():
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(7, 7, 3))
+    G = rng.normal(size=(49, 27))
+    assert np.isclose((warmnet.im2col(X) * G).sum(), (X * warmnet.col2im(G, 7, 3)).sum())
+
+
+def test_conv_matches_definition():
+    rng = np.random.default_rng(2)
+    L, ci, co = 5, 2, 3
+    X = rng.normal(size=(L, L, ci))
+    W = rng.normal(size=(9 * ci, co))
+    b = rng.normal(size=co)
+    Y = warmnet.conv(X, W, b)
+    for r in range(L):
+        for c in range(L):
+            for o in range(co):
+                acc = b[o]
+                for dy in range(3):
+                    for dx in range(3):
+                        rr, cc = r + dy - 1, c + dx - 1
+                        if 0 <= rr < L and 0 <= cc < L:
+                            for i in range(ci):
+                                acc += X[rr, cc, i] * W[(dy * 3 + dx) * ci + i, o]
+                assert np.isclose(Y[r, c, o], acc)
+
+
+def test_head_without_pairwise_terms_is_a_product():
+    # with Wp = bp = 0 the message is the normalised Kronecker product of the legs' exp(u_i)
+    rng = np.random.default_rng(3)
+    d, plan = 5, blockbp.Plan(5, 3, 3)
+    theta = rng.normal(size=warmnet.count(TINY)) * 0.3
+    prm = warmnet.unpack(theta, TINY)
+    for k in range(4):
+        prm[f"head{k}.Wp"][:] = 0.0
+        prm[f"head{k}.bp"][:] = 0.0
+    X0, _, _, _ = _job(d)
+    F, _ = warmnet.trunk(prm, X0)
+    e = 0
+    lg = warmnet.legs(d, plan, e)
+    direction = warmnet.direction_of(plan, e)
+    m = warmnet.head_message(prm, F, lg, direction)
+    v = np.ones(1)
+    for a, b in lg:
+        u = np.concatenate([F[a], F[b]]) @ prm[f"head{direction}.Wu"] + prm[f"head{direction}.bu"]
+        v = np.kron(v, np.exp(u))
+    np.testing.assert_allclose(m, v / np.linalg.norm(v), rtol=1e-12)
+
+
+def test_legs_cross_the_boundary():
+    d = 7
+    plan = blockbp.Plan(d, 4, 4)
+    for e in range(plan.M):
+        (I, J), (I2, J2), _ = plan.edges[e]
+        lg = warmnet.legs(d, plan, e)
+        assert len(lg) == plan.msg_len((I, J), (I2, J2))
+        for a, b in lg:
+            assert abs(a[0] - b[0]) + abs(a[1] - b[1]) == 1          # adjacent sites
+            inside = lambda s, B: plan.rows[B[0]][0] <= s[0] < sum(plan.rows[B[0]]) and \
+                plan.cols[B[1]][0] <= s[1] < sum(plan.cols[B[1]])
+            assert inside(a, (I, J)) and inside(b, (I2, J2))
+
+
+def test_loss_is_zero_on_its_own_prediction_and_sign_invariant():
+    rng = np.random.default_rng(4)
+    d = 5
+    X0, plan, _, _ = _job(d)
+    theta = rng.normal(size=warmnet.count(TINY)) * 0.3
+    pred = warmnet.predict(theta, X0, d, plan, TINY)
+    ids = list(range(plan.M))
+    l0, _ = warmnet.loss_and_grad(theta, X0, d, plan, pred, ids, TINY)
+    l1, _ = warmnet.loss_and_grad(theta, X0, d, plan, -pred, ids, TINY)
+    assert abs(l0) < 1e-12 and abs(l1) < 1e-12
+
+
+@pytest.mark.parametrize("d,k", [(3, 2), (5, 3)])
+def test_gradient_matches_finite_differences(d, k):
+    rng = np.random.default_rng(5 + d)
+    X0, _, _, _ = _job(d, k=k, seed=d)
+    plan = blockbp.Plan(d, k, k)
+    theta = rng.normal(size=warmnet.count(TINY)) * 0.4
+    # targets: unit vectors with positive entries, zero beyond 2^K
+    T = np.zeros((plan.M, 64))
+    for e in range(plan.M):
+        K = len(warmnet.legs(d, plan, e))
+        t = rng.uniform(0.1, 1.0, size=2 ** K)
+        T[e, :2 ** K] = t / np.linalg.norm(t)
+    ids = list(range(plan.M))
+    _, g = warmnet.loss_and_grad(theta, X0, d, plan, T, ids, TINY)
+    h = 1e-6
+    for j in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = (warmnet.loss_and_grad(tp, X0, d, plan, T, ids, TINY)[0] -
+              warmnet.loss_and_grad(tm, X0, d, plan, T, ids, TINY)[0]) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 + 1e-5 * abs(fd), (j, fd, g[j])
