@@ -162,6 +162,11 @@ typedef struct bbp_group {
   int32_t* iters_dev;             /* [batch][4] */
   uint8_t* coset_dev;             /* [batch] */
   uint8_t* correction_dev;        /* [batch][d^2 + (d-1)^2] */
+  const float* init_messages_dev; /* optional [batch][4][M][64] start messages (dense, layout of messages_dev of
+                                     bbp_decode_device), each scaled to unit norm by the decoder, entries beyond
+                                     2^K ignored, an all-zero or non-finite one replaced by the uniform start;
+                                     NULL = the uniform start of remark 2 */
+  float* messages_dev;            /* optional [batch][4][M][64] output: final messages, as in bbp_decode_device */
 } bbp_group;
 
 /* Workspace for bbp_decode_groups (the groups' own workspaces laid end to end). Output and syndrome
@@ -195,6 +200,67 @@ int bbp_set_tuning(int32_t d, const bbp_opts* opts, const bbp_tuning* tuning);
  * Allocates and frees its own device memory and synchronises. Errors as above. */
 int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts, double* loglik,
                        double* delta, int32_t* iters, uint8_t* coset, uint8_t* correction);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Learned warm start. BP of blockBP starts from uniform messages (remark 2); the paper names machine
+ * learning as a way to improve BP (Sec. V, summary and conclusions). Here a convolutional network
+ * predicts the start messages of every coset job from the local syndrome, and the decoder runs from them.
+ *
+ * Network (per coset job, on the L x L grid): 13 input channels per site (x and z bits of the coset label
+ * f_s L at qubits, the syndrome bit at checks, qubit / Z-check / X-check indicators, p, 1, the coset's x and
+ * z bits, at checks the generator bit G, r / (L-1), c / (L-1)), where G is the prefix parity of f_s L on the
+ * horizontal edges above a plaquette in its column (x part) or left of a vertex in its row (z part); three
+ * 3x3 convolutions with zero padding (13 -> 64 -> 128 -> 96 channels, ReLU after the first two) give features
+ * F; for each directed message with K legs (leg i joins site a_i of the sending block to site b_i across the
+ * boundary, leg 0 at the top / left) and f_i = [F(a_i), F(b_i)], the weights of the message's direction
+ * (E, W, S, N) give u_i = Wu^T f_i + bu (2 values) and P_i = Wp^T [f_i, f_{i+1}] + bp (4 values); the
+ * message is exp(s) scaled to unit norm, s(b) = sum_i u_i[b_i] + sum_i P_i[2 b_i + b_{i+1}] over the 2^K
+ * leg configurations b (leg 0 the most significant bit, the layout of the decoder's messages).
+ * Parameters: one float32 device array of bbp_warm_param_count() values, in the order conv1 W [117][64],
+ * b [64], conv2 W [576][128], b [128], conv3 W [1152][96], b [96], then for E, W, S, N: Wu [192][2], bu [2],
+ * Wp [384][4], bp [4]; W rows are (3 dy + dx) * C_in + c_in for the input site (r + dy - 1, c + dx - 1).
+ * Training loss of a message against a converged cold-start message t (non-negative): KL(q || p) of
+ * q = t / sum(t) and p = softmax(s).
+ * All pointers are device pointers unless stated; work is enqueued on `stream` (NULL = default stream).
+ * Errors: BBP_EINVAL (range, NULL, workspace too small), BBP_EUNSUPPORTED (blocks larger than 6),
+ * BBP_EHIP; bbp_warm_last_error() gives the message. */
+const char* bbp_warm_last_error(void);
+int bbp_warm_param_count(int64_t* count);
+
+/* Workspace of bbp_warm_predict (train = 0; bounded: the forward runs in chunks of 512 syndromes) or of
+ * bbp_warm_loss_grad (train = 1; grows with batch). */
+int bbp_warm_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, int32_t train, size_t* bytes);
+
+/* Predicted start messages of batch syndromes [batch][2d(d-1)] (noise rate p, or p_dev [batch] when not
+ * NULL): messages_dev [batch][4][M][64], unit norm, zero beyond 2^K (M and K as in bbp_plan_query). */
+int bbp_warm_predict(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
+                     const bbp_opts* opts, const float* params_dev, float* messages_dev, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Loss and gradient of the network on a training batch: targets_dev [batch][4][M][64] (converged messages,
+ * non-negative, entries beyond 2^K ignored), use_dev [batch * 4] (1 = train on every message of that coset
+ * job), trained_messages = M times the number of used jobs. loss_dev[0] = sum over used messages of
+ * KL(q || p) / trained_messages; grad_dev (param_count floats) receives its gradient (overwritten). */
+int bbp_warm_loss_grad(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
+                       const bbp_opts* opts, const float* params_dev, const float* targets_dev,
+                       const uint8_t* use_dev, int64_t trained_messages, float* grad_dev, float* loss_dev,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step >= 1) on the parameters; m_dev
+ * and v_dev are the moment arrays (param_count floats each, zero before step 1). */
+int bbp_warm_adam(float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int64_t step, float lr,
+                  void* stream);
+
+/* Warm-started decode with cold fallback: the network's messages start BP (bbp_group.init_messages_dev);
+ * every syndrome with a coset whose final distance is not below opts->delta1 is decoded again from the
+ * uniform start, and its results replace the warm ones (its iteration counts are the sum of both runs).
+ * Outputs as bbp_decode_device; *fallback_count (host, may be NULL) receives the number of reruns. The call
+ * synchronises `stream` once (to size the fallback batch). */
+int bbp_warm_decode_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* bytes);
+int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
+                    const bbp_opts* opts, const float* params_dev, void* workspace, size_t workspace_bytes,
+                    double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
+                    uint8_t* correction_dev, int64_t* fallback_count, void* stream);
 
 /* ---------------------------------------------------------------------------------------------------
  * Validation hook (host, float64): evaluates the block message update that produces message `msg_id`

@@ -1,15 +1,22 @@
 """FP64 oracle of the learned warm start (test infrastructure only: tests/, the smoke check and the
 benchmark's CPU baseline import it; the decoder never does).
 
-The network predicts, from the local syndrome, the initial messages of blockBP (the uniform start of
-Alg. 1 and remark 2 is what it replaces). Plain NumPy, generic channel counts so that tests can use tiny
-networks; every step is written out directly (no blocking or fusion).
+The network predicts, from the syndrome, the initial messages of blockBP (the uniform start of Alg. 1,
+remark 2, is what it replaces; the paper names machine learning as a way to improve BP in Sec. V). Plain
+NumPy, generic channel counts so that tests can use tiny networks; every step is written out directly (no
+blocking or fusion).
 
-Input, per coset job, a (2d-1) x (2d-1) grid with 8 channels per site:
+Input, per coset job, a (2d-1) x (2d-1) grid with 13 channels per site:
   0 x bit and 1 z bit of the coset label f_s L at qubit sites (0 at checks),
   2 syndrome bit at check sites (0 at qubits),
   3 qubit, 4 Z-check (even row, odd column), 5 X-check (odd row, even column) indicators,
-  6 the noise rate p, 7 constant 1 (marks the inside of the grid against the zero padding).
+  6 the noise rate p, 7 constant 1 (marks the inside of the grid against the zero padding),
+  8, 9 the coset's x and z bits (1 for X and Y, 1 for Y and Z),
+  10 at check sites the generator bit G: for a plaquette (X-check) at (r, c) the parity of the x bits of
+     f_s L on the horizontal edges above it in column c, for a vertex (Z-check) at (r, c) the parity of
+     the z bits of f_s L on the horizontal edges left of it in row r (the generators that clear f_s L from
+     the horizontal edges except the last row / column),
+  11 r / (L-1), 12 c / (L-1).
 Three 3x3 convolutions with zero padding, ReLU after the first two, give features F [L, L, C3].
 
 Message head, per directed message u -> v with K legs (the crossing bonds of the boundary, position 0 at
@@ -19,8 +26,9 @@ direction's weights,
   pairwise  P_i = Wp^T [f_i, f_{i+1}] + bp          (4 values, index 2 b_i + b_{i+1})
   s(b) = sum_i u_i[b_i] + sum_i P_i[b_i, b_{i+1}],  m(b) = exp(s(b)) / ||exp(s)||_2
 over the 2^K leg configurations b (dense index with leg 0 most significant, as the messages of the
-decoder). Loss of a message against its converged target t (unit vector): 1 - <m, t>^2 (invariant to the
-sign and scale of either vector); the training loss is the mean over messages.
+decoder). Loss of a message against its converged target t (non-negative): KL(q || p) with q = t / sum(t)
+and p = softmax(s) (invariant to the scale of t; zero when t is proportional to the prediction); the
+training loss is the mean over messages.
 
 Parameter vector (FP32 on the GPU, float64 here), in this order:
   conv1 W [9*C0][C1] (row (dy*3 + dx)*C0 + ci), b [C1]; conv2 W [9*C1][C2], b [C2]; conv3 W [9*C2][C3], b [C3];
@@ -30,7 +38,7 @@ from __future__ import annotations
 
 import numpy as np
 
-C0 = 8
+C0 = 13
 CHANNELS = (64, 128, 96)   # C1, C2, C3 of the network the GPU trains
 
 
@@ -60,25 +68,35 @@ def pack(parts, ch=CHANNELS):
     return np.concatenate([np.asarray(parts[n], dtype=np.float64).ravel() for n, _ in sizes(ch)])
 
 
-def features(d, labels, syndrome, p):
-    """Input grid [L, L, 8] of one coset job: labels [L, L] (bit 0 x, bit 1 z), syndrome [m] (0/1)."""
+def features(d, syndrome, p, coset):
+    """Input grid [L, L, 13] of coset job `coset` (0..3 = I, X, Y, Z) of a syndrome [m] (0/1)."""
+    from . import lattice
     L = 2 * d - 1
     nz = d * (d - 1)
+    xs, zs = lattice.coset_labels(d, np.asarray(syndrome))
+    lx, lz = np.asarray(xs[coset], dtype=np.int64), np.asarray(zs[coset], dtype=np.int64)
+    bx, bz = lattice.COSET_BITS[coset]
     X = np.zeros((L, L, C0))
     for r in range(L):
         for c in range(L):
             if (r + c) % 2 == 0:
-                X[r, c, 0] = labels[r, c] & 1
-                X[r, c, 1] = (labels[r, c] >> 1) & 1
+                X[r, c, 0] = lx[r, c]
+                X[r, c, 1] = lz[r, c]
                 X[r, c, 3] = 1.0
-            elif r % 2 == 0:          # Z-check
+            elif r % 2 == 0:          # Z-check (vertex)
                 X[r, c, 2] = syndrome[(r // 2) * (d - 1) + (c - 1) // 2]
                 X[r, c, 4] = 1.0
-            else:                     # X-check
+                X[r, c, 10] = sum(lz[r, cc] for cc in range(0, c, 2)) % 2
+            else:                     # X-check (plaquette)
                 X[r, c, 2] = syndrome[nz + ((r - 1) // 2) * d + c // 2]
                 X[r, c, 5] = 1.0
+                X[r, c, 10] = sum(lx[rr, c] for rr in range(0, r, 2)) % 2
             X[r, c, 6] = p
             X[r, c, 7] = 1.0
+            X[r, c, 8] = bx
+            X[r, c, 9] = bz
+            X[r, c, 11] = r / (L - 1)
+            X[r, c, 12] = c / (L - 1)
     return X
 
 
@@ -169,8 +187,8 @@ def _head_scores(prm, F, lg, direction):
 
 
 def loss_and_grad(theta, X0, d, plan, targets, msg_ids, ch=CHANNELS):
-    """Mean over msg_ids of 1 - <m_e, t_e>^2 for one coset job, and its gradient with respect to theta.
-    targets: [M, 64] dense unit messages (entries beyond 2^K ignored)."""
+    """Mean over msg_ids of KL(q_e || softmax(s_e)), q_e = t_e / sum(t_e), for one coset job, and its
+    gradient with respect to theta. targets: [M, 64] non-negative messages (entries beyond 2^K ignored)."""
     prm = unpack(theta, ch)
     F, (X0_, Z1, A1, Z2, A2) = trunk(prm, X0)
     L = F.shape[0]
@@ -182,16 +200,13 @@ def loss_and_grad(theta, X0, d, plan, targets, msg_ids, ch=CHANNELS):
         lg = legs(d, plan, e)
         K = len(lg)
         s, (f, u, P) = _head_scores(prm, F, lg, direction)
-        m = np.exp(s - s.max())
-        nrm = np.linalg.norm(m)
-        mh = m / nrm
-        t = targets[e, :2 ** K]
-        ov = float(mh @ t)
-        total += 1.0 - ov * ov
-        # d loss / d mh, then through the normalisation and the exponential
-        g_mh = -2.0 * ov * t
-        g_m = (g_mh - (g_mh @ mh) * mh) / nrm
-        g_s = g_m * m
+        logp = s - s.max() - np.log(np.exp(s - s.max()).sum())
+        q = np.maximum(targets[e, :2 ** K], 0.0)
+        q = q / q.sum()
+        nzq = q > 0
+        total += float((q[nzq] * (np.log(q[nzq]) - logp[nzq])).sum())
+        # d KL / d s = softmax(s) - q
+        g_s = np.exp(logp) - q
         gu = [np.zeros(2) for _ in range(K)]
         gP = [np.zeros(4) for _ in range(K - 1)]
         for idx in range(2 ** K):

@@ -111,12 +111,15 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     return out
 
 
-def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None, outs=None):
-    """Decode a mixed batch: `groups` is a list of (d, p, syndromes) or (d, p, syndromes, chi) with
-    syndromes a torch uint8 CUDA tensor [batch, 2d(d-1)], p a float or a float64 CUDA tensor [batch] of
-    per-syndrome noise rates, and chi the group's bond dimension (default opts.chi). Returns (list of
+def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None, outs=None,
+                  messages: bool = False):
+    """Decode a mixed batch: `groups` is a list of (d, p, syndromes[, chi[, init]]) with syndromes a torch
+    uint8 CUDA tensor [batch, 2d(d-1)], p a float or a float64 CUDA tensor [batch] of per-syndrome noise
+    rates, chi the group's bond dimension (0 or absent: opts.chi) and init optional start messages (float32
+    CUDA tensor [batch, 4, M, 64], e.g. from warm.predict; None: the uniform start). Returns (list of
     per-group output dicts as in decode_device, workspace, bbp_timing or None). `outs` (from an earlier
-    call with the same groups) receives the results in place, keeping graph-mode arguments identical."""
+    call with the same groups) receives the results in place, keeping graph-mode arguments identical.
+    messages=True adds each group's final messages [batch, 4, M, 64] as 'messages'."""
     import torch
 
     gs = (bbp_group * len(groups))()
@@ -126,6 +129,7 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
     for k, grp in enumerate(groups):
         d, p, syn = grp[:3]
         chi = grp[3] if len(grp) > 3 else 0
+        init = grp[4] if len(grp) > 4 else None
         assert syn.is_cuda and syn.dtype == torch.uint8 and syn.dim() == 2
         syn = syn.contiguous()
         keep.append(syn)
@@ -139,8 +143,21 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
             p_ptr, p_val = p.data_ptr(), 0.0
         o = outs_in[k] if outs_in is not None else _outputs(b, d * d + (d - 1) * (d - 1), dev)
         outs.append(o)
+        init_ptr = None
+        if init is not None:
+            assert init.is_cuda and init.dtype == torch.float32 and init.shape[0] == b and init.shape[1] == 4
+            init = init.contiguous()
+            keep.append(init)
+            init_ptr = init.data_ptr()
+        msg_ptr = None
+        if messages:
+            if "messages" not in o:
+                o["messages"] = torch.empty((b, 4, max(plan_query(d, _with_chi(opts, chi)).num_messages, 1), 64),
+                                            dtype=torch.float32, device=dev)
+            msg_ptr = o["messages"].data_ptr()
         gs[k] = bbp_group(d, chi, p_val, p_ptr, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),
-                          o["iters"].data_ptr(), o["coset"].data_ptr(), o["correction"].data_ptr())
+                          o["iters"].data_ptr(), o["coset"].data_ptr(), o["correction"].data_ptr(), init_ptr,
+                          msg_ptr)
     n = C.c_size_t()
     _lib.check(_lib.lib().bbp_workspace_size_groups(gs, len(groups), C.byref(opts), C.byref(n)))
     if workspace is None or workspace.numel() < n.value:
@@ -150,6 +167,13 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
     _lib.check(_lib.lib().bbp_decode_groups(gs, len(groups), C.byref(opts), workspace.data_ptr(),
                                             workspace.numel(), st, C.byref(tm) if tm is not None else None))
     return outs, workspace, tm
+
+
+def _with_chi(opts: bbp_opts, chi: int) -> bbp_opts:
+    o = bbp_opts.from_buffer_copy(opts)
+    if chi:
+        o.chi = chi
+    return o
 
 
 def autotune(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None, stream=None) -> bbp_tuning:

@@ -31,7 +31,8 @@ class bbp_group(C.Structure):
         ("d", C.c_int32), ("chi", C.c_int32), ("p", C.c_double), ("p_dev", C.c_void_p),
         ("syndromes_dev", C.c_void_p), ("batch", C.c_int64),
         ("loglik_dev", C.c_void_p), ("delta_dev", C.c_void_p), ("iters_dev", C.c_void_p),
-        ("coset_dev", C.c_void_p), ("correction_dev", C.c_void_p),
+        ("coset_dev", C.c_void_p), ("correction_dev", C.c_void_p), ("init_messages_dev", C.c_void_p),
+        ("messages_dev", C.c_void_p),
     ]
 
 
@@ -88,6 +89,20 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "bbp_reference_update_host": (C.c_int, [C.c_int32, C.c_double, C.POINTER(bbp_opts), C.c_void_p, C.c_int32,
                                             C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "bbp_warm_last_error": (C.c_char_p, []),
+    "bbp_warm_param_count": (C.c_int, [C.POINTER(C.c_int64)]),
+    "bbp_warm_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(bbp_opts), C.c_int32,
+                                          C.POINTER(C.c_size_t)]),
+    "bbp_warm_predict": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bbp_warm_loss_grad": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bbp_warm_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
+    "bbp_warm_decode_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(bbp_opts), C.POINTER(C.c_size_t)]),
+    "bbp_warm_decode": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
+                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
 }
 
 _lib = None
@@ -117,6 +132,13 @@ class BbpError(RuntimeError):
 def check(rc):
     if rc != BBP_OK:
         raise BbpError(rc, lib().bbp_last_error().decode())
+    return rc
+
+
+def check_warm(rc):
+    """check() for the warm-start entry points, which keep their own error message."""
+    if rc != BBP_OK:
+        raise BbpError(rc, lib().bbp_warm_last_error().decode())
     return rc
 
 

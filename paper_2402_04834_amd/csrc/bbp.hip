@@ -2,7 +2,7 @@
 //
 // Data path for a batch of syndromes (one "job" = one syndrome x one coset, job = 4*syndrome + coset):
 //   labels_kernel     syndrome -> f_s (left/up check chains) -> coset labels f_s L on the grid (Alg. 1)
-//   init_kernel       uniform unit messages (remark 2), convergence flags cleared
+//   init_kernel       uniform unit messages (remark 2) or given start messages, convergence flags cleared
 //   sweep_kernel      block message updates, one wavefront per (job, sweep), launched per sweep class
 //                     (sweep_kernel.hip, wave_sweep.hpp): Sec. III.D update, normalisation (remark 3),
 //                     damping (remark 7), distance term (remark 4)
@@ -76,13 +76,27 @@ __global__ __launch_bounds__(256) void labels_kernel(const uint8_t* __restrict__
   }
 }
 
-__global__ void init_kernel(float* __restrict__ msgs, const int32_t* __restrict__ edge_len, int M, int64_t jobs,
-                            int32_t* __restrict__ conv, int32_t* __restrict__ iters) {
+// start messages: uniform unit vectors (remark 2), or the given ones (a learned warm start) scaled to unit
+// norm with the entries beyond 2^K cleared; one workgroup per job, one wavefront per message
+__global__ __launch_bounds__(256) void init_kernel(float* __restrict__ msgs, const float* __restrict__ given,
+                                                   const int32_t* __restrict__ edge_len, int M, int64_t jobs,
+                                                   int32_t* __restrict__ conv, int32_t* __restrict__ iters) {
   const int64_t job = blockIdx.x;
-  for (int e = threadIdx.x; e < M * MSTRIDE; e += blockDim.x) {
-    const int id = e / MSTRIDE, h = e % MSTRIDE;
+  const int lane = threadIdx.x & 63;
+  for (int id = threadIdx.x >> 6; id < M; id += blockDim.x >> 6) {
     const int K = edge_len[id];
-    msgs[job * M * MSTRIDE + e] = (h < (1 << K)) ? exp2f(-0.5f * K) : 0.0f;
+    const bool in = lane < (1 << K);
+    const int64_t at = (job * M + id) * MSTRIDE + lane;
+    float v;
+    if (given) {
+      const float g = in ? given[at] : 0.0f;
+      float ss = g * g;
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      v = (ss > 0.0f && ss < INFINITY) ? g * __builtin_amdgcn_rsqf(ss) : (in ? exp2f(-0.5f * K) : 0.0f);
+    } else {
+      v = in ? exp2f(-0.5f * K) : 0.0f;
+    }
+    msgs[at] = v;
   }
   if (threadIdx.x == 0) {
     conv[job] = 0;
@@ -264,15 +278,7 @@ int validate(int32_t d, const bbp_opts* o) {
   return BBP_OK;
 }
 
-const bbp::Plan& host_plan(int d, const bbp_opts* o) {
-  static std::map<std::tuple<int, int, int, int>, bbp::Plan> cache;
-  static std::mutex mu;
-  std::lock_guard<std::mutex> lk(mu);
-  auto key = std::make_tuple(d, o->block_rows, o->block_cols, o->chi);
-  auto it = cache.find(key);
-  if (it == cache.end()) it = cache.emplace(key, bbp::make_plan(d, o->block_rows, o->block_cols, o->chi)).first;
-  return it->second;
-}
+const bbp::Plan& host_plan(int d, const bbp_opts* o) { return bbp::cached_plan(d, o->block_rows, o->block_cols, o->chi); }
 
 int device_plan(int d, const bbp_opts* o, DevPlan** out) {
   int dev = 0;
@@ -436,7 +442,7 @@ struct Mark {
 };
 
 // Enqueue the whole decode of the groups on st (and the auxiliary streams of the tune).
-int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, float* messages_dev, hipStream_t st,
+int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hipStream_t st,
             Aux* aux, std::vector<Mark>* marks) {
   const int ng = (int)gr.size();
   // consecutive launches on one stream share their boundary event (an event record is a queue packet)
@@ -474,8 +480,8 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, flo
     if (g.in.batch == 0) continue;
     if ((rc = begin_mark(st, 0, -1, -1))) return rc;
     labels_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(g.in.syndromes_dev, g.in.d, g.in.batch, g.labels);
-    init_kernel<<<dim3((unsigned)g.jobs), dim3(256), 0, st>>>(g.msgs, g.dp->edge_len, g.dp->plan.M, g.jobs, g.conv,
-                                                              g.iters);
+    init_kernel<<<dim3((unsigned)g.jobs), dim3(256), 0, st>>>(g.msgs, g.in.init_messages_dev, g.dp->edge_len,
+                                                              g.dp->plan.M, g.jobs, g.conv, g.iters);
     HIP_TRY(hipGetLastError());
     if ((rc = end_mark(st))) return rc;
   }
@@ -573,9 +579,10 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, flo
     HIP_TRY(hipGetLastError());
     if ((rc = end_mark(st))) return rc;
   }
-  if (messages_dev)
-    HIP_TRY(hipMemcpyAsync(messages_dev, gr[0].msgs, (size_t)gr[0].jobs * gr[0].dp->plan.M * MSTRIDE * sizeof(float),
-                           hipMemcpyDeviceToDevice, st));
+  for (auto& g : gr)
+    if (g.in.messages_dev && g.in.batch > 0 && g.dp->plan.M > 0)
+      HIP_TRY(hipMemcpyAsync(g.in.messages_dev, g.msgs, (size_t)g.jobs * g.dp->plan.M * MSTRIDE * sizeof(float),
+                             hipMemcpyDeviceToDevice, st));
   return BBP_OK;
 }
 
@@ -634,7 +641,7 @@ uint64_t u64(T v) {
 }
 
 int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* workspace, size_t workspace_bytes,
-                  float* messages_dev, void* stream, bbp_timing* timing, const Tune* force) {
+                  void* stream, bbp_timing* timing, const Tune* force) {
   std::vector<GroupRun> gr;
   size_t total = 0;
   int rc = resolve(groups, ng, opts, gr, &total, true);
@@ -658,7 +665,6 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     g.delta = (double*)(ws + g.lay.delta);
   }
   if (!any) return BBP_OK;
-  if (messages_dev && (ng != 1)) return fail(BBP_EINVAL, "messages are returned for one group only");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Tune tn;
@@ -675,19 +681,19 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
 
   if (timing) {
     std::vector<Mark> marks;
-    rc = enqueue(gr, opts, tn, messages_dev, st, aux, &marks);
+    rc = enqueue(gr, opts, tn, st, aux, &marks);
     if (rc == BBP_OK) {
       if (hipStreamSynchronize(st) != hipSuccess) rc = fail(BBP_EHIP, "stream synchronisation failed");
       else rc = collect_timing(gr, opts, marks, timing);
     }
     return rc;
   }
-  if (!opts->graph) return enqueue(gr, opts, tn, messages_dev, st, aux, nullptr);
+  if (!opts->graph) return enqueue(gr, opts, tn, st, aux, nullptr);
 
   // graph mode: capture the decode once per argument set, replay it afterwards
   if (!st) return fail(BBP_EINVAL, "graph mode needs a stream other than the default stream");
   std::vector<uint64_t> key = {(uint64_t)dev, (uint64_t)ng, u64(workspace), (uint64_t)workspace_bytes,
-                               u64(messages_dev), u64(st), (uint64_t)tn.order, (uint64_t)tn.streams};
+                               u64(st), (uint64_t)tn.order, (uint64_t)tn.streams};
   const bbp_opts o = *opts;
   key.insert(key.end(), {(uint64_t)o.block_rows, (uint64_t)o.block_cols, (uint64_t)o.chi, (uint64_t)o.max_iter,
                          u64(o.delta0), u64(o.delta1), u64(o.damping), (uint64_t)o.rule, (uint64_t)o.fixed_iters,
@@ -696,7 +702,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     key.insert(key.end(), {(uint64_t)g.in.d, (uint64_t)g.opts.chi, u64(g.in.p), u64(g.in.p_dev),
                            u64(g.in.syndromes_dev), (uint64_t)g.in.batch,
                            u64(g.in.loglik_dev), u64(g.in.delta_dev), u64(g.in.iters_dev), u64(g.in.coset_dev),
-                           u64(g.in.correction_dev)});
+                           u64(g.in.correction_dev), u64(g.in.init_messages_dev), u64(g.in.messages_dev)});
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -705,7 +711,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
   }
   if (!exec) {
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    rc = enqueue(gr, opts, tn, messages_dev, st, aux, nullptr);
+    rc = enqueue(gr, opts, tn, st, aux, nullptr);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &graph);
     if (rc) {
@@ -838,7 +844,7 @@ int bbp_workspace_size_groups(const bbp_group* groups, int32_t ngroups, const bb
 
 int bbp_decode_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, void* workspace,
                       size_t workspace_bytes, void* stream, bbp_timing* timing) {
-  return decode_groups(groups, ngroups, opts, workspace, workspace_bytes, nullptr, stream, timing, nullptr);
+  return decode_groups(groups, ngroups, opts, workspace, workspace_bytes, stream, timing, nullptr);
 }
 
 int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch, const bbp_opts* opts,
@@ -856,7 +862,8 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
   g.iters_dev = iters_dev;
   g.coset_dev = coset_dev;
   g.correction_dev = correction_dev;
-  return decode_groups(&g, 1, opts, workspace, workspace_bytes, messages_dev, stream, timing, nullptr);
+  g.messages_dev = messages_dev;
+  return decode_groups(&g, 1, opts, workspace, workspace_bytes, stream, timing, nullptr);
 }
 
 int bbp_set_tuning(int32_t d, const bbp_opts* opts, const bbp_tuning* t) {
@@ -908,11 +915,11 @@ int bbp_autotune(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batc
       Tune tn;
       tn.order = orders[oi];
       tn.streams = streams[si];
-      rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, nullptr, st, nullptr, &tn);   // warm-up
+      rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, st, nullptr, &tn);   // warm-up
       if (rc) break;
       if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(BBP_EHIP, "event record"); break; }
       for (int rep = 0; rep < 2 && rc == BBP_OK; ++rep)
-        rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, nullptr, st, nullptr, &tn);
+        rc = decode_groups(&g, 1, &o, workspace, workspace_bytes, st, nullptr, &tn);
       if (rc) break;
       float ms = 0.0f;
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1005,7 +1012,7 @@ int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts
   }
   bbp_opts o = *opts;
   o.graph = 0;
-  rc = decode_groups(groups.data(), ng, &o, ws, wsb, nullptr, nullptr, nullptr, nullptr);
+  rc = decode_groups(groups.data(), ng, &o, ws, wsb, nullptr, nullptr, nullptr);
   if (rc == BBP_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(BBP_EHIP, "decode failed");
   std::memset(correction, 0, (size_t)batch * nmax);
   for (int g = 0; g < ng && rc == BBP_OK; ++g) {

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 
 #include "geom.hpp"
@@ -500,6 +501,16 @@ int host_sweep(const Plan& p, const SweepDesc& s, const uint8_t* labels, const f
   for (int h = 0; h < H; ++h) out[h] = A[h] * scale;
   *logscale = ls;
   return 0;
+}
+
+const Plan& cached_plan(int d, int kr, int kc, int chi) {
+  static std::map<std::tuple<int, int, int, int>, Plan> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(d, kr, kc, chi);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, make_plan(d, kr, kc, chi)).first;
+  return it->second;
 }
 
 }  // namespace bbp

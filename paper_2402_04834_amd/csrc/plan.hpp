@@ -42,6 +42,9 @@ struct Plan {
 // Build the plan (and run the rank analysis) for distance d, blocks kr x kc, bond chi.
 Plan make_plan(int d, int kr, int kc, int chi);
 
+// make_plan, cached per (d, kr, kc, chi) for the life of the process (thread-safe).
+const Plan& cached_plan(int d, int kr, int kc, int chi);
+
 // Host-side reference of one block sweep in float64 with the GPU's index arithmetic (used only by the
 // self-check entry point). labels: L*L grid bytes; msgs: dense messages (stride 64) indexed by id.
 int host_sweep(const Plan& plan, const SweepDesc& s, const uint8_t* labels, const float* pi,

@@ -62,17 +62,29 @@ def _check_supports(d: int):
     return sup, reads_x
 
 
+_SUPPORT_TABLES = {}
+
+
+def _support_table(d: int):
+    """[m, 4] indices into the concatenation (x bits, z bits, one zero) of each check's neighbours."""
+    if d not in _SUPPORT_TABLES:
+        n = num_qubits(d)
+        sup, reads_x = _check_supports(d)
+        t = np.full((len(sup), 4), 2 * n, dtype=np.int64)
+        for i, (nb, rx) in enumerate(zip(sup, reads_x)):
+            t[i, :len(nb)] = np.asarray(nb, dtype=np.int64) + (0 if rx else n)
+        _SUPPORT_TABLES[d] = t
+    return _SUPPORT_TABLES[d]
+
+
 def syndrome_of(d: int, errors: np.ndarray) -> np.ndarray:
-    """Syndrome bits [..., m] of Pauli errors [..., n] coded x + 2z."""
+    """Syndrome bits [..., m] of Pauli errors [..., n] coded x + 2z: a Z-check is the parity of the x
+    components on its neighbouring qubits, an X-check that of the z components."""
     errors = np.asarray(errors, dtype=np.uint8)
     x = errors & 1
     z = (errors >> 1) & 1
-    sup, reads_x = _check_supports(d)
-    out = np.zeros(errors.shape[:-1] + (len(sup),), dtype=np.uint8)
-    for i, (nb, rx) in enumerate(zip(sup, reads_x)):
-        src = x if rx else z
-        out[..., i] = np.bitwise_xor.reduce(src[..., nb], axis=-1)
-    return out
+    bits = np.concatenate([x, z, np.zeros(errors.shape[:-1] + (1,), dtype=np.uint8)], axis=-1)
+    return np.bitwise_xor.reduce(bits[..., _support_table(d)], axis=-1).astype(np.uint8)
 
 
 def _rng(*key: int) -> np.random.Generator:

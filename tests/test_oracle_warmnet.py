@@ -13,22 +13,56 @@ TINY = (3, 4, 2)
 def _job(d, p=0.1, k=3, seed=0):
     _, syn = workload.make_batch(d, p, 1, workload="warm", p_index=seed)
     lab = warmnet.job_labels(d, syn[0])
-    X0 = warmnet.features(d, lab[seed % 4], syn[0], p)
+    X0 = warmnet.features(d, syn[0], p, seed % 4)
     return X0, blockbp.Plan(d, k, k), syn[0], lab
 
 
 def test_input_channels():
     d = 5
-    X0, _, syn, lab = _job(d)
-    kinds = X0[..., 3] + X0[..., 4] + X0[..., 5]
-    assert np.all(kinds == 1.0)
-    assert X0[..., 2].sum() == syn.sum()
     L = 2 * d - 1
-    for r in range(L):
-        for c in range(L):
-            if (r + c) % 2 == 0:
-                assert X0[r, c, 0] + 2 * X0[r, c, 1] == lab[0, r, c]
-    assert np.all(X0[..., 7] == 1.0) and np.allclose(X0[..., 6], 0.1)
+    _, syn = workload.make_batch(d, 0.1, 1, workload="warm", p_index=0)
+    lab = warmnet.job_labels(d, syn[0])
+    for coset in range(4):
+        X0 = warmnet.features(d, syn[0], 0.1, coset)
+        kinds = X0[..., 3] + X0[..., 4] + X0[..., 5]
+        assert np.all(kinds == 1.0)
+        assert X0[..., 2].sum() == syn[0].sum()
+        for r in range(L):
+            for c in range(L):
+                if (r + c) % 2 == 0:
+                    assert X0[r, c, 0] + 2 * X0[r, c, 1] == lab[coset, r, c]
+        assert np.all(X0[..., 7] == 1.0) and np.allclose(X0[..., 6], 0.1)
+        assert np.all(X0[..., 8] == (coset in (1, 2))) and np.all(X0[..., 9] == (coset in (2, 3)))
+        assert X0[0, 0, 11] == 0 and X0[L - 1, 0, 11] == 1 and X0[0, L - 1, 12] == 1
+
+
+@pytest.mark.parametrize("d", [3, 5, 7])
+def test_generator_bits_clear_the_horizontal_edges(d):
+    """Multiplying the coset label by the plaquettes (x part) and vertices (z part) whose G bit is 1 leaves
+    no x on the horizontal edges but the last row, and no z on the horizontal edges but the last column
+    (a plaquette flips x on its 4 edges, a vertex flips z on its 4 edges)."""
+    L = 2 * d - 1
+    _, syn = workload.make_batch(d, 0.15, 4, workload="warm", p_index=77)
+    for s in syn:
+        lab = warmnet.job_labels(d, s)
+        for coset in range(4):
+            X0 = warmnet.features(d, s, 0.15, coset)
+            x = (lab[coset] & 1).copy()
+            z = ((lab[coset] >> 1) & 1).copy()
+            for r in range(L):
+                for c in range(L):
+                    if (r + c) % 2 == 0 or X0[r, c, 10] == 0:
+                        continue
+                    tgt = x if r % 2 == 1 else z
+                    for rr, cc in ((r - 1, c), (r + 1, c), (r, c - 1), (r, c + 1)):
+                        if 0 <= rr < L and 0 <= cc < L:
+                            tgt[rr, cc] ^= 1
+            for r in range(0, L, 2):
+                for c in range(0, L, 2):
+                    if r != L - 1:
+                        assert x[r, c] == 0, (r, c)
+                    if c != L - 1:
+                        assert z[r, c] == 0, (r, c)
 
 
 def test_im2col_col2im_adjoint():
@@ -94,16 +128,21 @@ def test_legs_cross_the_boundary():
             assert inside(a, (I, J)) and inside(b, (I2, J2))
 
 
-def test_loss_is_zero_on_its_own_prediction_and_sign_invariant():
+def test_loss_is_zero_on_its_own_prediction_and_scale_invariant():
     rng = np.random.default_rng(4)
     d = 5
     X0, plan, _, _ = _job(d)
     theta = rng.normal(size=warmnet.count(TINY)) * 0.3
     pred = warmnet.predict(theta, X0, d, plan, TINY)
     ids = list(range(plan.M))
-    l0, _ = warmnet.loss_and_grad(theta, X0, d, plan, pred, ids, TINY)
-    l1, _ = warmnet.loss_and_grad(theta, X0, d, plan, -pred, ids, TINY)
+    l0, g0 = warmnet.loss_and_grad(theta, X0, d, plan, pred, ids, TINY)
+    l1, _ = warmnet.loss_and_grad(theta, X0, d, plan, 3.0 * pred, ids, TINY)
     assert abs(l0) < 1e-12 and abs(l1) < 1e-12
+    assert np.abs(g0).max() < 1e-12
+    # any other target gives a positive loss (KL divergence of distinct distributions)
+    other = pred.copy()
+    other[0, :2] = other[0, 1::-1]
+    assert warmnet.loss_and_grad(theta, X0, d, plan, other, ids, TINY)[0] > 0
 
 
 @pytest.mark.parametrize("d,k", [(3, 2), (5, 3)])
