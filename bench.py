@@ -95,8 +95,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, choices=(0, 1), default=0,
                     help="0: FP32 products (default); 1: products of BF16-rounded inputs, FP32 sums")
-    ap.add_argument("--workload", choices=("d17", "mixed"), default="d17",
-                    help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance")
+    ap.add_argument("--workload", choices=("d17", "mixed", "warm"), default="d17",
+                    help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance; warm: "
+                         "learned warm start against the uniform start at d=25, p=0.10")
+    ap.add_argument("--warm-d", type=int, default=25, help="distance of the warm-start comparison (default 25)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a known-size reference dispatch "
                          "for hardware byte counters)")
@@ -112,6 +114,8 @@ def main():
 
     if a.workload == "mixed":
         return mixed_main(a)
+    if a.workload == "warm":
+        return warm_main(a)
     if a.calibrate_copy > 0:
         n = a.calibrate_copy << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -248,6 +252,87 @@ def mixed_main(a):
                       frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=_lib.sweep_kernel_name(tm.top_class),
                       avg_launch_ms=tm.top_ms / max(tm.top_launches, 1), measured_on="one eager decode"),
         mean_iterations_per_coset={g[0]: float(o["iters"].double().mean()) for g, o in zip(groups, outs)},
+    )
+    print(json.dumps(line), flush=True)
+
+
+def logical_failures(d, errors, corrections):
+    """1 where the correction differs from the sampled error by a logical operator: the product P (no
+    syndrome) anticommutes with Z on the column-0 horizontal edges (an X logical component) or with X on
+    the row-0 horizontal edges (a Z logical component)."""
+    import numpy as np
+    from paper_2402_04834_amd import workload
+    q = workload.qubit_coords(d)
+    prod = np.bitwise_xor(errors, corrections)
+    col0 = (q[:, 1] == 0) & (q[:, 0] % 2 == 0)
+    row0 = (q[:, 0] == 0)
+    xs = np.bitwise_xor.reduce(prod[:, col0] & 1, axis=1)
+    zs = np.bitwise_xor.reduce((prod[:, row0] >> 1) & 1, axis=1)
+    return (xs | zs).astype(np.float64)
+
+
+def warm_main(a):
+    """Learned warm start against the uniform (cold) start: 4096 syndromes at d=25 (--warm-d), p=0.10, 6x6 blocks,
+    chi 32, early exit at delta0 1e-4 within at most 60 iterations (so that iterations to convergence are
+    measured, not the cap). The warm decode is the network's forward, the decode from its messages and the
+    cold rerun of the syndromes whose final distance stays at or above delta1; each is timed whole."""
+    import numpy as np
+    import torch
+
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm, workload
+
+    d, p, count, max_iter = a.warm_d, 0.10, a.batch, 60
+    dev = torch.device("cuda:0")
+    errors, syn = workload.make_batch(d, p, count, workload="warm", p_index=10)
+    s = torch.from_numpy(syn).to(dev)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1)
+    theta = torch.from_numpy(warm.load()).to(dev)
+
+    def timed(fn):
+        out = None
+        for _ in range(a.warmup):
+            out = fn(out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            out = fn(out)
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / a.steps
+
+    ws = torch.empty(bbp.workspace_size(d, count, opts), dtype=torch.uint8, device=dev)
+    cold, t_cold = timed(lambda o: bbp.decode_device(d, p, s, opts, workspace=ws, out=o))
+    wws = [None]
+
+    def warm_step(o):
+        r = warm.decode(d, p, s, opts, theta, workspace=wws[0], out=o)
+        wws[0] = r["workspace"]
+        return r
+    hot, t_warm = timed(warm_step)
+    pred_ws = torch.empty(warm.workspace_size(d, count, opts, False), dtype=torch.uint8, device=dev)
+    _, t_pred = timed(lambda o: warm.predict(d, p, s, opts, theta, workspace=pred_ws))
+    ci, wi = cold["iters"].double(), hot["iters"].double()
+    line = dict(
+        metric=f"syndromes decoded/s at d={d}, p=0.10 with the learned warm start (1 GPU)",
+        value=count / t_warm, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=1e3 * t_warm, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload=f"{count} syndromes, d={d}, p=0.10, 6x6 blocks, chi 32, <= {max_iter} BP iterations, "
+                             "early exit at delta0 1e-4; warm = network forward + decode from its messages + cold "
+                             "rerun where delta >= delta1", batch=count, parallelism="single GPU"),
+        cold=dict(value=count / t_cold, ms_per_step=1e3 * t_cold,
+                  mean_iterations_per_coset=float(ci.mean()),
+                  mean_iterations_per_syndrome_max=float(ci.max(dim=1).values.mean()),
+                  converged_cosets=float((cold["delta"] < opts.delta0).double().mean())),
+        warm=dict(value=count / t_warm, ms_per_step=1e3 * t_warm, forward_ms=1e3 * t_pred,
+                  mean_iterations_per_coset=float(wi.mean()),
+                  mean_iterations_per_syndrome_max=float(wi.max(dim=1).values.mean()),
+                  converged_cosets=float((hot["delta"] < opts.delta0).double().mean()),
+                  fallback_syndromes=int(hot["fallback"])),
+        decision_agreement_with_cold=float((hot["coset"] == cold["coset"]).double().mean()),
+        logical_failure_rate=dict(cold=logical_failures(d, errors, cold["correction"].cpu().numpy()).mean(),
+                                  warm=logical_failures(d, errors, hot["correction"].cpu().numpy()).mean()),
+        speedup=t_cold / t_warm,
     )
     print(json.dumps(line), flush=True)
 

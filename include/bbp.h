@@ -206,17 +206,17 @@ int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts
  * learning as a way to improve BP (Sec. V, summary and conclusions). Here a convolutional network
  * predicts the start messages of every coset job from the local syndrome, and the decoder runs from them.
  *
- * Network (per coset job, on the L x L grid): 13 input channels per site (x and z bits of the coset label
+ * Network (per coset job, on the L x L grid): 11 input channels per site (x and z bits of the coset label
  * f_s L at qubits, the syndrome bit at checks, qubit / Z-check / X-check indicators, p, 1, the coset's x and
- * z bits, at checks the generator bit G, r / (L-1), c / (L-1)), where G is the prefix parity of f_s L on the
- * horizontal edges above a plaquette in its column (x part) or left of a vertex in its row (z part); three
- * 3x3 convolutions with zero padding (13 -> 64 -> 128 -> 96 channels, ReLU after the first two) give features
+ * z bits, at checks the generator bit G), where G is the prefix parity of f_s L on the horizontal edges
+ * above a plaquette in its column (x part) or left of a vertex in its row (z part); three 3x3 convolutions
+ * with zero padding (11 -> 64 -> 128 -> 96 channels, ReLU after the first two) give features
  * F; for each directed message with K legs (leg i joins site a_i of the sending block to site b_i across the
  * boundary, leg 0 at the top / left) and f_i = [F(a_i), F(b_i)], the weights of the message's direction
  * (E, W, S, N) give u_i = Wu^T f_i + bu (2 values) and P_i = Wp^T [f_i, f_{i+1}] + bp (4 values); the
  * message is exp(s) scaled to unit norm, s(b) = sum_i u_i[b_i] + sum_i P_i[2 b_i + b_{i+1}] over the 2^K
  * leg configurations b (leg 0 the most significant bit, the layout of the decoder's messages).
- * Parameters: one float32 device array of bbp_warm_param_count() values, in the order conv1 W [117][64],
+ * Parameters: one float32 device array of bbp_warm_param_count() values, in the order conv1 W [99][64],
  * b [64], conv2 W [576][128], b [128], conv3 W [1152][96], b [96], then for E, W, S, N: Wu [192][2], bu [2],
  * Wp [384][4], bp [4]; W rows are (3 dy + dx) * C_in + c_in for the input site (r + dy - 1, c + dx - 1).
  * Training loss of a message against a converged cold-start message t (non-negative): KL(q || p) of

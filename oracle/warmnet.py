@@ -6,7 +6,7 @@ remark 2, is what it replaces; the paper names machine learning as a way to impr
 NumPy, generic channel counts so that tests can use tiny networks; every step is written out directly (no
 blocking or fusion).
 
-Input, per coset job, a (2d-1) x (2d-1) grid with 13 channels per site:
+Input, per coset job, a (2d-1) x (2d-1) grid with 11 channels per site:
   0 x bit and 1 z bit of the coset label f_s L at qubit sites (0 at checks),
   2 syndrome bit at check sites (0 at qubits),
   3 qubit, 4 Z-check (even row, odd column), 5 X-check (odd row, even column) indicators,
@@ -15,8 +15,8 @@ Input, per coset job, a (2d-1) x (2d-1) grid with 13 channels per site:
   10 at check sites the generator bit G: for a plaquette (X-check) at (r, c) the parity of the x bits of
      f_s L on the horizontal edges above it in column c, for a vertex (Z-check) at (r, c) the parity of
      the z bits of f_s L on the horizontal edges left of it in row r (the generators that clear f_s L from
-     the horizontal edges except the last row / column),
-  11 r / (L-1), 12 c / (L-1).
+     the horizontal edges except the last row / column).
+No absolute position enters, so the network applies unchanged to distances it was not trained on.
 Three 3x3 convolutions with zero padding, ReLU after the first two, give features F [L, L, C3].
 
 Message head, per directed message u -> v with K legs (the crossing bonds of the boundary, position 0 at
@@ -38,7 +38,7 @@ from __future__ import annotations
 
 import numpy as np
 
-C0 = 13
+C0 = 11
 CHANNELS = (64, 128, 96)   # C1, C2, C3 of the network the GPU trains
 
 
@@ -69,7 +69,7 @@ def pack(parts, ch=CHANNELS):
 
 
 def features(d, syndrome, p, coset):
-    """Input grid [L, L, 13] of coset job `coset` (0..3 = I, X, Y, Z) of a syndrome [m] (0/1)."""
+    """Input grid [L, L, 11] of coset job `coset` (0..3 = I, X, Y, Z) of a syndrome [m] (0/1)."""
     from . import lattice
     L = 2 * d - 1
     nz = d * (d - 1)
@@ -95,8 +95,6 @@ def features(d, syndrome, p, coset):
             X[r, c, 7] = 1.0
             X[r, c, 8] = bx
             X[r, c, 9] = bz
-            X[r, c, 11] = r / (L - 1)
-            X[r, c, 12] = c / (L - 1)
     return X
 
 

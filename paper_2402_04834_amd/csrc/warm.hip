@@ -3,10 +3,11 @@
 // training (forward, backward, Adam) for gfx950.
 //
 // Network (per coset job, on the (2d-1) x (2d-1) grid):
-//   input  13 channels per site: label x / z bits at qubits, syndrome bit at checks, qubit / Z-check /
-//          X-check indicators, the noise rate p, 1 (inside the grid), the coset's X and Z bits, the
-//          generator bit G at checks (features_kernel), and the position r / (L-1), c / (L-1);
-//   trunk  three 3x3 convolutions with zero padding (13 -> 64 -> 128 -> 96 channels), ReLU after the first
+//   input  11 channels per site: label x / z bits at qubits, syndrome bit at checks, qubit / Z-check /
+//          X-check indicators, the noise rate p, 1 (inside the grid), the coset's X and Z bits, and the
+//          generator bit G at checks (features_kernel); no absolute position, so that the network applies
+//          unchanged to distances it was not trained on;
+//   trunk  three 3x3 convolutions with zero padding (11 -> 64 -> 128 -> 96 channels), ReLU after the first
 //          two; each is an implicit GEMM on the matrix cores (v_mfma_f32_16x16x4f32, FP32 products and
 //          sums); activations are row-major [site][channel];
 //   head   per directed message with K legs (leg i joins site a_i of the sender to site b_i across the
@@ -17,7 +18,7 @@
 //   loss   KL(q || p) of the distributions q = t / sum(t) of the converged message t and p = softmax(s),
 //          averaged over the trained messages (its gradient in s, p - q, does not vanish when the
 //          prediction is peaked at the wrong configuration, unlike overlap losses of unit vectors).
-// Parameters (FP32, in this order): conv1 W [117][64], b [64]; conv2 W [576][128], b [128]; conv3 W
+// Parameters (FP32, in this order): conv1 W [99][64], b [64]; conv2 W [576][128], b [128]; conv3 W
 // [1152][96], b [96]; then per direction E, W, S, N: Wu [192][2], bu [2], Wp [384][4], bp [4].
 #include <hip/hip_runtime.h>
 
@@ -36,7 +37,7 @@
 
 namespace {
 
-constexpr int C0 = 13, C1 = 64, C2 = 128, C3 = 96;
+constexpr int C0 = 11, C1 = 64, C2 = 128, C3 = 96;
 constexpr int MAXK = 6;                                   // legs of a message (block size <= 6)
 constexpr int HEAD = 2 * C3 * 2 + 2 + 4 * C3 * 4 + 4;     // parameters of one direction's head
 constexpr int NOUT = 2 * MAXK + 4 * (MAXK - 1);           // head outputs of one message (<= 32)
@@ -165,8 +166,6 @@ __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict
     v[7] = 1.0f;
     v[8] = (float)bx;
     v[9] = (float)bz;
-    v[11] = (float)r / (float)(L - 1);
-    v[12] = (float)c / (float)(L - 1);
     float* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * C0;
     for (int k = 0; k < C0; ++k) o[k] = v[k];
   }

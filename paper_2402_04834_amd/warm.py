@@ -18,7 +18,7 @@ from ._lib import bbp_opts
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS_PATH = os.path.join(HERE, "weights", "warmstart_d13-21.npy")
-CHANNELS = (13, 64, 128, 96)
+CHANNELS = (11, 64, 128, 96)
 
 
 def param_count() -> int:

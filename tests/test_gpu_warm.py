@@ -223,3 +223,29 @@ def test_training_reduces_loss(dev):
     first, last = hist[:10].mean(), hist[-10:].mean()
     assert np.all(np.isfinite(hist))
     assert last < 0.8 * first, (first, last)
+
+
+def test_committed_weights_against_cold_start(dev):
+    """The committed network (trained on d 13..21) against the uniform start on held-out syndromes at d=13,
+    p=0.10: the warm decode agrees with the cold decisions on nearly every syndrome and its iteration
+    count stays close to the cold one. (Measured: the network does not reduce the iterations; the numbers
+    of the d=25 comparison are in the benchmark's warm workload.)"""
+    import torch
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm
+    d, p, b = 13, 0.10, 512
+    _, syn = workload.make_batch(d, p, b, workload="warm", p_index=1013)
+    s = torch.from_numpy(syn).to(dev)
+    th = torch.from_numpy(warm.load()).to(dev)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=40)
+    cold = _np(bbp.decode_device(d, p, s, opts))
+    res = warm.decode(d, p, s, opts, th)
+    torch.cuda.synchronize()
+    hot = _np(res)
+    agree = (hot["coset"] == cold["coset"]).mean()
+    ci, wi = cold["iters"].mean(), hot["iters"].mean()
+    _say(f"[warm weights] d={d}: agreement {agree:.4f}, iterations cold {ci:.2f} warm {wi:.2f}, "
+         f"fallback {res['fallback']}")
+    assert np.all(np.isfinite(hot["loglik"]))
+    assert agree >= 0.99
+    assert wi <= 1.1 * ci

@@ -33,7 +33,6 @@ def test_input_channels():
                     assert X0[r, c, 0] + 2 * X0[r, c, 1] == lab[coset, r, c]
         assert np.all(X0[..., 7] == 1.0) and np.allclose(X0[..., 6], 0.1)
         assert np.all(X0[..., 8] == (coset in (1, 2))) and np.all(X0[..., 9] == (coset in (2, 3)))
-        assert X0[0, 0, 11] == 0 and X0[L - 1, 0, 11] == 1 and X0[0, L - 1, 12] == 1
 
 
 @pytest.mark.parametrize("d", [3, 5, 7])
