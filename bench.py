@@ -41,6 +41,58 @@ def traffic(kernel):
     return 1024.0 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"])
 
 
+TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/geom.hpp", "paper_2402_04834_amd/csrc/sweep_launch.hpp",
+                   "paper_2402_04834_amd/csrc/wave_sweep.hpp", "paper_2402_04834_amd/csrc/sweep_kernel.hip"]
+
+
+def _short_kernel_name(name):
+    """'void bbp::(anonymous namespace)::sweep_kernel<float, 6, true, ...>(bbp::SweepArgs)' ->
+    'sweep_kernel<6, true, ...>' (the name bbp_timing reports); other kernels keep their name."""
+    import re
+    m = re.search(r"sweep_kernel<float, ([^>]*)>", name)
+    return f"sweep_kernel<{m.group(1)}>" if m else name
+
+
+def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of every FP32 sweep kernel from two rocprofv3 --pmc
+    counter CSVs of `bench.py --calibrate-copy MIB`, with the scale factors that make the calibration
+    copy read and write exactly its size; stamped with the hash of the kernel sources."""
+    import collections
+    import csv
+    import hashlib
+
+    def load(path, counter):
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return per
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    # the calibration copy is the largest single dispatch of a copy kernel
+    cf = max((v for k, d in fetch.items() if "copy" in k.lower() for v in d.values()), default=0.0)
+    cw = max((v for k, d in write.items() if "copy" in k.lower() for v in d.values()), default=0.0)
+    assert cf > 0 and cw > 0, "no calibration copy in the counter files"
+    fetch = {k: (sum(d.values()) / len(d), len(d)) for k, d in fetch.items()}
+    write = {k: (sum(d.values()) / len(d), len(d)) for k, d in write.items()}
+    size_kib = copy_mib * 1024.0
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    kernels = {}
+    for k, (v, n) in fetch.items():
+        short = _short_kernel_name(k)
+        if short.startswith("sweep_kernel<") and k in write:
+            kernels[short] = dict(fetch_kib=v, write_kib=write[k][0], dispatches=n)
+    out = dict(source_sha256=h.hexdigest(), sources=TRAFFIC_SOURCES, fetch_scale=round(size_kib / cf, 4),
+               write_scale=round(size_kib / cw, 4),
+               calibration=f"plain device copy of {copy_mib} MiB (bench.py --calibrate-copy {copy_mib}): FETCH_SIZE "
+                           f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB",
+               kernels=kernels)
+    with open(TRAFFIC, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def cpu_baseline(d, p, block, chi, max_iter):
     """The FP64 oracle on one syndrome of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
@@ -95,14 +147,27 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, choices=(0, 1), default=0,
                     help="0: FP32 products (default); 1: products of BF16-rounded inputs, FP32 sums")
-    ap.add_argument("--workload", choices=("d17", "mixed", "warm"), default="d17",
+    ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased"), default="d17",
                     help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance; warm: "
-                         "learned warm start against the uniform start at d=25, p=0.10")
+                         "learned warm start against the uniform start at d=25, p=0.10; biased: d=17 under "
+                         "Z-biased Pauli noise (p=0.10, bias 10)")
+    ap.add_argument("--block", type=int, default=6, choices=range(1, 7),
+                    help="block size k of the d17 workload (default 6; 1 = plain BP between single tensors)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-variant autotuner (job-major items, one stream): for profiler runs, "
+                         "whose kernel statistics should hold the timed decodes only")
     ap.add_argument("--warm-d", type=int, default=25, help="distance of the warm-start comparison (default 25)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a known-size reference dispatch "
                          "for hardware byte counters)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of the sweep kernels from two rocprofv3 counter files "
+                         "(FETCH_SIZE and WRITE_SIZE runs of this benchmark with --calibrate-copy 1024) and exit")
     a = ap.parse_args()
+    if a.traffic_summary:
+        out = write_traffic_summary(*a.traffic_summary)
+        print(json.dumps({k: v for k, v in out.items() if k != "kernels"}))
+        return
     if a.gpus != 1:
         print("bench.py: this decoder runs on one GPU; only --gpus 1 is supported", file=sys.stderr)
         sys.exit(2)
@@ -116,6 +181,8 @@ def main():
         return mixed_main(a)
     if a.workload == "warm":
         return warm_main(a)
+    if a.workload == "biased":
+        return biased_main(a)
     if a.calibrate_copy > 0:
         n = a.calibrate_copy << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -124,7 +191,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    d, p, block, chi, max_iter = 17, 0.10, 6, 32, 20
+    d, p, block, chi, max_iter = 17, 0.10, a.block, 32, 20
     _, syn = workload.make_batch(d, p, a.batch, workload="d17")
     dev = torch.device("cuda:0")
     syn_dev = torch.from_numpy(syn).to(dev)
@@ -136,7 +203,10 @@ def main():
     # The timed region keeps its item order on a single stream, so that every kernel launch is timed
     # alone and the roofline figure is the dominant kernel's own rate; the tuned multi-stream variant is
     # timed separately afterwards.
-    tune = bbp.autotune(d, p, syn_dev, opts, workspace=ws)
+    if a.no_autotune:   # profiling runs: only the timed single-stream decodes, job-major items
+        tune = bbp.bbp_tuning(1, 1, 0.0)
+    else:
+        tune = bbp.autotune(d, p, syn_dev, opts, workspace=ws)
     bbp.set_tuning(d, opts, tune.order, 1)
     for _ in range(a.warmup):
         bbp.decode_device(d, p, syn_dev, opts, workspace=ws)
@@ -197,7 +267,7 @@ def main():
                            autotuned_streams=tune.streams, autotuned_value=tuned, tuning_decode_ms=tune.ms),
         plan=dict(messages_per_coset=info.num_messages, exact_sweeps=bool(info.exact_sweeps),
                   max_boundary_rank=info.max_boundary_rank),
-        agreement=agreement(out, a.batch),
+        agreement=agreement(out, a.batch) if block == 6 else None,
     )
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, p, block, chi, max_iter)
@@ -252,6 +322,56 @@ def mixed_main(a):
                       frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=_lib.sweep_kernel_name(tm.top_class),
                       avg_launch_ms=tm.top_ms / max(tm.top_launches, 1), measured_on="one eager decode"),
         mean_iterations_per_coset={g[0]: float(o["iters"].double().mean()) for g, o in zip(groups, outs)},
+    )
+    print(json.dumps(line), flush=True)
+
+
+def biased_main(a):
+    """d=17 under Z-biased Pauli noise: p=0.10 with bias p_Z / (p_X + p_Y) = 10 (p_X = p_Y), 4096 syndromes,
+    6x6 blocks, chi 32, <= 20 iterations with early exit; the qubit entries take the four probabilities.
+    Eager decodes with per-launch HIP events, as the headline workload."""
+    import numpy as np
+    import torch
+
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import _lib, workload
+
+    d, count = 17, a.batch
+    probs = workload.biased_probs(0.10, 10.0)
+    errors, syn = workload.make_batch_pauli(d, probs, count, p_index=17)
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(syn).to(dev)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
+    bbp.set_tuning(d, opts, 1, 1)
+    outs, ws, _ = bbp.decode_groups([(d, probs, s)], opts)
+    for _ in range(a.warmup):
+        outs, ws, _ = bbp.decode_groups([(d, probs, s)], opts, workspace=ws, outs=outs)
+    torch.cuda.synchronize()
+    top_ms = top_flops = 0.0
+    top_launches, top_class = 0, -1
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        outs, ws, tm = bbp.decode_groups([(d, probs, s)], opts, workspace=ws, outs=outs, timing=True)
+        top_ms += tm.top_ms
+        top_flops += tm.top_flops
+        top_launches += tm.top_launches
+        top_class = tm.top_class
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    achieved = top_flops / (top_ms * 1e-3) / 1e12 if top_ms > 0 else 0.0
+    o = outs[0]
+    line = dict(
+        metric="syndromes decoded/s at d=17, chi=32, Z-biased noise (1 GPU)", value=count * a.steps / elapsed,
+        unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=1e3 * elapsed / a.steps,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=f"{count} syndromes, d=17, Pauli noise (I, X, Z, Y) = "
+                             f"({probs[0]:.4f}, {probs[1]:.5f}, {probs[2]:.5f}, {probs[3]:.5f}), 6x6 blocks, "
+                             "chi 32, <= 20 BP iterations, early exit", batch=count, parallelism="single GPU"),
+        roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=_lib.sweep_kernel_name(top_class),
+                      avg_launch_ms=top_ms / max(top_launches, 1)),
+        mean_iterations_per_coset=float(o["iters"].double().mean()),
+        logical_failure_rate=float(logical_failures(d, errors, o["correction"].cpu().numpy()).mean()),
     )
     print(json.dumps(line), flush=True)
 

@@ -114,8 +114,9 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
 def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None, outs=None,
                   messages: bool = False):
     """Decode a mixed batch: `groups` is a list of (d, p, syndromes[, chi[, init]]) with syndromes a torch
-    uint8 CUDA tensor [batch, 2d(d-1)], p a float or a float64 CUDA tensor [batch] of per-syndrome noise
-    rates, chi the group's bond dimension (0 or absent: opts.chi) and init optional start messages (float32
+    uint8 CUDA tensor [batch, 2d(d-1)], p a float (depolarizing rate), a float64 CUDA tensor [batch] of
+    per-syndrome depolarizing rates or a 4-sequence of Pauli probabilities (I, X, Z, Y) for biased noise,
+    chi the group's bond dimension (0 or absent: opts.chi) and init optional start messages (float32
     CUDA tensor [batch, 4, M, 64], e.g. from warm.predict; None: the uniform start). Returns (list of
     per-group output dicts as in decode_device, workspace, bbp_timing or None). `outs` (from an earlier
     call with the same groups) receives the results in place, keeping graph-mode arguments identical.
@@ -135,8 +136,11 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
         keep.append(syn)
         dev = syn.device
         b = syn.shape[0]
-        p_ptr, p_val = None, p
-        if torch.is_tensor(p):
+        p_ptr, p_val, noise = None, p, (0.0, 0.0, 0.0, 0.0)
+        if isinstance(p, (tuple, list, np.ndarray)):      # biased noise: probabilities of I, X, Z, Y
+            assert len(p) == 4
+            noise, p_val = tuple(float(v) for v in p), 0.0
+        elif torch.is_tensor(p):
             assert p.is_cuda and p.dtype == torch.float64 and p.shape == (b,)
             p = p.contiguous()
             keep.append(p)
@@ -157,7 +161,7 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
             msg_ptr = o["messages"].data_ptr()
         gs[k] = bbp_group(d, chi, p_val, p_ptr, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),
                           o["iters"].data_ptr(), o["coset"].data_ptr(), o["correction"].data_ptr(), init_ptr,
-                          msg_ptr)
+                          msg_ptr, (C.c_double * 4)(*noise))
     n = C.c_size_t()
     _lib.check(_lib.lib().bbp_workspace_size_groups(gs, len(groups), C.byref(opts), C.byref(n)))
     if workspace is None or workspace.numel() < n.value:

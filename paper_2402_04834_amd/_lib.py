@@ -32,7 +32,7 @@ class bbp_group(C.Structure):
         ("syndromes_dev", C.c_void_p), ("batch", C.c_int64),
         ("loglik_dev", C.c_void_p), ("delta_dev", C.c_void_p), ("iters_dev", C.c_void_p),
         ("coset_dev", C.c_void_p), ("correction_dev", C.c_void_p), ("init_messages_dev", C.c_void_p),
-        ("messages_dev", C.c_void_p),
+        ("messages_dev", C.c_void_p), ("noise", C.c_double * 4),
     ]
 
 

@@ -384,6 +384,7 @@ struct GroupRun {
   double *terms = nullptr, *lnw = nullptr, *delta = nullptr;
   int32_t *conv = nullptr, *iters = nullptr;
   int64_t jobs = 0;
+  int biased = 0;
 };
 
 // Validate the groups, fetch their plans and lay their state out in one workspace.
@@ -401,7 +402,19 @@ int resolve(const bbp_group* groups, int ng, const bbp_opts* opts, std::vector<G
     if (G.chi > 0) gr[g].opts.chi = G.chi;
     int rc = validate(G.d, &gr[g].opts);
     if (rc) return rc;
-    if (!G.p_dev && !(G.p > 0.0 && G.p < 1.0)) return fail(BBP_EINVAL, "p must be in (0, 1)");
+    gr[g].biased = (G.noise[0] != 0.0 || G.noise[1] != 0.0 || G.noise[2] != 0.0 || G.noise[3] != 0.0) ? 1 : 0;
+    if (gr[g].biased) {
+      double sum = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        if (!(G.noise[k] >= 0.0 && G.noise[k] <= 1.0)) return fail(BBP_EINVAL, "noise entries must be in [0, 1]");
+        sum += G.noise[k];
+      }
+      if (!(G.noise[0] > 0.0) || std::fabs(sum - 1.0) > 1e-6)
+        return fail(BBP_EINVAL, "noise must be probabilities summing to 1 with a positive identity entry");
+      if (G.p_dev) return fail(BBP_EINVAL, "noise and p_dev are exclusive");
+    } else if (!G.p_dev && !(G.p > 0.0 && G.p < 1.0)) {
+      return fail(BBP_EINVAL, "p must be in (0, 1)");
+    }
     if (G.batch < 0) return fail(BBP_EINVAL, "batch must be >= 0");
     if (G.batch > (int64_t)1 << 24) return fail(BBP_EINVAL, "batch too large");
     gr[g].in = G;
@@ -536,6 +549,8 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
         G.p00 = 1.0f - (float)g.in.p;
         G.pe = (float)g.in.p / 3.0f;
         G.pdev = g.in.p_dev;
+        G.biased = g.biased;
+        for (int k = 0; k < 4; ++k) G.pi[k] = (float)g.in.noise[k];
         items += g.jobs * (int64_t)r.count;
       }
       sa.items = items;
@@ -702,7 +717,8 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     key.insert(key.end(), {(uint64_t)g.in.d, (uint64_t)g.opts.chi, u64(g.in.p), u64(g.in.p_dev),
                            u64(g.in.syndromes_dev), (uint64_t)g.in.batch,
                            u64(g.in.loglik_dev), u64(g.in.delta_dev), u64(g.in.iters_dev), u64(g.in.coset_dev),
-                           u64(g.in.correction_dev), u64(g.in.init_messages_dev), u64(g.in.messages_dev)});
+                           u64(g.in.correction_dev), u64(g.in.init_messages_dev), u64(g.in.messages_dev),
+                           u64(g.in.noise[0]), u64(g.in.noise[1]), u64(g.in.noise[2]), u64(g.in.noise[3])});
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -67,6 +67,8 @@ void sweep_kernel(SweepArgs a) {
     c.p00 = G.p00;
     c.pe = G.pe;
   }
+  c.biased = G.biased;
+  for (int k = 0; k < 4; ++k) c.pib[k] = __float_as_int(G.pi[k]);
   c.exp2 = 0;
   const uint8_t* lab = G.labels + job * L * L;
   int lb = 0;

@@ -33,6 +33,8 @@ struct SweepGroup {
   int32_t d, M, nblocks;
   float p00, pe;             // depolarizing noise entries: 1 - p and p / 3
   const double* pdev;        // optional [job / 4] per-syndrome p (overrides p00, pe)
+  int32_t biased;            // 1: the qubit entries are pi (Pauli probabilities by code x + 2z)
+  float pi[4];
 };
 
 struct SweepArgs {

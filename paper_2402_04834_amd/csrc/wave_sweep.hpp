@@ -23,8 +23,9 @@
 // Cap below). Any placement of the dense core along the message gives the same exact contraction; a sweep
 // that runs against the message's leg order reads the message with its legs reversed.
 //
-// Noise: i.i.d. depolarizing; a qubit tensor entry is p00 = 1 - p when its label flipped by the adjacent
-// bond parities is the identity and pe = p/3 otherwise.
+// Noise: i.i.d. single-qubit Pauli noise; a qubit tensor entry is the probability of its label flipped by the
+// adjacent bond parities. Depolarizing (p00 = 1 - p for the identity, pe = p/3 otherwise) is the default;
+// a group may give four probabilities instead (biased noise), selected per qubit on the scalar unit.
 //
 // Middle-site caps with four new cap values (sweeps of 5 and 6 steps) contract on the matrix cores: the
 // message entries are the same for every lane, so lane 4b+i supplies entry (a, v, i) and lane h = 4b+j
@@ -188,6 +189,8 @@ struct Ctx {
   float labv;           // lane l < kt*kp: coset label of the site at (step l / kp, position l % kp)
   V mtv, mbv;           // lane l: entry l of the top / bottom side message (legs in sweep order)
   float p00, pe;        // depolarizing entries
+  int biased;           // 1: entries from pib instead
+  int pib[4];           // float bits of the Pauli probabilities by code x + 2z (I, X, Z, Y)
   int exp2;             // accumulated power-of-two scale (state values are true values * 2^-exp2)
 };
 
@@ -200,19 +203,33 @@ struct QC {
   V cs, cf;   // coefficient of the lane's own value and of the partner lane's (crossing bit flipped)
 };
 
-// Coefficients of a qubit with coset label lb and orientation swap for a lane whose vertical bond parity
-// is pv and output crossing bit ho; scaled by sc. The noise entry is p00 iff the label flipped by the
-// parities is the identity: the component the crossing parity acts on must equal it (0 for the lane's own
-// value, 1 for the partner's) and the other component must equal pv.
-__device__ __forceinline__ QC<float> qcoef(float p00, float pe, int lb, int swap, int pv, int ho, bool in_abs,
-                                           bool out_abs, float sc) {
-  const int lx = lb & 1, lz = (lb >> 1) & 1;
-  const int A = swap ? lx : lz, B = swap ? lz : lx;
-  const bool m = (pv == B);
-  const float hi = p00 * sc, lo = pe * sc;
+// probability of Pauli code k (uniform) from the float bits of the four probabilities
+__device__ __forceinline__ float pick4(const int* pib, int k) {
+  const int a = (k & 1) ? pib[1] : pib[0];
+  const int b = (k & 1) ? pib[3] : pib[2];
+  return __int_as_float((k & 2) ? b : a);
+}
+
+// Coefficients of a qubit with coset label lb (code x + 2z) and orientation swap for a lane whose vertical
+// bond parity is pv and output crossing bit ho; scaled by sc. The crossing parity (0 for the lane's own
+// value, 1 for the partner's) flips x when swap and z otherwise; pv flips the other component. Depolarizing:
+// the entry is p00 iff the flipped label is the identity.
+__device__ __forceinline__ QC<float> qcoef(float p00, float pe, int biased, const int* pib, int lb, int swap, int pv,
+                                           int ho, bool in_abs, bool out_abs, float sc) {
   QC<float> q;
-  q.cs = (m && A == 0) ? hi : lo;
-  q.cf = (m && A == 1) ? hi : lo;
+  if (biased) {
+    const int F = swap ? 1 : 2, G = F ^ 3;
+    const float s0 = pick4(pib, lb), f0 = pick4(pib, lb ^ F), s1 = pick4(pib, lb ^ G), f1 = pick4(pib, lb ^ 3);
+    q.cs = (pv ? s1 : s0) * sc;
+    q.cf = (pv ? f1 : f0) * sc;
+  } else {
+    const int lx = lb & 1, lz = (lb >> 1) & 1;
+    const int A = swap ? lx : lz, B = swap ? lz : lx;
+    const bool m = (pv == B);
+    const float hi = p00 * sc, lo = pe * sc;
+    q.cs = (m && A == 0) ? hi : lo;
+    q.cf = (m && A == 1) ? hi : lo;
+  }
   if (in_abs) {   // the input crossing bit must be 0
     q.cs = ho ? 0.0f : q.cs;
     q.cf = ho ? q.cf : 0.0f;
@@ -233,7 +250,7 @@ __device__ __forceinline__ int label_at(const Ctx<V>& c, int t, int i) {
 template <class V>
 __device__ __forceinline__ QC<V> qcoefs(const Ctx<V>& c, int t, int i, int swap, int pv, int ho, bool in_abs,
                                         bool out_abs, V sc) {
-  const QC<float> q = qcoef(c.p00, c.pe, label_at(c, t, i), swap, pv, ho, in_abs, out_abs, tof(sc));
+  const QC<float> q = qcoef(c.p00, c.pe, c.biased, c.pib, label_at(c, t, i), swap, pv, ho, in_abs, out_abs, tof(sc));
   return QC<V>{V{q.cs}, V{q.cf}};
 }
 

@@ -20,7 +20,7 @@ import numpy as np
 SEED_ENTROPY = 240204834
 
 # workload identifiers used in the seed's spawn key
-WORKLOAD_IDS = {"d5": 1, "d11": 2, "d17": 3, "mixed": 4, "warm": 5, "test": 9}
+WORKLOAD_IDS = {"d5": 1, "d11": 2, "d17": 3, "mixed": 4, "warm": 5, "biased": 6, "test": 9}
 
 
 def grid_size(d: int) -> int:
@@ -104,6 +104,34 @@ def sample_errors(d: int, p: float, count: int, workload: str = "test", p_index:
         which = np.minimum((u * (3.0 / p)).astype(np.int64), 2)
         out[i] = np.where(u < p, paulis[which], 0)
     return out
+
+
+def biased_probs(p: float, eta: float):
+    """Pauli probabilities (I, X, Z, Y) -- index = code x + 2z -- of Z-biased noise with total rate p and
+    bias eta = p_Z / (p_X + p_Y), p_X = p_Y."""
+    pz = p * eta / (1.0 + eta)
+    px = py = p / (2.0 * (1.0 + eta))
+    return (1.0 - p, px, pz, py)
+
+
+def sample_errors_pauli(d: int, probs, count: int, workload: str = "biased", p_index: int = 0,
+                        start: int = 0) -> np.ndarray:
+    """Errors [count, n] (codes x + 2z) of i.i.d. single-qubit Pauli noise with probabilities probs of
+    (I, X, Z, Y); error i uses its own counter-keyed stream like sample_errors."""
+    wid = WORKLOAD_IDS[workload]
+    n = num_qubits(d)
+    _, px, pz, py = (float(v) for v in probs)
+    out = np.empty((count, n), dtype=np.uint8)
+    for i in range(count):
+        u = _rng(wid, d, p_index, start + i).random(n)
+        out[i] = np.where(u < px, 1, np.where(u < px + py, 3, np.where(u < px + py + pz, 2, 0)))
+    return out
+
+
+def make_batch_pauli(d: int, probs, count: int, workload: str = "biased", p_index: int = 0, start: int = 0):
+    """(errors [count, n], syndromes [count, m]) of i.i.d. Pauli noise with probabilities (I, X, Z, Y)."""
+    e = sample_errors_pauli(d, probs, count, workload, p_index, start)
+    return e, syndrome_of(d, e)
 
 
 def make_batch(d: int, p: float, count: int, workload: str = "test", p_index: int = 0, start: int = 0):

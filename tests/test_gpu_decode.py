@@ -72,6 +72,9 @@ def _decisions_agree(gpu_coset, ref_ll, ref_coset, ref_delta, delta1):
     (7, 0.08, 6, 32, 5, 0.1, 8),        # 6x6 blocks with a 1-wide remainder
     (9, 0.10, 6, 32, 4, 0.1, 4),        # 6x6 blocks with a 5-wide remainder, both caps of dimension 8
     (11, 0.09, 6, 32, 3, 0.1, 2),       # 4x4 grid of blocks [6, 6, 6, 3]: every cap pattern of the d=17 workload
+    (5, 0.10, 1, 2, 6, 0.1, 8),         # 1x1 blocks: plain BP between single tensors (the paper's naive limit)
+    (7, 0.10, 2, 4, 5, 0.1, 6),         # 2x2 blocks ([2, 2, 2, 2, 2, 2, 1])
+    (9, 0.10, 5, 32, 4, 0.1, 4),        # 5x5 blocks ([5, 5, 5, 2])
 ])
 def test_fixed_iterations_parity(dev, d, p, k, chi, iters, eta, count):
     _say(f"[parity] d={d} p={p} k={k} chi={chi} iters={iters} eta={eta} count={count}")
@@ -199,3 +202,31 @@ def test_bf16_input_precision_against_oracle(dev, d, p, k, chi, iters, count):
     srt = np.sort(ref["loglik"], axis=1)
     clear = (srt[:, -1] - srt[:, -2]) > 0.2 * tol
     np.testing.assert_array_equal(got["coset"][clear], ref["coset"][clear])
+
+
+@pytest.mark.parametrize("d,k,iters", [(5, 3, 8), (7, 4, 5), (9, 6, 4)])
+def test_biased_noise_parity(dev, d, k, iters):
+    """Z-biased Pauli noise (bias 10, p=0.12) given as four probabilities: the qubit entries take
+    pi[code] for the flipped label; against the oracle with the same pi (same tolerances as above)."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    probs = workload.biased_probs(0.12, 10.0)                       # I, X, Z, Y
+    pi = np.array([[probs[0], probs[2]], [probs[1], probs[3]]])      # oracle layout [x][z]
+    _, syn = workload.make_batch_pauli(d, probs, 6, p_index=d)
+    _say(f"[biased] d={d} k={k} iters={iters}")
+    ref = blockbp.decode(d, 0.12, syn, block=(k, k), chi=32, max_iter=iters, fixed_iters=True, noise=pi,
+                         return_messages=True)
+    opts = bbp.default_opts(block=k, chi=32, max_iter=iters, fixed_iters=1)
+    outs, _, _ = bbp.decode_groups([(d, probs, torch.from_numpy(syn).to(dev))], opts, messages=True)
+    torch.cuda.synchronize()
+    got = {key: v.cpu().numpy() for key, v in outs[0].items()}
+    np.testing.assert_allclose(got["loglik"], ref["loglik"], rtol=0, atol=_ll_tol(ref["loglik"]).max())
+    _check_messages(got["messages"], ref, ref["plan"])
+    _decisions_agree(got["coset"], ref["loglik"], ref["coset"], ref["delta"], 1e-2)
+    np.testing.assert_array_equal(workload.syndrome_of(d, got["correction"]), syn)
+    # depolarizing noise given as four probabilities matches the depolarizing path to FP32 rounding
+    p = 0.1
+    dep = bbp.decode_device(d, p, torch.from_numpy(syn).to(dev), opts)
+    four, _, _ = bbp.decode_groups([(d, (1 - p, p / 3, p / 3, p / 3), torch.from_numpy(syn).to(dev))], opts)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(four[0]["loglik"].cpu().numpy(), dep["loglik"].cpu().numpy(), rtol=0, atol=1e-4)

@@ -65,3 +65,15 @@ def test_coset_labels_differ_by_logicals():
     np.testing.assert_array_equal(z[0, 2] ^ z[0, 0], zm)
     for k in range(4):   # every coset representative carries the same syndrome
         np.testing.assert_array_equal(lattice.syndrome_of_grid(d, x[:, k], z[:, k]), s)
+
+
+def test_pauli_sampler_frequencies():
+    """The biased sampler draws I, X, Z, Y with the given probabilities (4 sigma of the binomial)."""
+    probs = workload.biased_probs(0.1, 10.0)
+    assert abs(sum(probs) - 1.0) < 1e-12 and abs(probs[2] / (probs[1] + probs[3]) - 10.0) < 1e-9
+    e, s = workload.make_batch_pauli(9, probs, 400, p_index=3)
+    n = e.size
+    for code, pr in enumerate(probs):
+        f = np.mean(e == code)
+        assert abs(f - pr) <= 4 * np.sqrt(pr * (1 - pr) / n) + 1e-12, (code, f, pr)
+    np.testing.assert_array_equal(s, workload.syndrome_of(9, e))

@@ -12,8 +12,9 @@ from oracle import lattice, network
 from paper_2402_04834_amd import workload
 
 
-def _bruteforce_coset_probs(d, eps):
-    """P[s_key, coset] = sum of pi(E) over all errors E with syndrome s in coset f_s L G."""
+def _bruteforce_coset_probs(d, eps, pi=None):
+    """P[s_key, coset] = sum of pi(E) over all errors E with syndrome s in coset f_s L G; pi[x][z] the
+    single-qubit Pauli probabilities (default: depolarizing with eps)."""
     n = workload.num_qubits(d)
     m = workload.num_checks(d)
     nz = m // 2                                   # Z-checks come first in the syndrome
@@ -39,12 +40,19 @@ def _bruteforce_coset_probs(d, eps):
     ax = ((bits.astype(np.int64) ^ fxc) @ zbar) & 1
     az = ((bits.astype(np.int64) ^ fzc) @ xbar) & 1
     pc = np.array([bin(v).count("1") for v in range(1 << n)])
-    pw = (1 - eps) ** (n - np.arange(n + 1)) * (eps / 3) ** np.arange(n + 1)
+    if pi is None:
+        pi = [[1 - eps, eps / 3], [eps / 3, eps / 3]]
+    lp = np.log(np.asarray(pi, dtype=np.float64))            # [x][z]
     P = np.zeros((1 << nz, 2, 1 << nz, 2))
     zkey = kz * 2 + az
     for xv in range(1 << n):
-        w = pc[xv | vals]
-        acc = np.bincount(zkey, weights=pw[w], minlength=(1 << nz) * 2).reshape(1 << nz, 2)
+        # per-qubit counts of Y (x and z), X (x only), Z (z only) and I for every z pattern
+        ny = pc[xv & vals]
+        nx = pc[xv] - ny
+        nzz = pc[vals] - ny
+        ni = n - nx - ny - nzz
+        w = np.exp(ni * lp[0, 0] + nx * lp[1, 0] + nzz * lp[0, 1] + ny * lp[1, 1])
+        acc = np.bincount(zkey, weights=w, minlength=(1 << nz) * 2).reshape(1 << nz, 2)
         P[kx[xv], ax[xv]] += acc
     # full syndrome key: bit i of the key = syndrome bit i (Z-checks low, X-checks high)
     out = np.zeros((1 << m, 4))
@@ -80,6 +88,18 @@ def test_coset_sum_is_syndrome_probability_d3(bruteforce_d3):
     got = np.exp(network.exact_coset_loglik(d, s, 0.1)).sum(1)
     np.testing.assert_allclose(got, bruteforce_d3.sum(1), rtol=1e-10)
     assert abs(got.sum() - 1.0) < 1e-12
+
+
+def test_exact_contraction_equals_bruteforce_biased_d3():
+    """Biased Pauli noise (each of I, X, Z, Y its own probability): the qubit tensors take pi[x][z]."""
+    d, m = 3, 12
+    pi = np.array([[0.85, 0.09], [0.04, 0.02]])          # [x][z]: I, Z / X, Y
+    ref = _bruteforce_coset_probs(d, None, pi)
+    s = _all_syndromes(m)
+    x, z = lattice.coset_labels(d, s)
+    got = np.exp(network.exact_log_contraction(d, x, z, pi))
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-18)
+    assert abs(ref.sum() - 1.0) < 1e-12
 
 
 @pytest.mark.parametrize("d", [3, 5, 7])
