@@ -46,10 +46,11 @@ TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/geom.hpp", "paper_2402_04834_amd/c
 
 
 def _short_kernel_name(name):
-    """'void bbp::(anonymous namespace)::sweep_kernel<float, 6, true, ...>(bbp::SweepArgs)' ->
-    'sweep_kernel<6, true, ...>' (the name bbp_timing reports); other kernels keep their name."""
+    """'void bbp::(anonymous namespace)::sweep_kernel<float, 6, true, true, false, true, false>(...)' ->
+    'sweep_kernel<6, true, true, false, true>' (the name bbp_timing reports for the FP32 depolarizing
+    kernels); other kernels keep their name."""
     import re
-    m = re.search(r"sweep_kernel<float, ([^>]*)>", name)
+    m = re.search(r"sweep_kernel<float, (\d+(?:, (?:true|false)){4}), false>", name)
     return f"sweep_kernel<{m.group(1)}>" if m else name
 
 

@@ -236,7 +236,11 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
 }  // namespace
 
 hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
-  const int variant = (cls & 15) | (a.bf16 ? 16 : 0), kt = (cls >> 4) + 1;
+  if (a.small) return launch_small_sweeps(st, a);
+  bool biased = false;
+  for (int k = 0; k < a.ngroups; ++k) biased |= a.g[k].biased != 0;
+  if (biased && a.bf16) return hipErrorInvalidValue;   // refused earlier by resolve()
+  const int variant = (cls & 15) | (a.bf16 ? 16 : 0) | (biased ? 32 : 0), kt = (cls >> 4) + 1;
   const dim3 grid(sweep_groups(a.items));
   switch (kt) {
     case 1: return launch_sweeps_k1(variant, grid, st, a);
@@ -412,6 +416,7 @@ int resolve(const bbp_group* groups, int ng, const bbp_opts* opts, std::vector<G
       if (!(G.noise[0] > 0.0) || std::fabs(sum - 1.0) > 1e-6)
         return fail(BBP_EINVAL, "noise must be probabilities summing to 1 with a positive identity entry");
       if (G.p_dev) return fail(BBP_EINVAL, "noise and p_dev are exclusive");
+      if (opts->precision != 0) return fail(BBP_EUNSUPPORTED, "biased noise runs with precision 0 only");
     } else if (!G.p_dev && !(G.p > 0.0 && G.p < 1.0)) {
       return fail(BBP_EINVAL, "p must be in (0, 1)");
     }
@@ -529,6 +534,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
       sa.order = tn.order;
       sa.bf16 = opts->precision == 1 ? 1 : 0;
       sa.eta = (float)opts->damping;
+      sa.small = (opts->block_rows <= 2 && opts->block_cols <= 2 && opts->precision == 0) ? 1 : 0;
       int64_t items = 0;
       for (int k = 0; k < sa.ngroups; ++k) {
         const GroupRun& g = gr[members[k].first];

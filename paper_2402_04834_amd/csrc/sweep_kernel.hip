@@ -31,7 +31,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 __device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
 
 // V = float: FP32 products (precision 0); V = bfin: products of BF16-rounded inputs, FP32 sums (precision 1).
-template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
+// BIASED: some group of the launch has biased Pauli noise (otherwise the depolarizing entries are compiled
+// in and the biased selection is removed).
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, bool BIASED>
 __global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BBP_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
@@ -67,7 +69,7 @@ void sweep_kernel(SweepArgs a) {
     c.p00 = G.p00;
     c.pe = G.pe;
   }
-  c.biased = G.biased;
+  c.biased = BIASED ? G.biased : 0;
   for (int k = 0; k < 4; ++k) c.pib[k] = __float_as_int(G.pi[k]);
   c.exp2 = 0;
   const uint8_t* lab = G.labels + job * L * L;
@@ -132,11 +134,15 @@ void sweep_kernel(SweepArgs a) {
 #define BBP_CAT(a, b) BBP_CAT2(a, b)
 
 namespace {
+// variants 0..47: bit 4 BF16-input products, bit 5 biased noise (FP32 products only)
 template <int V>
 void launch_variant(dim3 grid, hipStream_t st, const SweepArgs& a) {
   constexpr bool TOP = (V >> 3) & 1, BOT = (V >> 2) & 1, SINGLE = (V >> 1) & 1, Q00 = V & 1;
-  if ((V >> 4) & 1) sweep_kernel<wave::bfin, BBP_KT, TOP, BOT, SINGLE, Q00><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
-  else sweep_kernel<float, BBP_KT, TOP, BOT, SINGLE, Q00><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+  constexpr bool BF = (V >> 4) & 1, BIASED = (V >> 5) & 1;
+  if constexpr (BF)
+    sweep_kernel<wave::bfin, BBP_KT, TOP, BOT, SINGLE, Q00, false><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+  else
+    sweep_kernel<float, BBP_KT, TOP, BOT, SINGLE, Q00, BIASED><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
 }
 
 template <int... I>
@@ -147,9 +153,9 @@ hipError_t dispatch(int variant, dim3 grid, hipStream_t st, const SweepArgs& a, 
 }
 }  // namespace
 
-// variant = (BF16-input products ? 16 : 0) + ((top * 2 + bottom) * 2 + single) * 2 + q00
+// variant = (biased noise ? 32 : BF16-input products ? 16 : 0) + ((top * 2 + bottom) * 2 + single) * 2 + q00
 hipError_t BBP_CAT(launch_sweeps_k, BBP_KT)(int variant, dim3 grid, hipStream_t st, const SweepArgs& a) {
-  return dispatch(variant, grid, st, a, std::make_integer_sequence<int, 32>{});
+  return dispatch(variant, grid, st, a, std::make_integer_sequence<int, 48>{});
 }
 
 }  // namespace bbp

@@ -45,6 +45,7 @@ struct SweepArgs {
   int32_t order;             // item order inside a group: 0 sweep-major (item = sweep * jobs + job), 1 job-major
   int32_t bf16;              // 1: products of BF16-rounded inputs (precision mode 1); 0: FP32 products
   float eta;                 // damping
+  int32_t small;             // 1: every block is at most 2x2 tensors: one lane per item (small_sweep.hip)
 };
 
 // Class of a sweep: the kernel instantiation that runs it -- length, caps present, one position across,
@@ -57,8 +58,11 @@ inline int sweep_class(const SweepDesc& s) {
 // Launch the a.items (job, sweep) items of class `cls` on stream st.
 hipError_t launch_sweeps(int cls, hipStream_t st, const SweepArgs& a);
 
+// blocks of at most 2x2 tensors, any class, FP32 (small_sweep.hip)
+hipError_t launch_small_sweeps(hipStream_t st, const SweepArgs& a);
+
 // per-length launchers (one translation unit each); variant = class code modulo 16, plus 16 for the
-// BF16-input kernels
+// BF16-input kernels or 32 for the biased-noise kernels
 hipError_t launch_sweeps_k1(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
 hipError_t launch_sweeps_k2(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
 hipError_t launch_sweeps_k3(int variant, dim3 grid, hipStream_t st, const SweepArgs& a);
