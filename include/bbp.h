@@ -169,7 +169,7 @@ typedef struct bbp_group {
   float* messages_dev;            /* optional [batch][4][M][64] output: final messages, as in bbp_decode_device */
   double noise[4];                /* optional biased Pauli noise: probabilities of I, X, Z, Y (index = code x + 2z),
                                      non-negative, summing to 1, noise[0] > 0; all zero = depolarizing with p.
-                                     Exclusive with p_dev. */
+                                     Exclusive with p_dev; opts->precision 0 only (else BBP_EUNSUPPORTED). */
 } bbp_group;
 
 /* Workspace for bbp_decode_groups (the groups' own workspaces laid end to end). Output and syndrome

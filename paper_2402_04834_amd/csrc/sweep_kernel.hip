@@ -16,7 +16,7 @@
 #error "compile with -DBBP_KT=<sweep length 1..6>"
 #endif
 #ifndef BBP_WAVES_PER_EU
-#define BBP_WAVES_PER_EU 3   // register budget: at least this many wavefronts per SIMD (no spills)
+#define BBP_WAVES_PER_EU 4   // register budget: at least this many wavefronts per SIMD
 #endif
 
 namespace bbp {

@@ -357,14 +357,16 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
         mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
         mA[a][1] = lane_get(c.mtv, CT::idx(a, 1, 0) + (h & 3));
       });
+      // the emitted bond equals the check's own bit v1: one accumulator per value of v1, unmasked operands,
+      // and the lane keeps the one of its own v1 (the other's products never enter)
       sfor<PSO>([&](auto s) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
         sfor<PTO>([&](auto a) {
           const float x = X[a * PSO + s];
-          acc = mfma4(mA[a][0], v1 ? 0.0f : x, acc);
-          acc = mfma4(mA[a][1], v1 ? x : 0.0f, acc);
+          acc0 = mfma4(mA[a][0], x, acc0);
+          acc1 = mfma4(mA[a][1], x, acc1);
         });
-        sfor<4>([&](auto n) { Z[n * PSO + s] = acc[(int)n]; });
+        sfor<4>([&](auto n) { Z[n * PSO + s] = v1 ? acc1[(int)n] : acc0[(int)n]; });
       });
     } else if constexpr (CT::kind == K_EQ) {
       sfor<PTO>([&](auto a) {
@@ -465,13 +467,13 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
         mB[b][1] = lane_get(c.mbv, CB::idx(b, 1, 0) + (h & 3));
       });
       sfor<PTN>([&](auto n) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
         sfor<PSO>([&](auto b) {
           const float z = Z[n * PSO + b];
-          acc = mfma4(mB[b][0], v1 ? 0.0f : z, acc);
-          acc = mfma4(mB[b][1], v1 ? z : 0.0f, acc);
+          acc0 = mfma4(mB[b][0], z, acc0);
+          acc1 = mfma4(mB[b][1], z, acc1);
         });
-        sfor<4>([&](auto sp) { Y[n * PSN + sp] = acc[(int)sp]; });
+        sfor<4>([&](auto sp) { Y[n * PSN + sp] = v1 ? acc1[(int)sp] : acc0[(int)sp]; });
       });
     } else if constexpr (CB::kind == K_EQ) {
       sfor<PSO>([&](auto b) {
