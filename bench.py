@@ -111,7 +111,18 @@ def cpu_baseline(d, p, block, chi, max_iter):
                        f"<= {max_iter} iterations with early exit, float64, one thread ({dt:.1f} s)")
 
 
-def agreement(out, batch):
+def wilson(k, n, z=1.959964):
+    """95 % Wilson score interval of a binomial proportion k / n."""
+    if n == 0:
+        return None
+    ph = k / n
+    den = 1 + z * z / n
+    mid = (ph + z * z / (2 * n)) / den
+    half = z * ((ph * (1 - ph) / n + z * z / (4 * n * n)) ** 0.5) / den
+    return [max(0.0, mid - half), min(1.0, mid + half)]
+
+
+def agreement(out, batch, errors=None, d=17):
     if not os.path.exists(GOLDEN):
         return None
     g = json.load(open(GOLDEN))
@@ -129,7 +140,26 @@ def agreement(out, batch):
              if it[r["index"], k] == r["iters"][k] and np.isfinite(r["loglik"][k])]
     same_it = sum(int(it[r["index"], k] == r["iters"][k]) for r in recs for k in range(4))
     fin = every[np.isfinite(every)]
-    return dict(syndromes=len(recs), decisions_equal=eq, frac=eq / len(recs),
+    logical = None
+    if errors is not None:
+        # logical failure against the sampled error: GPU from its correction; the oracle's correction differs
+        # from the GPU's by the logical of the coset difference (coset bits (x, z) of I, X, Y, Z)
+        idx = np.array([r["index"] for r in recs])
+        corr = out["correction"].cpu().numpy()
+        xs, zs = logical_class(d, errors[idx], corr[idx])
+        bits = np.array([(0, 0), (1, 0), (1, 1), (0, 1)])
+        go, orc = bits[cos[idx]], bits[np.array([r["coset"] for r in recs])]
+        f_gpu = (xs | zs).astype(bool)
+        f_orc = ((xs ^ go[:, 0] ^ orc[:, 0]) | (zs ^ go[:, 1] ^ orc[:, 1])).astype(bool)
+        allx, allz = logical_class(d, errors[:batch], corr[:batch])
+        n_all = int(((allx | allz) != 0).sum())
+        logical = dict(
+            gpu_fixture=dict(failures=int(f_gpu.sum()), rate=float(f_gpu.mean()), ci95=wilson(int(f_gpu.sum()), len(idx))),
+            oracle_fixture=dict(failures=int(f_orc.sum()), rate=float(f_orc.mean()),
+                                ci95=wilson(int(f_orc.sum()), len(idx))),
+            discordant=dict(gpu_only=int((f_gpu & ~f_orc).sum()), oracle_only=int((f_orc & ~f_gpu).sum())),
+            gpu_batch=dict(syndromes=int(batch), failures=n_all, rate=n_all / batch, ci95=wilson(n_all, batch)))
+    return dict(syndromes=len(recs), decisions_equal=eq, frac=eq / len(recs), logical_failure=logical,
                 cosets=4 * len(recs), cosets_same_iterations=same_it,
                 abs_dlnz_all_cosets=dict(max=float(fin.max()), p99=float(np.percentile(fin, 99)),
                                          median=float(np.median(fin)), nonfinite=int(every.size - fin.size))
@@ -193,7 +223,7 @@ def main():
         del src, dst
 
     d, p, block, chi, max_iter = 17, 0.10, a.block, 32, 20
-    _, syn = workload.make_batch(d, p, a.batch, workload="d17")
+    errors, syn = workload.make_batch(d, p, a.batch, workload="d17")
     dev = torch.device("cuda:0")
     syn_dev = torch.from_numpy(syn).to(dev)
     opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1,
@@ -268,7 +298,7 @@ def main():
                            autotuned_streams=tune.streams, autotuned_value=tuned, tuning_decode_ms=tune.ms),
         plan=dict(messages_per_coset=info.num_messages, exact_sweeps=bool(info.exact_sweeps),
                   max_boundary_rank=info.max_boundary_rank),
-        agreement=agreement(out, a.batch) if block == 6 else None,
+        agreement=agreement(out, a.batch, errors, d) if block == 6 else None,
     )
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, p, block, chi, max_iter)
@@ -377,10 +407,9 @@ def biased_main(a):
     print(json.dumps(line), flush=True)
 
 
-def logical_failures(d, errors, corrections):
-    """1 where the correction differs from the sampled error by a logical operator: the product P (no
-    syndrome) anticommutes with Z on the column-0 horizontal edges (an X logical component) or with X on
-    the row-0 horizontal edges (a Z logical component)."""
+def logical_class(d, errors, corrections):
+    """Logical components (x, z) of error * correction (no syndrome): the product anticommutes with Z on the
+    column-0 horizontal edges iff it has an X logical component, with X on row 0 iff a Z component."""
     import numpy as np
     from paper_2402_04834_amd import workload
     q = workload.qubit_coords(d)
@@ -389,6 +418,13 @@ def logical_failures(d, errors, corrections):
     row0 = (q[:, 0] == 0)
     xs = np.bitwise_xor.reduce(prod[:, col0] & 1, axis=1)
     zs = np.bitwise_xor.reduce((prod[:, row0] >> 1) & 1, axis=1)
+    return xs, zs
+
+
+def logical_failures(d, errors, corrections):
+    """1 where the correction differs from the sampled error by a logical operator."""
+    import numpy as np
+    xs, zs = logical_class(d, errors, corrections)
     return (xs | zs).astype(np.float64)
 
 

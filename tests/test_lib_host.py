@@ -122,3 +122,61 @@ def test_reference_sweep_matches_oracle(bbp, d, k):
             w = mps.to_dense(st)[0][0]
             wg = got[0]
         np.testing.assert_allclose(np.log(wg) + ls, np.log(w) + lr[0], atol=1e-7)
+
+
+def _group(d, p=0.1, batch=4, noise=None, p_dev=None):
+    from paper_2402_04834_amd import _lib
+    g = _lib.bbp_group()
+    g.d, g.p, g.batch = d, p, batch
+    if noise is not None:
+        for k in range(4):
+            g.noise[k] = noise[k]
+    g.p_dev = p_dev
+    return g
+
+
+def test_group_validation(bbp):
+    """bbp_workspace_size_groups validates every group (host only): noise probabilities, p, group count."""
+    import ctypes as C
+    from paper_2402_04834_amd import _lib
+    h = _lib.lib()
+    n = C.c_size_t()
+    opts = bbp.default_opts(block=6, chi=32)
+
+    def size(groups, o=opts):
+        arr = (_lib.bbp_group * len(groups))(*groups)
+        return h.bbp_workspace_size_groups(arr, len(groups), C.byref(o), C.byref(n))
+
+    assert size([_group(9)]) == _lib.BBP_OK and n.value > 0
+    one = n.value
+    assert size([_group(9), _group(9)]) == _lib.BBP_OK and n.value >= 2 * one
+    assert size([_group(9, noise=(0.9, 0.02, 0.06, 0.02))]) == _lib.BBP_OK
+    assert size([_group(9, noise=(0.9, 0.02, 0.06, 0.03))]) == _lib.BBP_EINVAL          # does not sum to 1
+    assert size([_group(9, noise=(0.0, 0.5, 0.5, 0.0))]) == _lib.BBP_EINVAL             # no identity weight
+    assert size([_group(9, noise=(1.2, -0.1, -0.05, -0.05))]) == _lib.BBP_EINVAL        # negative entries
+    assert size([_group(9, noise=(0.9, 0.02, 0.06, 0.02), p_dev=8)]) == _lib.BBP_EINVAL  # exclusive with p_dev
+    assert size([_group(9, noise=(0.9, 0.02, 0.06, 0.02))], bbp.default_opts(block=6, chi=32, precision=1)) \
+        == _lib.BBP_EUNSUPPORTED
+    assert size([_group(9, p=1.5)]) == _lib.BBP_EINVAL
+    assert size([_group(9)] * 9) == _lib.BBP_EINVAL                                     # at most 8 groups
+
+
+def test_warm_start_host_side(bbp):
+    """Parameter count of the network and workspace sizes; argument checks that precede any device work."""
+    import ctypes as C
+    from paper_2402_04834_amd import _lib, warm
+    from oracle import warmnet
+    assert warm.param_count() == warmnet.count() == 198648
+    opts = bbp.default_opts(block=6, chi=32)
+    small = warm.workspace_size(9, 4, opts, False)
+    assert warm.workspace_size(9, 10000, opts, False) == warm.workspace_size(9, 512, opts, False) > small
+    assert warm.workspace_size(9, 64, opts, True) > warm.workspace_size(9, 16, opts, True)
+    h = _lib.lib()
+    n = C.c_size_t()
+    assert h.bbp_warm_workspace_size(9, 4, C.byref(bbp.default_opts(block=7, chi=32)), 0, C.byref(n)) \
+        == _lib.BBP_EINVAL
+    assert h.bbp_warm_predict(9, 0.1, None, None, 4, C.byref(opts), None, None, None, 0, None) == _lib.BBP_EINVAL
+    assert h.bbp_warm_adam(None, None, None, None, 1, C.c_float(1e-3), None) == _lib.BBP_EINVAL
+    assert "NULL" in h.bbp_warm_last_error().decode() or "pointer" in h.bbp_warm_last_error().decode()
+    # the committed weights have the network's shape
+    assert warm.load().shape == (warm.param_count(),)
