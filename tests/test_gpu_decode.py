@@ -182,6 +182,36 @@ def test_full_size_d17_against_oracle_fixture(dev):
     assert np.all(np.isfinite(got["loglik"][np.arange(4096), got["coset"]]))
 
 
+@pytest.mark.parametrize("tag", ["p005", "p010", "p015"])
+def test_d11_configuration_against_oracle_fixture(dev, tag):
+    """Plain FP32 blockBP at d=11 (p 0.05, 0.10, 0.15; 1024 syndromes each, 4x4 blocks, chi=16, 20
+    iterations, damping 0.5): the whole batch is decoded, the first 48 syndromes are checked against the
+    committed oracle fixture (tests/golden/d11_<p>_k4_chi16_eta05.json, from oracle/ only)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"d11_{tag}_k4_chi16_eta05.json")
+    g = json.load(open(path))
+    meta = g["meta"]
+    assert (meta["d"], meta["block"], meta["chi"], meta["max_iter"], meta["eta"]) == (11, 4, 16, 20, 0.5)
+    _say(f"[d=11] p={meta['p']} batch=1024, {len(g['records'])} oracle records")
+    _, syn = workload.make_batch(11, meta["p"], 1024, workload=meta["workload"], p_index=meta["p_index"])
+    got = _gpu_decode(dev, 11, meta["p"], syn, messages=False, block=4, chi=16, max_iter=20,
+                      damping=meta["eta"], delta0=meta["delta0"], delta1=meta["delta1"])
+    idx = np.array([r["index"] for r in g["records"]])
+    ref_ll = np.array([r["loglik"] for r in g["records"]])
+    ref_dl = np.array([r["delta"] for r in g["records"]])
+    ref_it = np.array([r["iters"] for r in g["records"]])
+    ref_cs = np.array([r["coset"] for r in g["records"]])
+    it, ll = got["iters"][idx], got["loglik"][idx]
+    near = np.abs(np.log(np.maximum(ref_dl, 1e-30) / meta["delta0"])) < 0.05
+    assert np.all((it == ref_it) | near)
+    same = (it == ref_it) & np.isfinite(ref_ll)
+    np.testing.assert_array_less(np.abs(ll[same] - ref_ll[same]), _ll_tol(ref_ll[same]))
+    _decisions_agree(got["coset"][idx], ref_ll, ref_cs, ref_dl, meta["delta1"])
+    assert np.all(got["coset"] < 4)
+    np.testing.assert_array_equal(workload.syndrome_of(11, got["correction"]), syn)
+
+
 @pytest.mark.parametrize("d,p,k,chi,iters,count", [(5, 0.10, 3, 4, 10, 16), (7, 0.08, 6, 32, 5, 6), (9, 0.10, 6, 32, 4, 4)])
 def test_bf16_input_precision_against_oracle(dev, d, p, k, chi, iters, count):
     """Precision mode 1 (every product takes BF16-rounded inputs, FP32 sums). Bound: each of the n qubit
