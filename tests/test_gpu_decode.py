@@ -182,6 +182,20 @@ def test_full_size_d17_against_oracle_fixture(dev):
     assert np.all(np.isfinite(got["loglik"][np.arange(4096), got["coset"]]))
 
 
+def test_d5_configuration_against_oracle(dev):
+    """The small configuration whole: d=5, p=0.10, 200 seeded syndromes, 3x3 blocks, chi=4, 10 iterations;
+    every coset estimate, message and decision against the oracle."""
+    d, p = 5, 0.10
+    _, syn = workload.make_batch(d, p, 200, workload="d5")
+    _say("[d=5] 200 syndromes, fixed 10 iterations")
+    ref = blockbp.decode(d, p, syn, block=(3, 3), chi=4, max_iter=10, fixed_iters=True, return_messages=True)
+    got = _gpu_decode(dev, d, p, syn, block=3, chi=4, max_iter=10, fixed_iters=1)
+    np.testing.assert_allclose(got["loglik"], ref["loglik"], rtol=0, atol=_ll_tol(ref["loglik"]).max())
+    _check_messages(got["messages"], ref, ref["plan"])
+    _decisions_agree(got["coset"], ref["loglik"], ref["coset"], ref["delta"], 1e-2)
+    _say(f"   decisions equal: {(got['coset'] == ref['coset']).sum()} / 200")
+
+
 @pytest.mark.parametrize("tag", ["p005", "p010", "p015"])
 def test_d11_configuration_against_oracle_fixture(dev, tag):
     """Plain FP32 blockBP at d=11 (p 0.05, 0.10, 0.15; 1024 syndromes each, 4x4 blocks, chi=16, 20
