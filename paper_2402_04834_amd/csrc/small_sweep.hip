@@ -22,20 +22,6 @@ namespace {
 
 constexpr int SIDE_E = 0, SIDE_W = 1, SIDE_S = 2, SIDE_N = 3;
 
-struct Var {          // a check variable of the contraction
-  int r, c;
-};
-
-// variable index of the check at (r, c), adding it when new; -1 for a site outside the grid
-__device__ __forceinline__ int var_of(Var* v, int& nv, int r, int c, int L) {
-  if (r < 0 || r >= L || c < 0 || c >= L) return -1;
-  for (int k = 0; k < nv; ++k)
-    if (v[k].r == r && v[k].c == c) return k;
-  v[nv].r = r;
-  v[nv].c = c;
-  return nv++;
-}
-
 // sites (inside, outside) of leg i of the block's side
 __device__ __forceinline__ void leg_sites(int side, int r0, int c0, int kr, int kc, int i, int& ra, int& ca, int& rb,
                                          int& cb) {
@@ -45,6 +31,12 @@ __device__ __forceinline__ void leg_sites(int side, int r0, int c0, int kr, int 
     case SIDE_S: ra = r0 + kr - 1; ca = c0 + i; rb = ra + 1; cb = ca; break;
     default:     ra = r0; ca = c0 + i; rb = ra - 1; cb = ca; break;
   }
+}
+
+// entry e (0..3) of four values, without indexing a private array
+__device__ __forceinline__ float sel4(float a0, float a1, float a2, float a3, int e) {
+  const float lo = (e & 1) ? a1 : a0, hi = (e & 1) ? a3 : a2;
+  return (e & 2) ? hi : lo;
 }
 
 __global__ __launch_bounds__(256) void small_sweep_kernel(SweepArgs a) {
@@ -70,9 +62,12 @@ __global__ __launch_bounds__(256) void small_sweep_kernel(SweepArgs a) {
   const float* mbase = G.msgs + job * G.M * MSTRIDE;
 
   // Pauli probabilities by code x + 2z
-  float pi[4];
+  float pi0, pi1, pi2, pi3;
   if (G.biased) {
-    for (int k = 0; k < 4; ++k) pi[k] = G.pi[k];
+    pi0 = G.pi[0];
+    pi1 = G.pi[1];
+    pi2 = G.pi[2];
+    pi3 = G.pi[3];
   } else {
     float p00 = G.p00, pe = G.pe;
     if (G.pdev) {
@@ -80,121 +75,144 @@ __global__ __launch_bounds__(256) void small_sweep_kernel(SweepArgs a) {
       p00 = 1.0f - pj;
       pe = pj / 3.0f;
     }
-    pi[0] = p00;
-    pi[1] = pi[2] = pi[3] = pe;
+    pi0 = p00;
+    pi1 = pi2 = pi3 = pe;
   }
 
   // incoming messages by side; the receiver side carries the output (mode 0) or msg_close (mode 1)
   const int out_side = s.frame;
-  const int opp[4] = {SIDE_W, SIDE_E, SIDE_N, SIDE_S};
-  int mid[4] = {-1, -1, -1, -1};
-  mid[opp[out_side]] = s.msg_init;
-  if (out_side <= SIDE_W) {
-    mid[SIDE_N] = s.msg_top;
-    mid[SIDE_S] = s.msg_bot;
-  } else {
-    mid[SIDE_W] = s.msg_top;
-    mid[SIDE_E] = s.msg_bot;
+  int mid[4];
+  const int init_side = (out_side == SIDE_E) ? SIDE_W : (out_side == SIDE_W) ? SIDE_E : (out_side == SIDE_S) ? SIDE_N
+                                                                                                           : SIDE_S;
+#pragma unroll
+  for (int side = 0; side < 4; ++side) {
+    int id = -1;
+    if (side == init_side) id = s.msg_init;
+    else if (side == out_side) id = (a.mode == 1) ? s.msg_close : -1;
+    else if (out_side <= SIDE_W) id = (side == SIDE_N) ? s.msg_top : s.msg_bot;
+    else id = (side == SIDE_W) ? s.msg_top : s.msg_bot;
+    mid[side] = id;
   }
-  if (a.mode == 1) mid[out_side] = s.msg_close;
 
-  // variables: the block's checks, then the outside checks across its boundary
-  Var v[12];
-  int nv = 0;
-  int qr[2], qlab[2], qnb[2][4];   // the block's qubits: row, label, variables (up, left, down, right)
-  int nq = 0;
-  for (int r = s.r0; r < s.r0 + s.kr; ++r)
-    for (int c = s.c0; c < s.c0 + s.kc; ++c)
-      if (((r + c) & 1) != 0) var_of(v, nv, r, c, L);
-  for (int r = s.r0; r < s.r0 + s.kr; ++r)
-    for (int c = s.c0; c < s.c0 + s.kc; ++c)
-      if (((r + c) & 1) == 0) {
-        qr[nq] = r;
-        qlab[nq] = lab[r * L + c] & 3;
-        qnb[nq][0] = var_of(v, nv, r - 1, c, L);
-        qnb[nq][1] = var_of(v, nv, r, c - 1, L);
-        qnb[nq][2] = var_of(v, nv, r + 1, c, L);
-        qnb[nq][3] = var_of(v, nv, r, c + 1, L);
+  // A variable is a check site of the block or of its one-site halo, numbered by its position
+  // (r - r0 + 1) * 4 + (c - c0 + 1) < 16; an assignment of all variables is a 16-bit mask.
+  auto pos = [&](int r, int c) -> int {
+    return (r < 0 || r >= L || c < 0 || c >= L) ? -1 : (r - s.r0 + 1) * 4 + (c - s.c0 + 1);
+  };
+  int used = 0;
+  int qx[2] = {0, 0}, qnb[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}}, nq = 0;   // qx: label | vertical-edge flag << 2
+#pragma unroll
+  for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+    for (int dc = 0; dc < 2; ++dc) {
+      const int r = s.r0 + dr, c = s.c0 + dc;
+      if (dr >= s.kr || dc >= s.kc) continue;
+      if (((r + c) & 1) != 0) {
+        used |= 1 << pos(r, c);
+      } else {
+        const int nb[4] = {pos(r - 1, c), pos(r, c - 1), pos(r + 1, c), pos(r, c + 1)};
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (q == nq) {
+            qx[q] = (lab[r * L + c] & 3) | ((r & 1) << 2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              qnb[q][k] = nb[k];
+              if (nb[k] >= 0) used |= 1 << nb[k];
+            }
+          }
         ++nq;
       }
-  // legs of each side: the variable each carries (-1 where the leg leaves the grid)
-  int legv[4][2], K[4];
+    }
+  // legs: the variable (position) each carries, -1 where the leg leaves the grid; message entries
+  int legp[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}}, K[4];
+  float m[4][4];
+#pragma unroll
   for (int side = 0; side < 4; ++side) {
     K[side] = (side <= SIDE_W) ? s.kr : s.kc;
-    for (int i = 0; i < K[side]; ++i) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (i >= K[side]) continue;
       int ra, ca, rb, cb;
       leg_sites(side, s.r0, s.c0, s.kr, s.kc, i, ra, ca, rb, cb);
-      const bool a_check = ((ra + ca) & 1) != 0;
-      legv[side][i] = a_check ? var_of(v, nv, ra, ca, L)
-                              : ((rb < 0 || rb >= L || cb < 0 || cb >= L) ? -1 : var_of(v, nv, rb, cb, L));
+      legp[side][i] = (((ra + ca) & 1) != 0) ? pos(ra, ca) : pos(rb, cb);
     }
-  }
-  // message entries, read once
-  float m[4][4];
-  for (int side = 0; side < 4; ++side)
+#pragma unroll
     for (int e = 0; e < 4; ++e)
       m[side][e] = (mid[side] >= 0 && e < (1 << K[side])) ? mbase[mid[side] * MSTRIDE + e] : 0.0f;
+  }
 
-  // weight of one assignment x of all variables (bit k = variable k), without the output side's message
+  auto bitof = [](int x, int p) { return p < 0 ? 0 : (x >> p) & 1; };
+  // weight of one assignment x, the receiver side's message included or not
   auto weight = [&](int x, bool with_out) -> float {
     float w = 1.0f;
-    for (int q = 0; q < nq; ++q) {
-      auto val = [&](int k) { return k < 0 ? 0 : (x >> k) & 1; };
-      const int u = val(qnb[q][0]), l = val(qnb[q][1]), dn = val(qnb[q][2]), rt = val(qnb[q][3]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nq) continue;
+      const int u = bitof(x, qnb[q][0]), l = bitof(x, qnb[q][1]), dn = bitof(x, qnb[q][2]), rt = bitof(x, qnb[q][3]);
       // horizontal edge (even row): checks above / below flip x, left / right flip z; vertical edge: swapped
-      const int px = (qr[q] & 1) ? (l ^ rt) : (u ^ dn);
-      const int pz = (qr[q] & 1) ? (u ^ dn) : (l ^ rt);
-      w *= pi[(qlab[q] ^ px ^ (pz << 1)) & 3];
+      const bool vert = (qx[q] >> 2) & 1;
+      const int px = vert ? (l ^ rt) : (u ^ dn), pz = vert ? (u ^ dn) : (l ^ rt);
+      w *= sel4(pi0, pi1, pi2, pi3, (qx[q] ^ px ^ (pz << 1)) & 3);
     }
+#pragma unroll
     for (int side = 0; side < 4; ++side) {
       if (mid[side] < 0 || (side == out_side && !with_out)) continue;
       int e = 0;
-      for (int i = 0; i < K[side]; ++i) {
-        const int k = legv[side][i];
-        e = (e << 1) | (k < 0 ? 0 : (x >> k) & 1);
-      }
-      w *= m[side][e];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (i < K[side]) e = (e << 1) | bitof(x, legp[side][i]);
+      w *= sel4(m[side][0], m[side][1], m[side][2], m[side][3], e);
     }
     return w;
   };
 
   if (a.mode == 1) {
     double W = 0.0;
-    for (int x = 0; x < (1 << nv); ++x) W += (double)weight(x, true);
+    for (int sub = used;; sub = (sub - 1) & used) {
+      W += (double)weight(sub, true);
+      if (sub == 0) break;
+    }
     G.lnW[job * G.nblocks + s.block] = (W > 0.0) ? log(W) : NAN;
     return;
   }
-  // outgoing message: entries over the receiver side's legs (leg 0 most significant)
+  // outgoing message: entries over the receiver side's legs (leg 0 most significant); the legs fix their
+  // (distinct) variables, and a leg leaving the grid only takes 0
   const int Ko = K[out_side], H = 1 << Ko;
-  int fixed = 0;   // variables the output legs fix
-  for (int i = 0; i < Ko; ++i)
-    if (legv[out_side][i] >= 0) fixed |= 1 << legv[out_side][i];
+  int fixed = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    if (i < Ko && legp[out_side][i] >= 0) fixed |= 1 << legp[out_side][i];
+  const int free_mask = used & ~fixed;
   float fin[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int h = 0; h < H; ++h) {
-    // the output legs fix their (distinct) variables; a leg leaving the grid only takes 0
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    if (h >= H) continue;
     int base = 0;
     bool ok = true;
-    for (int i = 0; i < Ko; ++i) {
-      const int b = (h >> (Ko - 1 - i)) & 1, k = legv[out_side][i];
-      if (k < 0) ok = ok && b == 0;
-      else base |= b << k;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (i >= Ko) continue;
+      const int b = (h >> (Ko - 1 - i)) & 1, p = legp[out_side][i];
+      if (p < 0) ok = ok && b == 0;
+      else base |= b << p;
     }
-    if (!ok) continue;
     float acc = 0.0f;
-    const int free_mask = ((1 << nv) - 1) & ~fixed;
-    // enumerate the free variables as subsets of free_mask
-    for (int sub = free_mask;; sub = (sub - 1) & free_mask) {
-      acc += weight(base | sub, false);
-      if (sub == 0) break;
-    }
+    if (ok)
+      for (int sub = free_mask;; sub = (sub - 1) & free_mask) {
+        acc += weight(base | sub, false);
+        if (sub == 0) break;
+      }
     fin[h] = acc;
   }
   // normalised new message, damping against the old one, distance term
   float* mo = G.msgs + job * G.M * MSTRIDE + s.msg_out * MSTRIDE;
   float ss = 0.0f;
+#pragma unroll
   for (int h = 0; h < 4; ++h) ss += fin[h] * fin[h];
   const float rn = ss > 0.0f ? __builtin_amdgcn_rsqf(ss) : 0.0f;
   float dm[4], old[4], t2 = 0.0f;
+#pragma unroll
   for (int h = 0; h < 4; ++h) {
     old[h] = h < H ? mo[h] : 0.0f;
     dm[h] = (1.0f - a.eta) * (fin[h] * rn) + a.eta * old[h];
@@ -202,6 +220,7 @@ __global__ __launch_bounds__(256) void small_sweep_kernel(SweepArgs a) {
   }
   const float rd = t2 > 0.0f ? __builtin_amdgcn_rsqf(t2) : 0.0f;
   float dd = 0.0f, su = 0.0f;
+#pragma unroll
   for (int h = 0; h < 4; ++h) {
     const float fm = dm[h] * rd;
     dd += (fm - old[h]) * (fm - old[h]);
