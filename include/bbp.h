@@ -48,7 +48,9 @@ typedef struct bbp_opts {
   int32_t precision;    /* 0 = FP32 block contractions (FP64 convergence distance and Bethe sums) */
   int32_t graph;        /* 1 = capture the decode of a call into a HIP graph on first use and replay it on
                            later calls with identical arguments (pointers, sizes, options, stream); needs a
-                           stream other than the default stream; ignored when timing is requested */
+                           stream other than the default stream; ignored when timing is requested. At most
+                           64 graphs are kept; the 65th argument set empties the cache (after a device
+                           synchronisation) */
 } bbp_opts;
 
 /* Defaults of Sec. IV: 6x6 blocks, chi 16, 20 iterations, delta0 1e-4, delta1 1e-2, eta 0.1; eager

@@ -651,8 +651,11 @@ int collect_timing(std::vector<GroupRun>& gr, const bbp_opts* opts, std::vector<
   return BBP_OK;
 }
 
-// Instantiated graphs of whole decodes, keyed by every argument that the captured work depends on.
+// Instantiated graphs of whole decodes, keyed by every argument that the captured work depends on. At most
+// MAX_GRAPHS are kept: a new one beyond that empties the cache after a device synchronisation (no replay of
+// an evicted graph can still be in flight).
 std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
+constexpr size_t MAX_GRAPHS = 64;
 
 template <class T>
 uint64_t u64(T v) {
@@ -745,7 +748,18 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(BBP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     std::lock_guard<std::mutex> lk(g_mu);
-    g_graphs[key] = exec;
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {   // another thread captured the same decode meanwhile: keep one
+      (void)hipGraphExecDestroy(exec);
+      exec = it->second;
+    } else {
+      if (g_graphs.size() >= MAX_GRAPHS) {
+        HIP_TRY(hipDeviceSynchronize());
+        for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+        g_graphs.clear();
+      }
+      g_graphs[key] = exec;
+    }
   }
   HIP_TRY(hipGraphLaunch(exec, st));
   return BBP_OK;
