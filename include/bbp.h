@@ -237,10 +237,12 @@ int bbp_warm_param_count(int64_t* count);
 int bbp_warm_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, int32_t train, size_t* bytes);
 
 /* Predicted start messages of batch syndromes [batch][2d(d-1)] (noise rate p, or p_dev [batch] when not
- * NULL): messages_dev [batch][4][M][64], unit norm, zero beyond 2^K (M and K as in bbp_plan_query). */
+ * NULL): messages_dev [batch][4][M][64], unit norm, zero beyond 2^K (M and K as in bbp_plan_query).
+ * precision 0: FP32 convolutions (the arithmetic of training); 1: BF16 weights and activations with FP32
+ * accumulation (inference; the convolution weights are rounded to BF16 from params_dev on each call). */
 int bbp_warm_predict(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                     const bbp_opts* opts, const float* params_dev, float* messages_dev, void* workspace,
-                     size_t workspace_bytes, void* stream);
+                     const bbp_opts* opts, const float* params_dev, int32_t precision, float* messages_dev,
+                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Loss and gradient of the network on a training batch: targets_dev [batch][4][M][64] (converged messages,
  * non-negative, entries beyond 2^K ignored), use_dev [batch * 4] (1 = train on every message of that coset
@@ -260,10 +262,11 @@ int bbp_warm_adam(float* params_dev, const float* grad_dev, float* m_dev, float*
  * every syndrome with a coset whose final distance is not below opts->delta1 is decoded again from the
  * uniform start, and its results replace the warm ones (its iteration counts are the sum of both runs).
  * Outputs as bbp_decode_device; *fallback_count (host, may be NULL) receives the number of reruns. The call
- * synchronises `stream` once (to size the fallback batch). */
+ * synchronises `stream` once (to size the fallback batch). precision: the network's, as bbp_warm_predict. */
 int bbp_warm_decode_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* bytes);
 int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                    const bbp_opts* opts, const float* params_dev, void* workspace, size_t workspace_bytes,
+                    const bbp_opts* opts, const float* params_dev, int32_t precision, void* workspace,
+                    size_t workspace_bytes,
                     double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
                     uint8_t* correction_dev, int64_t* fallback_count, void* stream);
 

@@ -132,14 +132,27 @@ def conv(X, W, b):
     return (im2col(X) @ W + b).reshape(L, L, -1)
 
 
-def trunk(prm, X0):
-    """Forward of the three convolutions; returns the features and the intermediates for backward."""
+def trunk(prm, X0, store=None):
+    """Forward of the three convolutions; returns the features and the intermediates for backward.
+    store: optional rounding applied where the inference variant stores values in a narrower format (the
+    input channels and the two hidden activations); None = exact."""
+    keep = (lambda a: a) if store is None else store
+    X0 = keep(X0)
     Z1 = conv(X0, prm["conv1.W"], prm["conv1.b"])
-    A1 = np.maximum(Z1, 0.0)
+    A1 = keep(np.maximum(Z1, 0.0))
     Z2 = conv(A1, prm["conv2.W"], prm["conv2.b"])
-    A2 = np.maximum(Z2, 0.0)
+    A2 = keep(np.maximum(Z2, 0.0))
     F = conv(A2, prm["conv3.W"], prm["conv3.b"])
     return F, (X0, Z1, A1, Z2, A2)
+
+
+def round_bf16(x):
+    """Round to BF16 (8 significant bits, nearest even) through the float32 bit pattern; the BF16
+    inference variant stores its input channels, hidden activations and convolution weights this way."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 DIRECTIONS = {"E": 0, "W": 1, "S": 2, "N": 3}
@@ -248,10 +261,10 @@ def loss_and_grad(theta, X0, d, plan, targets, msg_ids, ch=CHANNELS):
     return total / n, pack(grads, ch)
 
 
-def predict(theta, X0, d, plan, ch=CHANNELS):
-    """Dense initial messages [M, 64] of one coset job."""
+def predict(theta, X0, d, plan, ch=CHANNELS, store=None):
+    """Dense initial messages [M, 64] of one coset job (store: see trunk)."""
     prm = unpack(theta, ch)
-    F, _ = trunk(prm, X0)
+    F, _ = trunk(prm, X0, store)
     out = np.zeros((plan.M, 64))
     for e in range(plan.M):
         lg = legs(d, plan, e)

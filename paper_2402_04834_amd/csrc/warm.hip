@@ -8,8 +8,9 @@
 //          generator bit G at checks (features_kernel); no absolute position, so that the network applies
 //          unchanged to distances it was not trained on;
 //   trunk  three 3x3 convolutions with zero padding (11 -> 64 -> 128 -> 96 channels), ReLU after the first
-//          two; each is an implicit GEMM on the matrix cores (v_mfma_f32_16x16x4f32, FP32 products and
-//          sums); activations are row-major [site][channel];
+//          two; each is an implicit GEMM on the matrix cores: FP32 (v_mfma_f32_16x16x4f32) for training and
+//          for parity, or BF16 weights and activations with FP32 sums (v_mfma_f32_16x16x16bf16) for inference;
+//          activations are row-major [site][channel];
 //   head   per directed message with K legs (leg i joins site a_i of the sender to site b_i across the
 //          boundary), with f_i = [F(a_i), F(b_i)] and the weights of the message's direction:
 //          u_i = Wu^T f_i + bu (2 values), P_i = Wp^T [f_i, f_{i+1}] + bp (4 values),
@@ -90,8 +91,18 @@ __device__ __forceinline__ float wmax(float v) {
 // of (f_s L)^z on the horizontal edges left of it in row r. They are quadrant parities of the syndrome: the
 // non-local part of where the coset network's generator variables concentrate, out of reach of 3x3
 // convolutions.
+// BF16 storage (round to nearest even on the bit pattern) and widening
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ void store_el(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_el(unsigned short* p, float v) { *p = f2bf(v); }
+
+template <class T>
 __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict__ syn, const double* __restrict__ pdev,
-                                                       float p, int d, float* __restrict__ X) {
+                                                       float p, int d, T* __restrict__ X) {
   __shared__ uint8_t s[2 * 32 * 31];
   __shared__ uint8_t Q[64][64];   // bit 0: (f_s)^x, bit 1: (f_s)^z on horizontal edges
   __shared__ uint8_t G[64][64];   // generator bits of coset I at check sites
@@ -166,8 +177,8 @@ __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict
     v[7] = 1.0f;
     v[8] = (float)bx;
     v[9] = (float)bz;
-    float* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * C0;
-    for (int k = 0; k < C0; ++k) o[k] = v[k];
+    T* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * C0;
+    for (int k = 0; k < C0; ++k) store_el(o + k, v[k]);
   }
 }
 
@@ -298,6 +309,91 @@ __global__ __launch_bounds__(256) void conv_gemm(int L, int64_t rows, int cin, i
         } else {
           atomicAdd(dst, v);
         }
+      }
+}
+
+// Forward convolution in BF16 (inference): activations and weights stored as BF16, products and sums in FP32
+// on v_mfma_f32_16x16x16bf16 (lane l supplies A row l%16 and B column l%16, k = 4 (l/16) .. +3 of a 16-step).
+// Same gather as conv_gemm<G_FWD>; 64 x 64 output tile per workgroup of four waves (2 x 2 blocks of 16 x 16
+// each), K in chunks of 32 staged in LDS with k innermost for both operands (8-byte fragment reads).
+typedef short bf4 __attribute__((ext_vector_type(4)));
+
+__global__ void to_bf16_kernel(const float* __restrict__ src, unsigned short* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = f2bf(src[i]);
+}
+
+template <int RELU, bool OUT_BF>
+__global__ __launch_bounds__(256) void conv_fwd_bf16(int L, int64_t rows, int cin, int cout,
+                                                     const unsigned short* __restrict__ X,
+                                                     const unsigned short* __restrict__ W,
+                                                     const float* __restrict__ bias, void* __restrict__ Y) {
+  __shared__ __align__(16) unsigned short As[64][40];   // [row][k], 32 k + 8 pad
+  __shared__ __align__(16) unsigned short Bs[64][40];   // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * 64;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int K = 9 * cin;
+  f4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int amm = tid >> 2, akq = (tid & 3) * 8;   // A: row amm, k = akq .. akq + 7 of the chunk
+  const bool arow_ok = m0 + amm < rows;
+  Site arow{0, 0, 0};
+  if (arow_ok) arow = site_of(m0 + amm, L);
+  const int bkk = tid >> 3, bnq = (tid & 7) * 8;   // B: k = bkk of the chunk, n = bnq .. bnq + 7
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    if ((cin & 7) == 0) {   // the 8 k of a thread lie in one tap: one 16-byte load
+      const int k = k0 + akq;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (arow_ok && k < K) {
+        const int tap = k / cin, ch = k - tap * cin;
+        const int64_t src = shifted(arow, tap, 1, L);
+        if (src >= 0) v = *(const uint4*)(X + src * cin + ch);
+      }
+      *(uint4*)&As[amm][akq] = v;
+    } else {
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + akq + j;
+        unsigned short v = 0;
+        if (arow_ok && k < K) {
+          const int tap = k / cin, ch = k - tap * cin;
+          const int64_t src = shifted(arow, tap, 1, L);
+          if (src >= 0) v = X[src * cin + ch];
+        }
+        As[amm][akq + j] = v;
+      }
+    }
+    {
+      const int k = k0 + bkk;
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + bnq + j;
+        Bs[bnq + j][bkk] = (k < K && n < cout) ? W[(int64_t)k * cout + n] : (unsigned short)0;
+      }
+    }
+    __syncthreads();
+    for (int ks = 0; ks < 2; ++ks) {
+      const int kk = ks * 16 + 4 * (lane >> 4);
+      bf4 a[2], b[2];
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf4*)&As[wm + i * 16 + (lane & 15)][kk];
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf4*)&Bs[wn + j * 16 + (lane & 15)][kk];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row >= rows || col >= cout) continue;
+        float v = acc[i][j][r] + bias[col];
+        if (RELU) v = fmaxf(v, 0.0f);
+        if (OUT_BF) ((unsigned short*)Y)[row * cout + col] = f2bf(v);
+        else ((float*)Y)[row * cout + col] = v;
       }
 }
 
@@ -604,7 +700,7 @@ int legs_for(int d, const bbp_opts* o, Legs* out) {
 constexpr int64_t PREDICT_CHUNK = 512;
 
 struct WLayout {
-  size_t X0, A1, A2, F, dF, dA2, dA1, dout, loss, total;
+  size_t X0, A1, A2, F, Wb, dF, dA2, dA1, dout, loss, total;
 };
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 WLayout wlayout(int d, int64_t jobs, int M, bool train) {
@@ -615,6 +711,7 @@ WLayout wlayout(int d, int64_t jobs, int M, bool train) {
   l.A1 = o; o = a256(o + rows * C1 * 4);
   l.A2 = o; o = a256(o + rows * C2 * 4);
   l.F = o; o = a256(o + rows * C3 * 4);
+  l.Wb = o; o = a256(o + (size_t)(9 * C0 * C1 + 9 * C1 * C2 + 9 * C2 * C3) * 2);   // BF16 convolution weights
   if (train) {
     l.dF = o; o = a256(o + rows * C3 * 4);
     l.dA2 = o; o = a256(o + rows * C2 * 4);
@@ -655,12 +752,50 @@ struct Args {
 };
 
 // forward trunk of `jobs` coset jobs starting at syndrome syn / noise rates pdev: features F [rows][C3]
+template <int RELU, bool OUT_BF>
+int conv_bf16(int L, int64_t rows, int cin, int cout, const unsigned short* X, const unsigned short* W,
+              const float* bias, void* Y, hipStream_t st) {
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cout + 63) / 64));
+  conv_fwd_bf16<RELU, OUT_BF><<<grid, dim3(256), 0, st>>>(L, rows, cin, cout, X, W, bias, Y);
+  W_TRY(hipGetLastError());
+  return BBP_OK;
+}
+
+// BF16 copies of the convolution weights into the workspace (done per forward call: 199k values)
+int weights_bf16(const float* prm, const WLayout& w, char* ws, hipStream_t st) {
+  unsigned short* Wb = (unsigned short*)(ws + w.Wb);
+  const int64_t n1 = 9 * C0 * C1, n2 = 9 * C1 * C2, n3 = 9 * C2 * C3;
+  to_bf16_kernel<<<grid1(n1), 256, 0, st>>>(prm + OFF.w1, Wb, n1);
+  to_bf16_kernel<<<grid1(n2), 256, 0, st>>>(prm + OFF.w2, Wb + n1, n2);
+  to_bf16_kernel<<<grid1(n3), 256, 0, st>>>(prm + OFF.w3, Wb + n1 + n2, n3);
+  W_TRY(hipGetLastError());
+  return BBP_OK;
+}
+
+// forward trunk in BF16 storage with FP32 accumulation: input channels, A1 and A2 in BF16, F in FP32
+int trunk_bf16(int d, const uint8_t* syn, const double* pdev, double p, int64_t jobs, char* ws, const WLayout& w,
+               const float* prm, hipStream_t st) {
+  const int L = 2 * d - 1;
+  const int64_t rows = jobs * L * L;
+  unsigned short *X0 = (unsigned short*)(ws + w.X0), *A1 = (unsigned short*)(ws + w.A1),
+                 *A2 = (unsigned short*)(ws + w.A2), *Wb = (unsigned short*)(ws + w.Wb);
+  float* F = (float*)(ws + w.F);
+  features_kernel<unsigned short><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
+  W_TRY(hipGetLastError());
+  int rc;
+  const int64_t n1 = 9 * C0 * C1, n2 = 9 * C1 * C2;
+  if ((rc = conv_bf16<1, true>(L, rows, C0, C1, X0, Wb, prm + OFF.b1, A1, st))) return rc;
+  if ((rc = conv_bf16<1, true>(L, rows, C1, C2, A1, Wb + n1, prm + OFF.b2, A2, st))) return rc;
+  if ((rc = conv_bf16<0, false>(L, rows, C2, C3, A2, Wb + n1 + n2, prm + OFF.b3, F, st))) return rc;
+  return BBP_OK;
+}
+
 int trunk(int d, const uint8_t* syn, const double* pdev, double p, int64_t jobs, const float* prm, char* ws,
           const WLayout& w, hipStream_t st) {
   const int L = 2 * d - 1;
   const int64_t rows = jobs * L * L;
   float *X0 = (float*)(ws + w.X0), *A1 = (float*)(ws + w.A1), *A2 = (float*)(ws + w.A2), *F = (float*)(ws + w.F);
-  features_kernel<<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
+  features_kernel<float><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
   W_TRY(hipGetLastError());
   int rc;
   if ((rc = conv<G_FWD, 1>(L, rows, C0, C1, X0, prm + OFF.w1, A1, prm + OFF.b1, st))) return rc;
@@ -705,22 +840,26 @@ int bbp_warm_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, int3
 }
 
 int bbp_warm_predict(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                     const bbp_opts* opts, const float* params_dev, float* messages_dev, void* workspace,
-                     size_t workspace_bytes, void* stream) {
+                     const bbp_opts* opts, const float* params_dev, int32_t precision, float* messages_dev,
+                     void* workspace, size_t workspace_bytes, void* stream) {
   Args a{d, opts, syndromes_dev, p_dev, p, batch, params_dev, workspace, workspace_bytes, (hipStream_t)stream};
   Legs lg;
   int rc = check_common(a, &lg);
   if (rc) return rc;
   if (!messages_dev) return wfail(BBP_EINVAL, "messages_dev is NULL");
+  if (precision != 0 && precision != 1) return wfail(BBP_EINVAL, "precision must be 0 (FP32) or 1 (BF16)");
   const int64_t chunk = std::min(batch, PREDICT_CHUNK);
   const WLayout w = wlayout(d, 4 * chunk, lg.M, false);
   if (workspace_bytes < w.total) return wfail(BBP_EINVAL, "workspace too small");
   const int L = 2 * d - 1, m = 2 * d * (d - 1);
+  if (precision == 1 && (rc = weights_bf16(params_dev, w, (char*)workspace, a.st))) return rc;
   for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, batch - b0), jobs = 4 * nb;
-    if ((rc = trunk(d, syndromes_dev + b0 * m, p_dev ? p_dev + b0 : nullptr, p, jobs, params_dev, (char*)workspace, w,
-                    a.st)))
-      return rc;
+    const uint8_t* sb = syndromes_dev + b0 * m;
+    const double* pb = p_dev ? p_dev + b0 : nullptr;
+    rc = (precision == 1) ? trunk_bf16(d, sb, pb, p, jobs, (char*)workspace, w, params_dev, a.st)
+                          : trunk(d, sb, pb, p, jobs, params_dev, (char*)workspace, w, a.st);
+    if (rc) return rc;
     if (lg.M > 0) {
       head_kernel<false><<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
           (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, nullptr, nullptr, 0.0f,
@@ -838,7 +977,8 @@ int bbp_warm_decode_workspace_size(int32_t d, int64_t batch, const bbp_opts* opt
 }
 
 int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                    const bbp_opts* opts, const float* params_dev, void* workspace, size_t workspace_bytes,
+                    const bbp_opts* opts, const float* params_dev, int32_t precision, void* workspace,
+                    size_t workspace_bytes,
                     double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
                     uint8_t* correction_dev, int64_t* fallback_count, void* stream) {
   if (!opts || !params_dev || !syndromes_dev || !workspace || !loglik_dev || !delta_dev || !iters_dev ||
@@ -853,7 +993,7 @@ int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syn
   char* ws = (char*)workspace;
   const int m = 2 * d * (d - 1), nq = d * d + (d - 1) * (d - 1);
   float* msgs = (float*)(ws + l.msgs);
-  if ((rc = bbp_warm_predict(d, p, p_dev, syndromes_dev, batch, opts, params_dev, msgs, ws + l.pred,
+  if ((rc = bbp_warm_predict(d, p, p_dev, syndromes_dev, batch, opts, params_dev, precision, msgs, ws + l.pred,
                              l.msgs - l.pred, stream)))
     return rc;
   bbp_group g;

@@ -81,8 +81,9 @@ def workspace_size(d: int, batch: int, opts: bbp_opts, train: bool) -> int:
     return n.value
 
 
-def predict(d: int, p, syndromes, opts: bbp_opts, params, *, workspace=None, stream=None):
-    """Start messages [batch, 4, M, 64] (float32, unit norm) for syndromes [batch, m] (uint8 CUDA)."""
+def predict(d: int, p, syndromes, opts: bbp_opts, params, *, precision: int = 1, workspace=None, stream=None):
+    """Start messages [batch, 4, M, 64] (float32, unit norm) for syndromes [batch, m] (uint8 CUDA).
+    precision 1: BF16 weights and activations, FP32 accumulation (inference); 0: FP32 throughout."""
     import torch
     syndromes = syndromes.contiguous()
     b, dev = syndromes.shape[0], syndromes.device
@@ -94,7 +95,7 @@ def predict(d: int, p, syndromes, opts: bbp_opts, params, *, workspace=None, str
     pv, pt = _p_args(p, b)
     _lib.check_warm(_lib.lib().bbp_warm_predict(
         d, pv, pt.data_ptr() if pt is not None else None, syndromes.data_ptr(), b, C.byref(opts),
-        params.data_ptr(), out.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream, dev)))
+        params.data_ptr(), precision, out.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream, dev)))
     return out
 
 
@@ -135,7 +136,8 @@ def adam(params, grad, m, v, step: int, lr: float, *, stream=None) -> None:
                                              lr, _stream(stream, params.device)))
 
 
-def decode(d: int, p, syndromes, opts: bbp_opts, params, *, workspace=None, stream=None, out=None):
+def decode(d: int, p, syndromes, opts: bbp_opts, params, *, precision: int = 1, workspace=None, stream=None,
+           out=None):
     """Warm-started decode with cold fallback (bbp_warm_decode). Returns the output dict of decode_device
     plus 'fallback' (number of syndromes decoded again from the uniform start)."""
     import torch
@@ -152,7 +154,8 @@ def decode(d: int, p, syndromes, opts: bbp_opts, params, *, workspace=None, stre
     fb = C.c_int64()
     _lib.check_warm(_lib.lib().bbp_warm_decode(
         d, pv, pt.data_ptr() if pt is not None else None, syndromes.data_ptr(), b, C.byref(opts),
-        params.data_ptr(), workspace.data_ptr(), workspace.numel(), out["loglik"].data_ptr(), out["delta"].data_ptr(),
+        params.data_ptr(), precision, workspace.data_ptr(), workspace.numel(), out["loglik"].data_ptr(),
+        out["delta"].data_ptr(),
         out["iters"].data_ptr(), out["coset"].data_ptr(), out["correction"].data_ptr(), C.byref(fb),
         _stream(stream, dev)))
     res = dict(out)

@@ -74,7 +74,7 @@ def test_forward_messages_against_oracle(dev, d, k):
     opts = bbp.default_opts(block=k, chi=32)
     _say(f"[warm fwd] d={d} k={k} batch {b}")
     got = warm.predict(d, torch.from_numpy(ps).to(dev), torch.from_numpy(syn).to(dev), opts,
-                       torch.from_numpy(th).to(dev)).cpu().numpy()
+                       torch.from_numpy(th).to(dev), precision=0).cpu().numpy()
     torch.cuda.synchronize()
     plan = blockbp.Plan(d, k, k)
     for j, X0 in enumerate(_oracle_jobs(d, syn, ps)):
@@ -82,6 +82,48 @@ def test_forward_messages_against_oracle(dev, d, k):
         np.testing.assert_allclose(got[j // 4, j % 4, :plan.M], ref, atol=2e-4, err_msg=f"job {j}")
     # messages are far from uniform (the comparison is not trivial)
     assert np.abs(got[..., :8] - got[..., :1]).max() > 0.05
+
+
+@pytest.mark.parametrize("d,k", [(5, 3), (9, 6)])
+def test_bf16_forward_against_oracle(dev, d, k):
+    """Inference precision: BF16 convolution weights, input channels and hidden activations, FP32 sums. The
+    oracle runs the FP64 network with the same BF16 weights and rounds to BF16 at the same storage points
+    (warmnet.trunk(store=round_bf16)). What remains is FP32 against FP64 summation (<= K 2^-24 of the
+    absolute sums, K <= 1152: about 1e-4 relative), which can also move a stored value across a BF16
+    rounding midpoint -- one BF16 step, 2^-7 relative, at the rare positions where that happens. Both shift
+    the scores s(b) by O(1e-3) nats, against score ranges of several nats here. Compared: log m(b) where the
+    oracle's entry exceeds 1e-4, up to the common normalisation constant; tolerance 0.02 nats."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm
+    b = 2
+    _, syn = workload.make_batch(d, 0.1, b, workload="warm", p_index=250 + d)
+    ps = np.array([0.07, 0.13])
+    th = _theta(d + 1)
+    parts = warmnet.unpack(th.astype(np.float64))
+    for n in ("conv1.W", "conv2.W", "conv3.W"):
+        parts[n] = warmnet.round_bf16(parts[n])
+    th_b = warmnet.pack(parts)
+    opts = bbp.default_opts(block=k, chi=32)
+    _say(f"[warm bf16 fwd] d={d} k={k}")
+    got = warm.predict(d, torch.from_numpy(ps).to(dev), torch.from_numpy(syn).to(dev), opts,
+                       torch.from_numpy(th).to(dev), precision=1).cpu().numpy()
+    torch.cuda.synchronize()
+    plan = blockbp.Plan(d, k, k)
+    worst, span = 0.0, 0.0
+    for j, X0 in enumerate(_oracle_jobs(d, syn, ps)):
+        ref = warmnet.predict(th_b, X0, d, plan, store=warmnet.round_bf16)
+        g = got[j // 4, j % 4, :plan.M]
+        for e in range(plan.M):
+            K = len(warmnet.legs(d, plan, e))
+            r, q = ref[e, :2 ** K], g[e, :2 ** K]
+            sel = r > 1e-4
+            diff = np.log(np.maximum(q[sel], 1e-30)) - np.log(r[sel])
+            worst = max(worst, float(diff.max() - diff.min()))
+            span = max(span, float(np.log(r[sel]).max() - np.log(r[sel]).min()))
+            assert diff.max() - diff.min() <= 0.02, (j, e, diff)
+    _say(f"   largest log-message spread: {worst:.2e} nats (score differences up to {span:.1f} nats)")
+    assert span > 1.0      # the comparison is not trivial
 
 
 @pytest.mark.parametrize("d,k", [(5, 3), (7, 4)])

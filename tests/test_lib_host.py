@@ -175,7 +175,7 @@ def test_warm_start_host_side(bbp):
     n = C.c_size_t()
     assert h.bbp_warm_workspace_size(9, 4, C.byref(bbp.default_opts(block=7, chi=32)), 0, C.byref(n)) \
         == _lib.BBP_EINVAL
-    assert h.bbp_warm_predict(9, 0.1, None, None, 4, C.byref(opts), None, None, None, 0, None) == _lib.BBP_EINVAL
+    assert h.bbp_warm_predict(9, 0.1, None, None, 4, C.byref(opts), None, 1, None, None, 0, None) == _lib.BBP_EINVAL
     assert h.bbp_warm_adam(None, None, None, None, 1, C.c_float(1e-3), None) == _lib.BBP_EINVAL
     assert "NULL" in h.bbp_warm_last_error().decode() or "pointer" in h.bbp_warm_last_error().decode()
     # the committed weights have the network's shape

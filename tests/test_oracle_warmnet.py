@@ -166,3 +166,27 @@ def test_gradient_matches_finite_differences(d, k):
         fd = (warmnet.loss_and_grad(tp, X0, d, plan, T, ids, TINY)[0] -
               warmnet.loss_and_grad(tm, X0, d, plan, T, ids, TINY)[0]) / (2 * h)
         assert abs(fd - g[j]) <= 1e-6 + 1e-5 * abs(fd), (j, fd, g[j])
+
+
+def test_bf16_rounding():
+    """round_bf16 keeps 8 significant bits with ties to even, and is the identity on BF16 values."""
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 0.0, 3.0e-30, 65536.0 * 1.00390625])
+    r = warmnet.round_bf16(x)
+    np.testing.assert_array_equal(r, [1.0, 1.0, 1.0 + 2 ** -7, 1.0 + 2 ** -6, -2.5, 0.0, r[6], 65536.0])
+    assert abs(r[6] - 3.0e-30) <= 2 ** -8 * 3.0e-30
+    np.testing.assert_array_equal(warmnet.round_bf16(r), r)
+    rng = np.random.default_rng(9)
+    y = rng.normal(size=1000) * 10.0
+    # 8 significant bits: relative error <= 2^-8; float64 values pass through float32 first (the values the
+    # GPU rounds are float32), which adds 2^-24
+    assert np.all(np.abs(warmnet.round_bf16(y) - y) <= (2 ** -8 + 2 ** -24) * np.abs(y))
+
+
+def test_trunk_store_identity_is_exact():
+    rng = np.random.default_rng(10)
+    X0, _, _, _ = _job(5)
+    theta = rng.normal(size=warmnet.count(TINY)) * 0.3
+    prm = warmnet.unpack(theta, TINY)
+    a, _ = warmnet.trunk(prm, X0)
+    b, _ = warmnet.trunk(prm, X0, store=lambda t: t)
+    np.testing.assert_array_equal(a, b)
