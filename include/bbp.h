@@ -180,6 +180,8 @@ int bbp_workspace_size_groups(const bbp_group* groups, int32_t ngroups, const bb
 
 /* Whole decoder (Alg. 1) on the groups, with the semantics of bbp_decode_device per group (results are
  * identical to decoding each group alone). Errors as bbp_decode_device. */
+/* The launch variant of a call is the one tuned (bbp_autotune / bbp_set_tuning) for the group with the most
+ * work (syndromes x flops per iteration), else the default. */
 int bbp_decode_groups(const bbp_group* groups, int32_t ngroups, const bbp_opts* opts, void* workspace,
                       size_t workspace_bytes, void* stream, bbp_timing* timing);
 

@@ -695,8 +695,18 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
   if (force) {
     tn = *force;
   } else {
+    // the launch variant tuned for the group that carries the most work (jobs x flops per iteration)
+    const GroupRun* big = &gr[0];
+    double most = -1.0;
+    for (auto& g : gr) {
+      const double w = (double)g.jobs * g.dp->plan.flops_iter;
+      if (w > most) {
+        most = w;
+        big = &g;
+      }
+    }
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_tune.find(std::make_tuple(gr[0].in.d, opts->block_rows, opts->block_cols, gr[0].opts.chi, dev));
+    auto it = g_tune.find(std::make_tuple(big->in.d, opts->block_rows, opts->block_cols, big->opts.chi, dev));
     if (it != g_tune.end()) tn = it->second;
   }
   Aux* aux = nullptr;

@@ -103,6 +103,30 @@ def test_graph_replays_match_eager(dev):
         torch.cuda.synchronize()
 
 
+def test_graph_capture_of_multi_stream_rounds(dev):
+    """A decode whose rounds spread over 4 streams (fork / join events) captures into one graph; its replays
+    equal the eager decode bitwise."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    d, p = 9, 0.10
+    _, syn = workload.make_batch(d, p, 16, workload="mixed", p_index=95)
+    eager_opts = bbp.default_opts(block=6, chi=32, max_iter=10)
+    bbp.set_tuning(d, eager_opts, 1, 4)
+    ref = _alone(dev, d, p, syn, eager_opts)
+    graph_opts = bbp.default_opts(block=6, chi=32, max_iter=10, graph=1)
+    st = torch.cuda.Stream(dev)
+    syn_dev = torch.from_numpy(syn).to(dev)
+    ws = torch.empty(bbp.workspace_size(d, 16, graph_opts), dtype=torch.uint8, device=dev)
+    out = None
+    for rep in range(3):
+        _say(f"[graph 4 streams] {'capture' if rep == 0 else 'replay'} {rep}")
+        with torch.cuda.stream(st):
+            out = bbp.decode_device(d, p, syn_dev, graph_opts, workspace=ws, stream=st, out=out)
+        st.synchronize()
+        _same(_np(out), ref, f"replay {rep}")
+    bbp.set_tuning(d, eager_opts, 0, 1)
+
+
 def test_launch_variants_give_identical_results(dev):
     import torch
     import paper_2402_04834_amd as bbp
