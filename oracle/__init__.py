@@ -15,6 +15,8 @@ Modules
   blockbp  -- block partition, MPS-message belief propagation with the two-colour schedule, damping and
               convergence distance, the Bethe estimate of Lemma 3.1, and the decision rule (Sec. III.C-E,
               Alg. 1 and its remarks)
+  bmps     -- boundary-MPS contraction of a whole coset network with bond dimension chi: the single-block
+              limit of blockBP and the paper's chi = 16 accuracy reference (Sec. III.A, III.D, IV)
 
 Every floating-point quantity is float64. Shapes carry an arbitrary leading batch ("...") so that many
 syndromes and cosets are processed by one NumPy call; no blocking, fusion or reordering beyond what the
