@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "syndromes decoded/s at d=17, chi=32 (1 GPU); agreement vs FP64 oracle"
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk (packed dual FMA)
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
 GOLDEN = os.path.join(ROOT, "tests", "golden", "d17_p010_k6_chi32.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "sweep_kernel_d17_b4096_traffic.txt")
 
@@ -178,10 +179,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, choices=(0, 1), default=0,
                     help="0: FP32 products (default); 1: products of BF16-rounded inputs, FP32 sums")
-    ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased"), default="d17",
+    ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased", "bmps"), default="d17",
                     help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance; warm: "
                          "learned warm start against the uniform start at d=25, p=0.10; biased: d=17 under "
-                         "Z-biased Pauli noise (p=0.10, bias 10)")
+                         "Z-biased Pauli noise (p=0.10, bias 10); bmps: the single-block limit (boundary-MPS "
+                         "decoder, chi 16) on the d17 syndromes")
     ap.add_argument("--block", type=int, default=6, choices=range(1, 7),
                     help="block size k of the d17 workload (default 6; 1 = plain BP between single tensors)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -214,6 +216,8 @@ def main():
         return warm_main(a)
     if a.workload == "biased":
         return biased_main(a)
+    if a.workload == "bmps":
+        return bmps_main(a)
     if a.calibrate_copy > 0:
         n = a.calibrate_copy << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -413,6 +417,93 @@ def biased_main(a):
         logical_failure_rate=float(logical_failures(d, errors, o["correction"].cpu().numpy()).mean()),
     )
     print(json.dumps(line), flush=True)
+
+
+def bmps_flops(d):
+    """Algorithmic FP64 flops of one coset contraction by bmps_kernel at the padded sizes it works on (bonds
+    2 chi_max = 32, so at d=17 every interior bond is full): per grid row of every column but the last, the
+    carry product R B (2 * 64 * 32 * 32), Householder QR of the 64 x 32 result and its explicit Q
+    (2 (2 m n^2 - 2 n^3 / 3) with m = 64, n = 32), the carry product Q C (2 * 64 * 32 * 16), the SVD of the
+    32 x 32 matrix N with its right singular vectors (the Golub-Van Loan count 21 n^3) and C = N V^T
+    (2 * 32 * 32 * 16)."""
+    L = 2 * d - 1
+    m, n = 64, 32
+    qr = 2 * m * n * n - 2 * n ** 3 / 3
+    per_row = 2 * 64 * 32 * 32 + 2 * qr + 2 * 64 * 32 * 16 + 21 * n ** 3 + 2 * 32 * 32 * 16
+    return (L - 1) * L * per_row
+
+
+def bmps_main(a):
+    """The single-block limit of blockBP -- the boundary-MPS decoder, chi 16 -- on the 4096 syndromes of the
+    d=17, p=0.10 workload. One decode per step; the contraction kernel is timed with HIP events on its
+    stream. Reports decision agreement with the blockBP decoder (6x6 blocks, chi 32) on the same syndromes
+    and both logical failure rates."""
+    import numpy as np
+    import torch
+
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import workload
+
+    d, p, chi, count = 17, 0.10, 16, a.batch
+    errors, syn = workload.make_batch(d, p, count, workload="d17")
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(syn).to(dev)
+    out = bbp.bmps_decode(d, p, s, chi)
+    ws = out["workspace"]
+    for _ in range(a.warmup):
+        out = bbp.bmps_decode(d, p, s, chi, workspace=ws)
+    torch.cuda.synchronize()
+    kms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = bbp.bmps_decode(d, p, s, chi, workspace=ws, timing=True)
+        kms += out["kernel_ms"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    avg_ms = kms / a.steps
+    flops = bmps_flops(d) * 4 * count
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    opts = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
+    ref = bbp.decode_device(d, p, s, opts)
+    torch.cuda.synchronize()
+    cb = out["coset"].cpu().numpy()
+    cr = ref["coset"].cpu().numpy()
+    fb = logical_failures(d, errors, out["correction"].cpu().numpy())
+    fr = logical_failures(d, errors, ref["correction"].cpu().numpy())
+    line = dict(
+        metric="syndromes decoded/s at d=17 by the single-block limit (bMPS, chi 16; 1 GPU)",
+        value=count * a.steps / elapsed, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"{count} syndromes, d=17, p=0.10 (the d17 syndromes), one block = the whole "
+                             "network, boundary MPS chi 16, FP64", batch=count, parallelism="single GPU"),
+        roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / PEAK_FP64_TFLOPS, traffic=None, kernel="bmps_kernel<double>",
+                      avg_launch_ms=avg_ms, flops_per_launch=flops),
+        decisions_equal_to_blockbp=float((cb == cr).mean()),
+        logical_failures=dict(bmps=[int(fb.sum()), count, list(wilson(int(fb.sum()), count))],
+                              blockbp=[int(fr.sum()), count, list(wilson(int(fr.sum()), count))]),
+    )
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = bmps_cpu_baseline(d, p, chi)
+    print(json.dumps(line), flush=True)
+
+
+def bmps_cpu_baseline(d, p, chi, count=8):
+    """The FP64 bMPS oracle on the first `count` syndromes of the same workload, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import bmps, network
+    from paper_2402_04834_amd import workload
+
+    _, syn = workload.make_batch(d, p, count, workload="d17")
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        bmps.bmps_coset_loglik(d, syn, network.depolarizing(p), chi)
+        dt = time.perf_counter() - t0
+    return dict(value=count / dt, unit="syndromes/s", cores=1, kind="oracle",
+                sample=f"syndromes 0..{count - 1} of the d={d} p={p} workload, all 4 cosets, chi={chi}, "
+                       f"float64, one thread ({dt:.1f} s)")
 
 
 def logical_class(d, errors, corrections):

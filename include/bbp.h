@@ -209,6 +209,39 @@ int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts
                        double* delta, int32_t* iters, uint8_t* coset, uint8_t* correction);
 
 /* ---------------------------------------------------------------------------------------------------
+ * Boundary-MPS decoder: the single-block limit of blockBP (Sec. III.D), i.e. the bMPS decoder of Sec.
+ * III.A that Sec. IV runs with chi = 16 as its accuracy reference. Each coset network is contracted column
+ * by column, left to right, as an MPS over the L rows; after every column but the last the MPS is
+ * compressed to bond dimension chi (a QR sweep from the top row down, then a truncated-SVD sweep from the
+ * bottom row up keeping the chi largest singular values of every bond, the norm split off into an FP64
+ * log-scale); the last column's chain of matrices is multiplied out. One wavefront per coset network;
+ * matrix work in FP64 (an estimate is resolved down to about the unit roundoff times the state's norm, which
+ * the likeliest configurations set, so FP32 would leave cosets some tens of nats below the best unresolved).
+ *
+ * Workspace: bbp_bmps_workspace_size bytes (coset labels plus 16*2*16 + 64*32 doubles per grid row and coset
+ * network: 20 KiB * L * 4 * batch). Errors: BBP_EINVAL (d outside [2, 32], chi outside [1, 16], batch < 0
+ * or above 2^22).
+ */
+int bbp_bmps_workspace_size(int32_t d, int64_t batch, int32_t chi, size_t* bytes);
+
+/* Decode `batch` syndromes resident in device memory (uint8 [batch][2d(d-1)]), enqueued on `stream` (a
+ * hipStream_t; NULL = the default stream).
+ *   noise: p in (0, 1) (depolarizing) unless p_dev ([batch] device doubles, each syndrome's own p) or
+ *          noise (host double[4]: Pauli probabilities of I, X, Z, Y by code x + 2z, summing to 1, noise[0]
+ *          > 0; exclusive with p_dev) is given;
+ *   loglik_dev [batch][4]: the estimates of ln pi(f_s L G), L in (I, X, Y, Z), NaN where the contraction
+ *          ended with a value that is not positive;
+ *   coset_dev [batch]: the largest estimate (NaN as -inf, ties to the lowest index);
+ *   correction_dev [batch][n] (may be NULL): f_s L* as Pauli codes x + 2z;
+ *   kernel_ms (host, may be NULL): duration of the contraction kernel, measured with HIP events on the
+ *          stream (the call then synchronises with the stream).
+ * batch 0 is a no-op. Errors: BBP_EINVAL (arguments, workspace too small), BBP_EHIP. */
+int bbp_bmps_decode_device(int32_t d, double p, const double* p_dev, const double* noise,
+                           const uint8_t* syndromes_dev, int64_t batch, int32_t chi, void* workspace,
+                           size_t workspace_bytes, double* loglik_dev, uint8_t* coset_dev, uint8_t* correction_dev,
+                           void* stream, float* kernel_ms);
+
+/* ---------------------------------------------------------------------------------------------------
  * Learned warm start. BP of blockBP starts from uniform messages (remark 2); the paper names machine
  * learning as a way to improve BP (Sec. V, summary and conclusions). Here a convolutional network
  * predicts the start messages of every coset job from the local syndrome, and the decoder runs from them.

@@ -111,6 +111,53 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     return out
 
 
+def bmps_workspace_size(d: int, batch: int, chi: int = 16) -> int:
+    n = C.c_size_t(0)
+    _lib.check(_lib.lib().bbp_bmps_workspace_size(d, batch, chi, C.byref(n)))
+    return n.value
+
+
+def bmps_decode(d: int, p, syndromes, chi: int = 16, *, workspace=None, correction: bool = True,
+                timing: bool = False, stream=None):
+    """Boundary-MPS decoder (the single-block limit of blockBP) on a torch uint8 CUDA tensor [batch, m] of
+    syndromes: p is a float (depolarizing rate), a float64 CUDA tensor [batch] of per-syndrome rates or a
+    4-sequence of Pauli probabilities (I, X, Z, Y). Returns a dict of torch tensors (loglik [batch, 4],
+    coset [batch], correction [batch, n] unless correction=False), the workspace, and with timing=True the
+    contraction kernel's duration in ms ('kernel_ms', measured with HIP events on the stream)."""
+    import torch
+
+    assert syndromes.is_cuda and syndromes.dtype == torch.uint8 and syndromes.dim() == 2
+    syndromes = syndromes.contiguous()
+    batch = syndromes.shape[0]
+    dev = syndromes.device
+    n = d * d + (d - 1) * (d - 1)
+    ws_bytes = bmps_workspace_size(d, batch, chi)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    pval, p_ptr, noise, keep = 0.0, None, None, None
+    if isinstance(p, torch.Tensor):
+        keep = p.to(device=dev, dtype=torch.float64).contiguous()
+        p_ptr = keep.data_ptr()
+    elif isinstance(p, (tuple, list)):
+        noise = (C.c_double * 4)(*[float(v) for v in p])
+    else:
+        pval = float(p)
+    out = dict(loglik=torch.empty((batch, 4), dtype=torch.float64, device=dev),
+               coset=torch.empty(batch, dtype=torch.uint8, device=dev))
+    if correction:
+        out["correction"] = torch.empty((batch, n), dtype=torch.uint8, device=dev)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    ms = C.c_float(0.0)
+    _lib.check(_lib.lib().bbp_bmps_decode_device(
+        d, pval, p_ptr, noise, syndromes.data_ptr(), batch, chi, workspace.data_ptr(), workspace.numel(),
+        out["loglik"].data_ptr(), out["coset"].data_ptr(),
+        out["correction"].data_ptr() if correction else None, st, C.byref(ms) if timing else None))
+    if timing:
+        out["kernel_ms"] = ms.value
+    out["workspace"] = workspace
+    return out
+
+
 def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = False, stream=None, outs=None,
                   messages: bool = False):
     """Decode a mixed batch: `groups` is a list of (d, p, syndromes[, chi[, init]]) with syndromes a torch

@@ -89,6 +89,10 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "bbp_reference_update_host": (C.c_int, [C.c_int32, C.c_double, C.POINTER(bbp_opts), C.c_void_p, C.c_int32,
                                             C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "bbp_bmps_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "bbp_bmps_decode_device": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.POINTER(C.c_float)]),
     "bbp_warm_last_error": (C.c_char_p, []),
     "bbp_warm_param_count": (C.c_int, [C.POINTER(C.c_int64)]),
     "bbp_warm_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(bbp_opts), C.c_int32,

@@ -28,6 +28,7 @@
 #include "../../include/bbp.h"
 #include "geom.hpp"
 #include "plan.hpp"
+#include "bmps_launch.hpp"
 #include "sweep_launch.hpp"
 
 using bbp::SweepDesc;
@@ -234,6 +235,11 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
 }
 
 }  // namespace
+
+hipError_t bbp::launch_labels(hipStream_t st, const uint8_t* syn, int d, int64_t batch, uint8_t* labels) {
+  if (batch > 0) labels_kernel<<<dim3((unsigned)batch), dim3(256), 0, st>>>(syn, d, batch, labels);
+  return hipGetLastError();
+}
 
 hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
   if (a.small) return launch_small_sweeps(st, a);
@@ -910,6 +916,89 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
   g.correction_dev = correction_dev;
   g.messages_dev = messages_dev;
   return decode_groups(&g, 1, opts, workspace, workspace_bytes, stream, timing, nullptr);
+}
+
+// ---- boundary-MPS decoder (single block) ----
+static int bmps_check(int32_t d, int64_t batch, int32_t chi) {
+  if (d < 2 || d > 32) return fail(BBP_EINVAL, "d must be in [2, 32]");
+  if (chi < 1 || chi > bbp::BMPS_CHI_MAX) return fail(BBP_EINVAL, "chi must be in [1, 16]");
+  if (batch < 0) return fail(BBP_EINVAL, "batch must be >= 0");
+  if (batch > (int64_t)1 << 22) return fail(BBP_EINVAL, "batch too large");
+  return BBP_OK;
+}
+
+static size_t bmps_label_bytes(int32_t d, int64_t batch) {
+  const int64_t L = 2 * d - 1;
+  return align256((size_t)(batch * 4 * L * L));
+}
+
+int bbp_bmps_workspace_size(int32_t d, int64_t batch, int32_t chi, size_t* bytes) {
+  int rc = bmps_check(d, batch, chi);
+  if (rc) return rc;
+  if (!bytes) return fail(BBP_EINVAL, "bytes is NULL");
+  *bytes = bmps_label_bytes(d, batch) + align256(bbp::bmps_state_bytes(d, 4 * batch));
+  return BBP_OK;
+}
+
+int bbp_bmps_decode_device(int32_t d, double p, const double* p_dev, const double* noise,
+                           const uint8_t* syndromes_dev, int64_t batch, int32_t chi, void* workspace,
+                           size_t workspace_bytes, double* loglik_dev, uint8_t* coset_dev, uint8_t* correction_dev,
+                           void* stream, float* kernel_ms) {
+  int rc = bmps_check(d, batch, chi);
+  if (rc) return rc;
+  bbp::BmpsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  if (noise) {
+    double sum = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      if (!(noise[k] >= 0.0 && noise[k] <= 1.0)) return fail(BBP_EINVAL, "noise entries must be in [0, 1]");
+      sum += noise[k];
+      a.pi[k] = noise[k];
+    }
+    if (!(noise[0] > 0.0) || std::fabs(sum - 1.0) > 1e-6)
+      return fail(BBP_EINVAL, "noise must be probabilities summing to 1 with a positive identity entry");
+    if (p_dev) return fail(BBP_EINVAL, "noise and p_dev are exclusive");
+    a.biased = 1;
+  } else if (!p_dev && !(p > 0.0 && p < 1.0)) {
+    return fail(BBP_EINVAL, "p must be in (0, 1)");
+  }
+  if (kernel_ms) *kernel_ms = 0.0f;
+  if (batch == 0) return BBP_OK;
+  if (!syndromes_dev || !workspace || !loglik_dev || !coset_dev) return fail(BBP_EINVAL, "NULL device pointer");
+  size_t need = 0;
+  bbp_bmps_workspace_size(d, batch, chi, &need);
+  if (workspace_bytes < need) return fail(BBP_EINVAL, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* base = (uint8_t*)workspace;
+  const size_t lb = bmps_label_bytes(d, batch);
+  const int64_t L = 2 * d - 1, jobs = 4 * batch;
+  a.labels = base;
+  a.A = (double*)(base + lb);
+  a.Q = a.A + jobs * L * (16 * 2 * 16);
+  a.loglik = loglik_dev;
+  a.pdev = p_dev;
+  a.d = d;
+  a.chi = chi;
+  a.jobs = jobs;
+  a.p00 = 1.0 - p;
+  a.pe = p / 3.0;
+  HIP_TRY(bbp::launch_labels(st, syndromes_dev, d, batch, base));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  HIP_TRY(bbp::launch_bmps_contract(st, a));
+  if (kernel_ms) HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(bbp::launch_bmps_decide(st, a, coset_dev, correction_dev));
+  if (kernel_ms) {
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(kernel_ms, e0, e1));
+    HIP_TRY(hipEventDestroy(e0));
+    HIP_TRY(hipEventDestroy(e1));
+  }
+  return BBP_OK;
 }
 
 int bbp_set_tuning(int32_t d, const bbp_opts* opts, const bbp_tuning* t) {
