@@ -92,9 +92,12 @@ __device__ __forceinline__ T wave_max(T v) {
   return __shfl(v, 0);
 }
 
-// LDS: pass 1 and pass 2 never overlap in time, so their buffers share one pool
-constexpr int POOL_P1 = 32 * 32 + 32 * 64 + 32 + SITE_A;             // R, Householder vectors and betas, row
-constexpr int POOL_P2 = 2 * 32 * 32 + 32 * 32 + 16 * 32 + 32 * 16 + 32; // exchange, N, V, C, singular values
+// LDS: pass 1 and pass 2 never overlap in time, so their buffers share one pool (16.6 KB in FP64, so that two
+// wavefronts fit per SIMD); the Householder vectors of pass 1 live in the row's workspace slot until Q
+// replaces them
+constexpr int POOL_P1 = 32 * 32 + 32 + SITE_A;              // R, Householder betas, row
+constexpr int XSTRIDE = 17;                                 // exchange row stride: 16 entries + 1 (LDS banks)
+constexpr int POOL_P2 = 64 * XSTRIDE + 16 * 32 + 32 * 16 + 32;   // exchange, V, C, singular values
 constexpr int POOL = POOL_P1 > POOL_P2 ? POOL_P1 : POOL_P2;
 
 template <typename T>
@@ -106,13 +109,11 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
   __shared__ T vch[32];                 // last-column chain vector
   // pass 1
   T* Rsh = pool;                        // carry R [k][li]
-  T* Hv = Rsh + 32 * 32;                // Householder vectors [j][row]
-  T* Hb = Hv + 32 * 64;                 // their coefficients
+  T* Hb = Rsh + 32 * 32;                // Householder coefficients
   T* Ash = Hb + 32;                     // the row being absorbed [a][s][b]
   // pass 2
-  T* Xsh = pool;                        // Jacobi exchange, double-buffered [buf][l][t][k]
-  T* Nsh = Xsh + 2 * 32 * 32;           // N before the rotations [l][t][k]
-  T* Vsh = Nsh + 32 * 32;               // kept right singular vectors [j][t][k]
+  T* Xsh = pool;                        // Jacobi exchange [(l, t)][k], row stride XSTRIDE
+  T* Vsh = Xsh + 64 * XSTRIDE;          // kept right singular vectors [j][t][k]
   T* Csh = Vsh + 16 * 32;               // carry C [k][j]
   T* sig = Csh + 32 * 16;               // singular values by row
 
@@ -171,19 +172,15 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
         const int b = hi >> 1, dn = hi & 1;
         const T t00 = tentry(r, c, L, lb, 0, 0, dn, par, p0, p1, p2, p3), t01 = tentry(r, c, L, lb, 0, 1, dn, par, p0, p1, p2, p3);
         const T t10 = tentry(r, c, L, lb, 1, 0, dn, par, p0, p1, p2, p3), t11 = tentry(r, c, L, lb, 1, 1, dn, par, p0, p1, p2, p3);
-        T bc[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) x[k] = T(0);
+        // B[li][par][col] for li = (aa, u), formed as it is used
 #pragma unroll
         for (int aa = 0; aa < 16; ++aa) {
           const T a0 = Ash[(aa * 2 + 0) * 16 + b], a1 = Ash[(aa * 2 + 1) * 16 + b];
-          bc[aa * 2 + 0] = a0 * t00 + a1 * t01;
-          bc[aa * 2 + 1] = a0 * t10 + a1 * t11;
-        }
+          const T b0 = a0 * t00 + a1 * t01, b1 = a0 * t10 + a1 * t11;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-          T acc = T(0);
-#pragma unroll
-          for (int li = 0; li < 32; ++li) acc += Rsh[k * 32 + li] * bc[li];
-          x[k] = acc;
+          for (int k = 0; k < 32; ++k) x[k] += Rsh[k * 32 + aa * 2] * b0 + Rsh[k * 32 + aa * 2 + 1] * b1;
         }
       }
       __syncthreads();   // every lane has read R
@@ -193,21 +190,28 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
         for (int k = 0; k < 32; ++k) Qr[(2 * k + par) * 32 + hi] = x[k];
         continue;
       }
-      // Householder QR of M_r (64 x 32): reflection j zeroes rows j+1.. of column j
+      // Householder QR of M_r (64 x 32): reflection j zeroes rows j+1.. of column j. Vector j is kept in the
+      // row's workspace slot as Hg[j][par][k] (row 2k + par), each lane's half contiguous.
+      T* Hg = Qr;
       for (int j = 0; j < 32; ++j) {
         if (hi == j) {
 #pragma unroll
-          for (int k = 0; k < 32; ++k) Hv[j * 64 + 2 * k + par] = (2 * k + par >= j) ? x[k] : T(0);
+          for (int k = 0; k < 32; ++k) Hg[(j * 2 + par) * 32 + k] = (2 * k + par >= j) ? x[k] : T(0);
         }
         __syncthreads();
-        T raw[32], pn = T(0), pw = T(0);
+        // one read of the (raw) vector for its norm and its product with this column; the pivot entry
+        // changes from alpha to vj, which the product corrects with this lane's pivot-row entry xp
+        const T* hv = Hg + (j * 2 + par) * 32;
+        T pn = T(0), pw = T(0), xp = T(0);
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
-          raw[k] = Hv[j * 64 + 2 * k + par];
-          pn += raw[k] * raw[k];
+          const T v = hv[k];
+          pn += v * v;
+          pw += v * x[k];
+          xp += (2 * k + par == j) ? x[k] : T(0);
         }
         const T nrm = msqrt(pn + __shfl_xor(pn, 1));
-        const T alpha = Hv[j * 64 + j];
+        const T alpha = Hg[(j * 2 + (j & 1)) * 32 + (j >> 1)];
         T beta = T(0), vj = alpha, diag = alpha;
         if (nrm > T(0)) {
           const T sg = (alpha >= T(0)) ? T(1) : T(-1);
@@ -215,15 +219,11 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
           beta = T(1) / (nrm * (nrm + mabs(alpha)));
           diag = -sg * nrm;
         }
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-          if (2 * k + par == j) raw[k] = vj;
-          pw += raw[k] * x[k];
-        }
+        pw += (vj - alpha) * xp;
         const T w = (pw + __shfl_xor(pw, 1)) * beta;
         if (hi > j) {
 #pragma unroll
-          for (int k = 0; k < 32; ++k) x[k] -= w * raw[k];
+          for (int k = 0; k < 32; ++k) x[k] -= w * ((2 * k + par == j) ? vj : hv[k]);
         } else if (hi == j && nrm > T(0)) {
 #pragma unroll
           for (int k = 0; k < 32; ++k) {
@@ -231,9 +231,9 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
             x[k] = (row == j) ? diag : (row > j ? T(0) : x[k]);
           }
         }
-        __syncthreads();   // every lane has read Hv[j] as it was
+        __syncthreads();   // every lane has read vector j as it was
         if (ln == 0) {
-          Hv[j * 64 + j] = vj;
+          Hg[(j * 2 + (j & 1)) * 32 + (j >> 1)] = vj;
           Hb[j] = beta;
         }
       }
@@ -255,16 +255,15 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
 #pragma unroll
         for (int k = 0; k < 32; ++k) q[k] = (2 * k + par == hi) ? T(1) : T(0);
         for (int j = 31; j >= 0; --j) {
-          T raw[32], pw = T(0);
+          const T* hv = Hg + (j * 2 + par) * 32;
+          T pw = T(0);
 #pragma unroll
-          for (int k = 0; k < 32; ++k) {
-            raw[k] = Hv[j * 64 + 2 * k + par];
-            pw += raw[k] * q[k];
-          }
+          for (int k = 0; k < 32; ++k) pw += hv[k] * q[k];
           const T w = (pw + __shfl_xor(pw, 1)) * Hb[j];
 #pragma unroll
-          for (int k = 0; k < 32; ++k) q[k] -= w * raw[k];
+          for (int k = 0; k < 32; ++k) q[k] -= w * hv[k];
         }
+        __syncthreads();   // every lane has read the vectors before Q replaces them
 #pragma unroll
         for (int k = 0; k < 32; ++k) Qr[(2 * k + par) * 32 + hi] = q[k];
       }
@@ -291,43 +290,49 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
 #pragma unroll
           for (int k = 0; k < 16; ++k) y[k] += qv[m] * Csh[m * 16 + k];
         }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) Nsh[ln * 16 + k] = y[k];
       }
+      T y0[16];   // N before the rotations
+#pragma unroll
+      for (int k = 0; k < 16; ++k) y0[k] = y[k];
       // one-sided Jacobi on the rows of N (columns of N^T), paired by the circle method over 32
       T nf2 = T(0);
 #pragma unroll
       for (int k = 0; k < 16; ++k) nf2 += y[k] * y[k];
       const T thr2 = wave_sum(nf2) * (Tol<T>::rank * Tol<T>::rank);
-      int buf = 0;
       for (int sw = 0; sw < Tol<T>::sweeps; ++sw) {
         int rotated = 0;
         for (int rd = 0; rd < 31; ++rd) {
           const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : (2 * rd - hi + 62) % 31;
-          T* X = Xsh + buf * (32 * 32);
 #pragma unroll
-          for (int k = 0; k < 16; ++k) X[ln * 16 + k] = y[k];
+          for (int k = 0; k < 16; ++k) Xsh[ln * XSTRIDE + k] = y[k];
           __syncthreads();
           T z[16], aa = T(0), bb = T(0), gg = T(0);
 #pragma unroll
           for (int k = 0; k < 16; ++k) {
-            z[k] = X[(2 * pl + par) * 16 + k];
+            z[k] = Xsh[(2 * pl + par) * XSTRIDE + k];
             aa += y[k] * y[k];
             bb += z[k] * z[k];
             gg += y[k] * z[k];
           }
+          __syncthreads();   // every lane has read its partner before the next round's writes
           aa += __shfl_xor(aa, 1);
           bb += __shfl_xor(bb, 1);
           gg += __shfl_xor(gg, 1);
-          buf ^= 1;
           // (alpha, beta) = squared norms of the lower- and higher-numbered row of the pair
           const bool lower = hi < pl;
           const T al = lower ? aa : bb, be = lower ? bb : aa;
           if (al > thr2 && be > thr2 && mabs(gg) > Tol<T>::jac * msqrt(al * be)) {
-            const T zeta = (be - al) / (T(2) * gg), az = mabs(zeta);
-            const T den = az + (az < T(1e18) ? msqrt(zeta * zeta + T(1)) : az);
-            const T tt = (zeta >= T(0) ? T(1) : T(-1)) / den;
-            const T cs = T(1) / msqrt(tt * tt + T(1)), sn = cs * tt;
+            // The angle only has to bring the pair closer to orthogonal, so t = tan(theta) is formed in FP32
+            // (fast reciprocal and square root; above the noise threshold zeta stays within 1e30); cos and
+            // sin are then formed in FP64 from that t, so that the rotation is orthogonal to FP64 rounding.
+            const float zf = (float)(be - al) * __builtin_amdgcn_rcpf(2.0f * (float)gg), azf = fabsf(zf);
+            const float denf = azf + (azf < 1e18f ? __builtin_sqrtf(fmaf(zf, zf, 1.0f)) : azf);
+            const T tt = (T)copysignf(__builtin_amdgcn_rcpf(denf), zf);
+            const T xx = tt * tt + T(1);
+            T cs = __builtin_amdgcn_rsq(xx);
+            cs = cs * (T(1.5) - T(0.5) * xx * cs * cs);
+            cs = cs * (T(1.5) - T(0.5) * xx * cs * cs);
+            const T sn = cs * tt;
             // lower row p: c p - s q; higher row q: s p + c q
 #pragma unroll
             for (int k = 0; k < 16; ++k) y[k] = lower ? (cs * y[k] - sn * z[k]) : (sn * z[k] + cs * y[k]);
@@ -362,19 +367,17 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
       }
       const T fro = msqrt(wave_sum((par == 0 && kept) ? sv * sv : T(0)));
       __syncthreads();
-      // C[l][j] = sum_(t, k) N[l][(t, k)] V[j][(t, k)]: lane ln does l = ln / 2, j = 8 (ln % 2) .. + 7
+      // C[l][j] = sum_(t, k) N[l][(t, k)] V[j][(t, k)]: lane (l, t) sums its half t, the pair adds halves;
+      // lane t = 0 stores j < 8, lane t = 1 stores j >= 8
       {
         const T finv = (fro > T(0)) ? T(1) / fro : T(0);
-        T nrow[32];
 #pragma unroll
-        for (int e = 0; e < 32; ++e) nrow[e] = Nsh[hi * 32 + e];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-          const int j = par * 8 + jj;
+        for (int j = 0; j < 16; ++j) {
           T acc = T(0);
 #pragma unroll
-          for (int e = 0; e < 32; ++e) acc += nrow[e] * Vsh[j * 32 + e];
-          Csh[hi * 16 + j] = acc * finv;
+          for (int k = 0; k < 16; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
+          acc += __shfl_xor(acc, 1);
+          if ((j >> 3) == par) Csh[hi * 16 + j] = acc * finv;
         }
         logs += log((double)fro);
       }
