@@ -92,16 +92,17 @@ __device__ __forceinline__ T wave_max(T v) {
   return __shfl(v, 0);
 }
 
-// LDS: pass 1 and pass 2 never overlap in time, so their buffers share one pool (16.6 KB in FP64, so that two
-// wavefronts fit per SIMD); the Householder vectors of pass 1 live in the row's workspace slot until Q
-// replaces them
+// LDS: pass 1 and pass 2 never overlap in time, so their buffers share one pool (13 KB in FP64, so that three
+// wavefronts fit per SIMD; the register file then holds 168 VGPRs per lane and the rest of the working set
+// spills to scratch, which measures faster than one resident wavefront per SIMD); the Householder vectors of
+// pass 1 live in the row's workspace slot until Q replaces them
 constexpr int POOL_P1 = 32 * 32 + 32 + SITE_A;              // R, Householder betas, row
 constexpr int XSTRIDE = 17;                                 // exchange row stride: 16 entries + 1 (LDS banks)
-constexpr int POOL_P2 = 64 * XSTRIDE + 16 * 32 + 32 * 16 + 32;   // exchange, V, C, singular values
+constexpr int POOL_P2 = 64 * XSTRIDE + 32 * 16 + 32;   // exchange (then V), C, singular values
 constexpr int POOL = POOL_P1 > POOL_P2 ? POOL_P1 : POOL_P2;
 
 template <typename T>
-__global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void bmps_kernel(BmpsArgs a) {
   const int64_t job = blockIdx.x;
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   const int L = 2 * a.d - 1, chi = a.chi;
@@ -113,8 +114,8 @@ __global__ __launch_bounds__(64) void bmps_kernel(BmpsArgs a) {
   T* Ash = Hb + 32;                     // the row being absorbed [a][s][b]
   // pass 2
   T* Xsh = pool;                        // Jacobi exchange [(l, t)][k], row stride XSTRIDE
-  T* Vsh = Xsh + 64 * XSTRIDE;          // kept right singular vectors [j][t][k]
-  T* Csh = Vsh + 16 * 32;               // carry C [k][j]
+  T* Vsh = pool;                        // after the rotations: kept right singular vectors [j][t][k]
+  T* Csh = Xsh + 64 * XSTRIDE;          // carry C [k][j]
   T* sig = Csh + 32 * 16;               // singular values by row
 
   T* Aj = a.A + job * (int64_t)L * SITE_A;
