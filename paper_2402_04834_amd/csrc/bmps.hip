@@ -21,14 +21,16 @@
 // ln Z = log-scale + ln(value), NaN when the value is not positive.
 //
 // Precision: FP64 throughout. The estimate of a coset is resolved only down to about the unit roundoff
-// times the state's norm, and the state's norm is set by the likeliest configurations: a coset tens of nats
-// below the best is an O(1) fraction of that resolution in FP32 (measured: errors of 1e-2 nats and
-// non-positive values within 8 nats of the best), so the kernel keeps every matrix in FP64.
+// times the state's norm, and the state's norm is set by the likeliest configurations of the partial
+// network, not by the coset's own value. An FP32 build of this kernel was off by up to 4 nats on cosets
+// 15-30 nats below the best and returned non-positive values within 8 nats of the best (d=5, chi 16), so
+// every matrix is FP64; only rotation angles (below) are formed in FP32.
 //
 // Layout: every lane owns matrix columns in registers. Pass 1: lane (col, par) holds the 32 entries of
-// column col of M_r in the rows of parity par; a Householder vector is broadcast through LDS. Pass 2: lane
-// (l, t) holds the 16 entries (t, k) of row l of N_r; a Jacobi round pairs rows by the circle method and
-// exchanges them through LDS. Bond dimensions are padded to 2 chi_max = 32 with zeros.
+// column col of M_r in the rows of parity par; a Householder vector is broadcast through the row's workspace
+// slot (L1-resident). Pass 2: lane (l, t) holds the 16 entries (t, k) of row l of N_r; a Jacobi round pairs
+// rows by the circle method and exchanges them through LDS. Bond dimensions are padded to 2 chi_max = 32
+// with zeros.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
