@@ -160,9 +160,17 @@ def _take(sites, idx):
     return [s[idx] for s in sites]
 
 
-def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: float, fixed_iters: bool):
+def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: float, fixed_iters: bool,
+           gate: float = 0.0):
     """BP loop of Alg. 1 for a batch of coset networks (tensors[r][c] of shape [B, ...]).
-    Returns (messages dict, Delta [B], iterations [B])."""
+    Returns (messages dict, Delta [B], iterations [B]).
+
+    gate > 0 selects the residual-gated schedule, a scheduling variant (Sec. IV names smarter BP scheduling
+    as a way to improve the hardest regimes and leaves it open; the rule itself is this implementation's
+    reading): in a colour round
+    the update of message u->v is skipped for a coset when every message entering block u other than v->u
+    changed, in its most recent update, by a distance term 2 - 2<m, m_old>^2 below gate; a skipped message
+    keeps its value and its term becomes 0. Messages that were never updated count as changed."""
     B = tensors[0][0].shape[0]
     msgs = {}
     for (src, dst, _) in plan.edges:
@@ -170,6 +178,9 @@ def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: flo
         msgs[(src, dst)] = mps.uniform([2] * K, chi, (B,))
     delta = np.full(B, np.inf)
     iters = np.zeros(B, dtype=np.int64)
+    terms = {(src, dst): np.full(B, np.inf) for (src, dst, _) in plan.edges}
+    inputs = {(src, dst): [(w, s2) for (w, s2, _) in plan.edges if s2 == src and w != dst]
+              for (src, dst, _) in plan.edges}
     active = np.arange(B)
     L = len(tensors)
     for _ in range(max_iter):
@@ -189,8 +200,20 @@ def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: flo
                 if eta > 0.0:
                     mix = mps.direct_sum(m_new, sub_m[(src, dst)], np.full(nb, 1.0 - eta), np.full(nb, eta))
                     m_new, _ = mps.canonical_message(mix, chi)
+                if gate > 0.0:
+                    changed = np.zeros(nb, dtype=bool)
+                    for key_in in inputs[(src, dst)]:
+                        changed |= ~(terms[key_in][active] < gate)
+                    old = sub_m[(src, dst)]
+                    m_new = [np.where(changed[:, None, None, None], a_new, a_old)
+                             for a_new, a_old in zip(m_new, old)]
                 fresh[(src, dst)] = m_new
             sub_m.update(fresh)
+            if gate > 0.0:
+                for key, v in fresh.items():
+                    ov = mps.overlap(v, prev[key])
+                    t = terms[key]
+                    t[active] = 2.0 - 2.0 * ov * ov
         acc = np.zeros(nb)
         for e in plan.edges:
             key = (e[0], e[1])
@@ -242,7 +265,7 @@ def decide(loglik: np.ndarray, delta: np.ndarray, delta1: float, rule: int = 0) 
 
 def decode(d: int, eps: float, syndromes: np.ndarray, block=(6, 6), chi: int = 16, max_iter: int = 20,
            delta0: float = 1e-4, delta1: float = 1e-2, eta: float = 0.1, fixed_iters: bool = False,
-           rule: int = 0, noise=None, return_messages: bool = False):
+           rule: int = 0, noise=None, return_messages: bool = False, gate: float = 0.0):
     """Decode syndromes [S, m]. Returns a dict with loglik [S, 4] (ln of the Bethe estimate of each coset
     probability, order I, X, Y, Z), delta [S, 4], iters [S, 4], coset [S], correction [S, n] (codes
     x + 2z of f_s L*), and optionally the final messages."""
@@ -255,7 +278,7 @@ def decode(d: int, eps: float, syndromes: np.ndarray, block=(6, 6), chi: int = 1
     zb = z.reshape(S * 4, L, L)
     plan = Plan(d, block[0], block[1])
     tensors = network.coset_tensors(d, xb, zb, pi)
-    msgs, delta, iters = run_bp(plan, tensors, chi, max_iter, delta0, eta, fixed_iters)
+    msgs, delta, iters = run_bp(plan, tensors, chi, max_iter, delta0, eta, fixed_iters, gate)
     lnz, bad = bethe(plan, tensors, msgs, chi)
     lnz = np.where(bad, np.nan, lnz)
     delta = np.where(bad, np.inf, delta)
