@@ -493,20 +493,24 @@ def bmps_main(a):
 
 
 SCHEDULE_VARIANTS = [
-    # (label, max_iter, delta0, delta1, fixed_iters)
-    ("paper: <= 20 iterations, early exit at 1e-4", 20, 1e-4, 1e-2, 0),
-    ("<= 10 iterations", 10, 1e-4, 1e-2, 0),
-    ("<= 5 iterations", 5, 1e-4, 1e-2, 0),
-    ("<= 3 iterations", 3, 1e-4, 1e-2, 0),
-    ("early exit at 1e-3", 20, 1e-3, 1e-2, 0),
-    ("early exit at 1e-2", 20, 1e-2, 1e-2, 0),
-    ("trust threshold 1e-1", 20, 1e-4, 1e-1, 0),
-    ("20 iterations, no early exit", 20, 1e-4, 1e-2, 1),
+    # (label, max_iter, delta0, delta1, fixed_iters, gate)
+    ("paper: <= 20 iterations, early exit at 1e-4", 20, 1e-4, 1e-2, 0, 0.0),
+    ("<= 10 iterations", 10, 1e-4, 1e-2, 0, 0.0),
+    ("<= 5 iterations", 5, 1e-4, 1e-2, 0, 0.0),
+    ("<= 3 iterations", 3, 1e-4, 1e-2, 0, 0.0),
+    ("early exit at 1e-3", 20, 1e-3, 1e-2, 0, 0.0),
+    ("early exit at 1e-2", 20, 1e-2, 1e-2, 0, 0.0),
+    ("trust threshold 1e-1", 20, 1e-4, 1e-1, 0, 0.0),
+    ("20 iterations, no early exit", 20, 1e-4, 1e-2, 1, 0.0),
+    ("residual gate 1e-7", 20, 1e-4, 1e-2, 0, 1e-7),
+    ("residual gate 1e-6", 20, 1e-4, 1e-2, 0, 1e-6),
+    ("residual gate 1e-5", 20, 1e-4, 1e-2, 0, 1e-5),
+    ("residual gate 1e-6, early exit at 1e-2", 20, 1e-2, 1e-2, 0, 1e-6),
 ]
 
 
 def schedule_main(a):
-    """Iteration and threshold variants of the blockBP decoder (6x6 blocks, chi 32, eta 0.1) on 4096
+    """Iteration, threshold and schedule variants of the blockBP decoder (6x6 blocks, chi 32, eta 0.1) on 4096
     syndromes at d=17 for p = 0.05 and 0.10, each judged against the single-block limit (bMPS, chi 16) on the
     same syndromes: throughput of one eager decode after a warm-up, mean iterations per coset, decisions
     equal to the reference, logical failures against the sampled errors."""
@@ -530,9 +534,9 @@ def schedule_main(a):
                          logical_failures=int(fr.sum())))
         del ref
         ws = None
-        for label, max_iter, d0, d1, fixed in SCHEDULE_VARIANTS:
+        for label, max_iter, d0, d1, fixed, gate in SCHEDULE_VARIANTS:
             opts = bbp.default_opts(block=6, chi=32, max_iter=max_iter, delta0=d0, delta1=d1, damping=0.1,
-                                    fixed_iters=fixed)
+                                    fixed_iters=fixed, gate=gate)
             out = bbp.decode_device(d, p, s, opts, workspace=ws)
             ws = out["workspace"]
             torch.cuda.synchronize()

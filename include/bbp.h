@@ -51,6 +51,12 @@ typedef struct bbp_opts {
                            stream other than the default stream; ignored when timing is requested. At most
                            64 graphs are kept; the 65th argument set empties the cache (after a device
                            synchronisation) */
+  double gate;          /* 0 = the paper's schedule. > 0: residual-gated schedule, a scheduling variant (Sec. IV
+                           leaves smarter scheduling open): in a colour round the update of message u->v is
+                           skipped for a coset when u->v itself and every message entering block u other than
+                           v->u changed, in their most recent updates, by a distance term 2 - 2<m, m_old>^2
+                           below gate; a skipped message keeps its value and its term becomes 0 (so it also
+                           counts 0 in Delta) */
 } bbp_opts;
 
 /* Defaults of Sec. IV: 6x6 blocks, chi 16, 20 iterations, delta0 1e-4, delta1 1e-2, eta 0.1; eager

@@ -167,10 +167,11 @@ def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: flo
 
     gate > 0 selects the residual-gated schedule, a scheduling variant (Sec. IV names smarter BP scheduling
     as a way to improve the hardest regimes and leaves it open; the rule itself is this implementation's
-    reading): in a colour round
-    the update of message u->v is skipped for a coset when every message entering block u other than v->u
-    changed, in its most recent update, by a distance term 2 - 2<m, m_old>^2 below gate; a skipped message
-    keeps its value and its term becomes 0. Messages that were never updated count as changed."""
+    reading): in a colour round the update of message u->v is skipped for a coset when the message itself and
+    every message entering block u other than v->u changed, in their most recent updates, by a distance term
+    2 - 2<m, m_old>^2 below gate; a skipped message keeps its value and its term becomes 0. Messages that were
+    never updated count as changed. (With damping, a message whose inputs have settled still moves towards
+    their image, so its own change is part of the test.)"""
     B = tensors[0][0].shape[0]
     msgs = {}
     for (src, dst, _) in plan.edges:
@@ -201,7 +202,7 @@ def run_bp(plan: Plan, tensors, chi: int, max_iter: int, delta0: float, eta: flo
                     mix = mps.direct_sum(m_new, sub_m[(src, dst)], np.full(nb, 1.0 - eta), np.full(nb, eta))
                     m_new, _ = mps.canonical_message(mix, chi)
                 if gate > 0.0:
-                    changed = np.zeros(nb, dtype=bool)
+                    changed = ~(terms[(src, dst)][active] < gate)
                     for key_in in inputs[(src, dst)]:
                         changed |= ~(terms[key_in][active] < gate)
                     old = sub_m[(src, dst)]

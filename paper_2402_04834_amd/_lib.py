@@ -23,6 +23,7 @@ class bbp_opts(C.Structure):
         ("block_rows", C.c_int32), ("block_cols", C.c_int32), ("chi", C.c_int32), ("max_iter", C.c_int32),
         ("delta0", C.c_double), ("delta1", C.c_double), ("damping", C.c_double),
         ("rule", C.c_int32), ("fixed_iters", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
+        ("gate", C.c_double),
     ]
 
 

@@ -81,7 +81,8 @@ __global__ __launch_bounds__(256) void labels_kernel(const uint8_t* __restrict__
 // norm with the entries beyond 2^K cleared; one workgroup per job, one wavefront per message
 __global__ __launch_bounds__(256) void init_kernel(float* __restrict__ msgs, const float* __restrict__ given,
                                                    const int32_t* __restrict__ edge_len, int M, int64_t jobs,
-                                                   int32_t* __restrict__ conv, int32_t* __restrict__ iters) {
+                                                   int32_t* __restrict__ conv, int32_t* __restrict__ iters,
+                                                   double* __restrict__ terms) {
   const int64_t job = blockIdx.x;
   const int lane = threadIdx.x & 63;
   for (int id = threadIdx.x >> 6; id < M; id += blockDim.x >> 6) {
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(256) void init_kernel(float* __restrict__ msgs, con
       v = in ? exp2f(-0.5f * K) : 0.0f;
     }
     msgs[at] = v;
+    if (lane == 0) terms[job * M + id] = INFINITY;   // never updated: counts as changed for a gated schedule
   }
   if (threadIdx.x == 0) {
     conv[job] = 0;
@@ -285,6 +287,7 @@ int validate(int32_t d, const bbp_opts* o) {
   if (o->rule != 0 && o->rule != 1) return fail(BBP_EINVAL, "rule must be 0 or 1");
   if (o->precision != 0 && o->precision != 1) return fail(BBP_EINVAL, "precision must be 0 (FP32) or 1 (BF16 inputs)");
   if (o->graph != 0 && o->graph != 1) return fail(BBP_EINVAL, "graph must be 0 or 1");
+  if (!(o->gate >= 0.0 && o->gate < INFINITY)) return fail(BBP_EINVAL, "gate must be finite and >= 0");
   return BBP_OK;
 }
 
@@ -505,7 +508,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
     if ((rc = begin_mark(st, 0, -1, -1))) return rc;
     labels_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(g.in.syndromes_dev, g.in.d, g.in.batch, g.labels);
     init_kernel<<<dim3((unsigned)g.jobs), dim3(256), 0, st>>>(g.msgs, g.in.init_messages_dev, g.dp->edge_len,
-                                                              g.dp->plan.M, g.jobs, g.conv, g.iters);
+                                                              g.dp->plan.M, g.jobs, g.conv, g.iters, g.terms);
     HIP_TRY(hipGetLastError());
     if ((rc = end_mark(st))) return rc;
   }
@@ -540,6 +543,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
       sa.order = tn.order;
       sa.bf16 = opts->precision == 1 ? 1 : 0;
       sa.eta = (float)opts->damping;
+      sa.gate = opts->gate;
       sa.small = (opts->block_rows <= 2 && opts->block_cols <= 2 && opts->precision == 0) ? 1 : 0;
       int64_t items = 0;
       for (int k = 0; k < sa.ngroups; ++k) {
@@ -737,7 +741,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
   const bbp_opts o = *opts;
   key.insert(key.end(), {(uint64_t)o.block_rows, (uint64_t)o.block_cols, (uint64_t)o.chi, (uint64_t)o.max_iter,
                          u64(o.delta0), u64(o.delta1), u64(o.damping), (uint64_t)o.rule, (uint64_t)o.fixed_iters,
-                         (uint64_t)o.precision});
+                         (uint64_t)o.precision, u64(o.gate)});
   for (auto& g : gr)
     key.insert(key.end(), {(uint64_t)g.in.d, (uint64_t)g.opts.chi, u64(g.in.p), u64(g.in.p_dev),
                            u64(g.in.syndromes_dev), (uint64_t)g.in.batch,

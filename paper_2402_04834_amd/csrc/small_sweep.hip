@@ -57,6 +57,16 @@ __global__ __launch_bounds__(256) void small_sweep_kernel(SweepArgs a) {
   }
   if (a.mode == 0 && G.conv[job]) return;
   const SweepDesc s = G.sweeps[sw];
+  if (a.mode == 0 && a.gate > 0.0) {
+    // residual-gated schedule: skip the update when the message and every input message have settled
+    const double* tj = G.terms + job * G.M;
+    const double ti = s.msg_init >= 0 ? tj[s.msg_init] : 0.0, tt = s.msg_top >= 0 ? tj[s.msg_top] : 0.0,
+                 tb = s.msg_bot >= 0 ? tj[s.msg_bot] : 0.0;
+    if (tj[s.msg_out] < a.gate && ti < a.gate && tt < a.gate && tb < a.gate) {
+      G.terms[job * G.M + s.msg_out] = 0.0;
+      return;
+    }
+  }
   const int L = 2 * G.d - 1;
   const uint8_t* lab = G.labels + job * L * L;
   const float* mbase = G.msgs + job * G.M * MSTRIDE;

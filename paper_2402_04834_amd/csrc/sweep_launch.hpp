@@ -46,6 +46,7 @@ struct SweepArgs {
   int32_t bf16;              // 1: products of BF16-rounded inputs (precision mode 1); 0: FP32 products
   float eta;                 // damping
   int32_t small;             // 1: every block is at most 2x2 tensors: one lane per item (small_sweep.hip)
+  double gate;               // > 0: skip an update whose message and input messages all changed by less (terms)
 };
 
 // Class of a sweep: the kernel instantiation that runs it -- length, caps present, one position across,

@@ -275,3 +275,41 @@ def test_biased_noise_parity(dev, d, k, iters):
     four, _, _ = bbp.decode_groups([(d, (1 - p, p / 3, p / 3, p / 3), torch.from_numpy(syn).to(dev))], opts)
     torch.cuda.synchronize()
     np.testing.assert_allclose(four[0]["loglik"].cpu().numpy(), dep["loglik"].cpu().numpy(), rtol=0, atol=1e-4)
+
+
+def test_residual_gate_limits(dev):
+    """Residual-gated schedule at its limits, through the C ABI: a gate of 1e-300 skips only updates whose
+    message and inputs did not change at all in FP32, which reproduce their message up to rounding; a gate
+    above the largest possible term (8) lets only the first iteration update, so the messages after three
+    iterations are those after one, Delta is 0 and early exit happens after the second iteration."""
+    d, p, k, chi = 7, 0.10, 4, 16
+    _say(f"[gate limits] d={d} k={k} chi={chi}")
+    _, syn = workload.make_batch(d, p, 8, workload="test", p_index=41)
+    base = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=6, fixed_iters=1)
+    tiny = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=6, fixed_iters=1, gate=1e-300)
+    np.testing.assert_allclose(tiny["messages"], base["messages"], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(tiny["loglik"], base["loglik"], rtol=0, atol=1e-5)
+    np.testing.assert_array_equal(tiny["coset"], base["coset"])
+    one = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=1, fixed_iters=1)
+    big = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=3, fixed_iters=1, gate=10.0)
+    np.testing.assert_array_equal(big["messages"], one["messages"])
+    assert np.all(big["delta"] == 0.0) and np.all(one["delta"] > 1e-3)
+    ex = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=20, gate=10.0)
+    assert np.all(ex["iters"] == 2)
+
+
+def test_residual_gate_against_oracle(dev):
+    """Gate 1e-6 in early-exit mode against the oracle's gated schedule. FP32 and FP64 distance terms may fall
+    on different sides of the gate, and a skip decision taken differently moves a message by about the
+    square root of the gate, so estimates must agree to 2e-3 nats, iteration counts to 3, decisions exactly
+    away from ties."""
+    d, p, k, chi = 7, 0.10, 4, 16
+    _say(f"[gate parity] d={d} k={k} chi={chi} gate=1e-6")
+    _, syn = workload.make_batch(d, p, 6, workload="test")
+    ref = blockbp.decode(d, p, syn, block=(k, k), chi=chi, max_iter=40, gate=1e-6)
+    got = _gpu_decode(dev, d, p, syn, block=k, chi=chi, max_iter=40, gate=1e-6)
+    err = np.abs(got["loglik"] - ref["loglik"])
+    _say(f"   max |d lnZ| {err.max():.2e}, iterations gpu {got['iters'].mean():.2f} oracle {ref['iters'].mean():.2f}")
+    assert err.max() < 2e-3
+    assert np.all(np.abs(got["iters"] - ref["iters"]) <= 3)
+    _decisions_agree(got["coset"], ref["loglik"], ref["coset"], ref["delta"], 1e-2)

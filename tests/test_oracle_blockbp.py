@@ -319,12 +319,12 @@ def test_residual_gate_limits():
 
 
 def test_residual_gate_keeps_decisions():
-    """With a gate of 1e-5 (per-message distance term) the decoder skips the updates of blocks whose inputs
-    have settled: it needs fewer iterations, and its estimates stay within 0.05 nats of the paper's schedule
-    with the same decisions (d=7, 4x4 blocks, chi 16)."""
+    """With a gate of 1e-6 (per-message distance term) the decoder skips the updates of messages that have
+    settled together with their inputs: it needs fewer iterations, and its estimates stay within 0.05 nats of
+    the paper's schedule with the same decisions (d=7, 4x4 blocks, chi 16)."""
     _, s = workload.make_batch(7, 0.1, 6, workload="test")
     a = blockbp.decode(7, 0.1, s, block=(4, 4), chi=16, max_iter=40)
-    b = blockbp.decode(7, 0.1, s, block=(4, 4), chi=16, max_iter=40, gate=1e-5)
+    b = blockbp.decode(7, 0.1, s, block=(4, 4), chi=16, max_iter=40, gate=1e-6)
     np.testing.assert_array_equal(a["coset"], b["coset"])
     assert np.nanmax(np.abs(a["loglik"] - b["loglik"])) < 0.05
     assert b["iters"].mean() < a["iters"].mean()
