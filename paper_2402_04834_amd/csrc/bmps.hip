@@ -304,6 +304,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
       const T thr2 = wave_sum(nf2) * (Tol<T>::rank * Tol<T>::rank);
       for (int sw = 0; sw < Tol<T>::sweeps; ++sw) {
         int rotated = 0;
+        T c2max = T(0);   // largest squared cosine of a pair above the noise threshold in this sweep
         for (int rd = 0; rd < 31; ++rd) {
           const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : (2 * rd - hi + 62) % 31;
 #pragma unroll
@@ -324,7 +325,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
           // (alpha, beta) = squared norms of the lower- and higher-numbered row of the pair
           const bool lower = hi < pl;
           const T al = lower ? aa : bb, be = lower ? bb : aa;
-          if (al > thr2 && be > thr2 && mabs(gg) > Tol<T>::jac * msqrt(al * be)) {
+          // squared cosine of the pair (approximate reciprocal: it only decides whether to rotate)
+          const T c2 = (al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : T(0);
+          c2max = c2 > c2max ? c2 : c2max;
+          if (c2 > Tol<T>::jac * Tol<T>::jac) {
             // The angle only has to bring the pair closer to orthogonal, so t = tan(theta) is formed in FP32
             // (fast reciprocal and square root; above the noise threshold zeta stays within 1e30); cos and
             // sin are then formed in FP64 from that t, so that the rotation is orthogonal to FP64 rounding.
@@ -342,7 +346,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
             rotated = 1;
           }
         }
-        if (!__any(rotated)) break;
+        // Jacobi converges quadratically: after a sweep whose pairs all started within cos 1e-8 of
+        // orthogonal, they are within ~1e-16 and a confirming sweep would rotate nothing
+        if (!__any(rotated) || wave_max(c2max) < T(1e-16)) break;
       }
       // singular values, ranks (largest first, ties to the lower row), kept rows
       T s2 = T(0);
