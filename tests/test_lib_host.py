@@ -180,3 +180,34 @@ def test_warm_start_host_side(bbp):
     assert "NULL" in h.bbp_warm_last_error().decode() or "pointer" in h.bbp_warm_last_error().decode()
     # the committed weights have the network's shape
     assert warm.load().shape == (warm.param_count(),)
+
+
+def test_bmps_and_gate_host_side(bbp):
+    """Boundary-MPS workspace sizes (labels plus 20 KiB of FP64 state per grid row and coset network) and
+    the argument checks that precede any device work; the gate option's range."""
+    import ctypes as C
+    from paper_2402_04834_amd import _lib
+    h = _lib.lib()
+    n = C.c_size_t()
+    d, batch = 17, 8
+    L = 2 * d - 1
+    assert h.bbp_bmps_workspace_size(d, batch, 16, C.byref(n)) == _lib.BBP_OK
+    label_bytes = -(-batch * 4 * L * L // 256) * 256
+    assert n.value == label_bytes + 4 * batch * L * (16 * 2 * 16 + 64 * 32) * 8
+    assert h.bbp_bmps_workspace_size(d, batch, 17, C.byref(n)) == _lib.BBP_EINVAL     # chi above 16
+    assert h.bbp_bmps_workspace_size(d, batch, 0, C.byref(n)) == _lib.BBP_EINVAL      # chi below 1
+    assert h.bbp_bmps_workspace_size(1, batch, 16, C.byref(n)) == _lib.BBP_EINVAL     # d below 2
+    assert h.bbp_bmps_workspace_size(d, -1, 16, C.byref(n)) == _lib.BBP_EINVAL        # negative batch
+    # batch 0 is a no-op that touches no pointer; bad noise is refused before any launch
+    assert h.bbp_bmps_decode_device(d, 0.1, None, None, None, 0, 16, None, 0, None, None, None, None, None) \
+        == _lib.BBP_OK
+    bad = (C.c_double * 4)(0.5, 0.2, 0.2, 0.2)
+    assert h.bbp_bmps_decode_device(d, 0.1, None, bad, None, 0, 16, None, 0, None, None, None, None, None) \
+        == _lib.BBP_EINVAL
+    assert h.bbp_bmps_decode_device(d, 1.5, None, None, None, 0, 16, None, 0, None, None, None, None, None) \
+        == _lib.BBP_EINVAL
+    # the residual gate must be finite and non-negative
+    assert h.bbp_workspace_size(d, batch, C.byref(bbp.default_opts(gate=1e-6)), C.byref(n)) == _lib.BBP_OK
+    assert h.bbp_workspace_size(d, batch, C.byref(bbp.default_opts(gate=-1.0)), C.byref(n)) == _lib.BBP_EINVAL
+    assert h.bbp_workspace_size(d, batch, C.byref(bbp.default_opts(gate=float("inf"))), C.byref(n)) \
+        == _lib.BBP_EINVAL
