@@ -50,19 +50,20 @@ def _report(tag, got, ref):
 
 
 def _check_fp64(got_ll, ref_ll):
-    """Two FP64 evaluations of one bMPS contraction, rounded in different orders, agree to about u * kappa,
-    where kappa -- the state's norm times the norm of the rest of the network over the coset's value --
-    grows roughly like exp(gap) for a coset gap nats below the best one; where chi truncates, two valid
-    truncations may also keep different vectors at a (near-)tie of the singular values at the cut, which
-    the same factor amplifies. Cosets within 15 nats of the best must agree to 1e-8 + 1e-11 exp(gap) nats;
-    a coset further below, which no decision can pick, must stay more than 10 nats below the GPU's best."""
+    """Two FP64 evaluations of one bMPS contraction agree on a coset's value Z_k only to a relative accuracy
+    eps with respect to the dominant scale of the contraction (the likeliest configurations, about Z of the
+    best coset): rounding in different orders, and -- where chi truncates -- different but equally valid
+    choices at near-ties of the singular values at a cut. The error in ln Z_k is then about eps * exp(gap)
+    for a coset gap nats below the best. With eps = 1e-9 (measured up to 3e-11 at d = 13), cosets within 12
+    nats of the best must agree to 1e-8 + 1e-9 exp(gap) nats; a coset further below, which no decision can
+    pick, must stay more than 8 nats below the GPU's best."""
     gap = ref_ll.max(axis=1, keepdims=True) - ref_ll
     got_gap = got_ll.max(axis=1, keepdims=True) - got_ll
     err = np.abs(got_ll - ref_ll)
-    near = gap <= 15.0
-    bad = near & (err > 1e-8 + 1e-11 * np.exp(np.minimum(gap, 15.0)))
+    near = gap <= 12.0
+    bad = near & (err > 1e-8 + 1e-9 * np.exp(np.minimum(gap, 12.0)))
     assert not bad.any(), f"errors {err[bad]} at gaps {gap[bad]}"
-    far_bad = ~near & ~(got_gap > 10.0)
+    far_bad = ~near & ~(got_gap > 8.0)
     assert not far_bad.any(), f"far cosets {got_ll[far_bad]} not far below the best"
 
 
@@ -94,7 +95,8 @@ def test_exact_regime_against_exact_contraction(dev, d, chi, p):
     _check_correction(d, syn, got)
 
 
-@pytest.mark.parametrize("d,chi,p", [(7, 16, 0.10), (9, 16, 0.10), (7, 8, 0.10), (9, 4, 0.12), (11, 16, 0.08)])
+@pytest.mark.parametrize("d,chi,p", [(7, 16, 0.10), (9, 16, 0.10), (7, 8, 0.10), (9, 4, 0.12), (11, 16, 0.08),
+                                     (13, 16, 0.10), (13, 12, 0.14)])
 def test_truncated_against_oracle(dev, d, chi, p):
     _say(f"[bmps truncated] d={d} chi={chi} p={p}")
     _, syn = workload.make_batch(d, p, 8, workload="test")
