@@ -502,24 +502,28 @@ def bmps_main(a):
 
 
 SCHEDULE_VARIANTS = [
-    # (label, max_iter, delta0, delta1, fixed_iters, gate)
-    ("paper: <= 20 iterations, early exit at 1e-4", 20, 1e-4, 1e-2, 0, 0.0),
-    ("<= 10 iterations", 10, 1e-4, 1e-2, 0, 0.0),
-    ("<= 5 iterations", 5, 1e-4, 1e-2, 0, 0.0),
-    ("<= 3 iterations", 3, 1e-4, 1e-2, 0, 0.0),
-    ("early exit at 1e-3", 20, 1e-3, 1e-2, 0, 0.0),
-    ("early exit at 1e-2", 20, 1e-2, 1e-2, 0, 0.0),
-    ("trust threshold 1e-1", 20, 1e-4, 1e-1, 0, 0.0),
-    ("20 iterations, no early exit", 20, 1e-4, 1e-2, 1, 0.0),
-    ("residual gate 1e-7", 20, 1e-4, 1e-2, 0, 1e-7),
-    ("residual gate 1e-6", 20, 1e-4, 1e-2, 0, 1e-6),
-    ("residual gate 1e-5", 20, 1e-4, 1e-2, 0, 1e-5),
-    ("residual gate 1e-6, early exit at 1e-2", 20, 1e-2, 1e-2, 0, 1e-6),
+    # (label, block, max_iter, delta0, delta1, fixed_iters, gate)
+    ("paper: <= 20 iterations, early exit at 1e-4", 6, 20, 1e-4, 1e-2, 0, 0.0),
+    ("<= 10 iterations", 6, 10, 1e-4, 1e-2, 0, 0.0),
+    ("<= 5 iterations", 6, 5, 1e-4, 1e-2, 0, 0.0),
+    ("<= 3 iterations", 6, 3, 1e-4, 1e-2, 0, 0.0),
+    ("early exit at 1e-3", 6, 20, 1e-3, 1e-2, 0, 0.0),
+    ("early exit at 1e-2", 6, 20, 1e-2, 1e-2, 0, 0.0),
+    ("trust threshold 1e-1", 6, 20, 1e-4, 1e-1, 0, 0.0),
+    ("20 iterations, no early exit", 6, 20, 1e-4, 1e-2, 1, 0.0),
+    ("residual gate 1e-7", 6, 20, 1e-4, 1e-2, 0, 1e-7),
+    ("residual gate 1e-6", 6, 20, 1e-4, 1e-2, 0, 1e-6),
+    ("residual gate 1e-5", 6, 20, 1e-4, 1e-2, 0, 1e-5),
+    ("residual gate 1e-6, early exit at 1e-2", 6, 20, 1e-2, 1e-2, 0, 1e-6),
+    ("blocks 4x4", 4, 20, 1e-4, 1e-2, 0, 0.0),
+    ("blocks 3x3", 3, 20, 1e-4, 1e-2, 0, 0.0),
+    ("blocks 2x2", 2, 20, 1e-4, 1e-2, 0, 0.0),
+    ("blocks 1x1 (plain BP)", 1, 20, 1e-4, 1e-2, 0, 0.0),
 ]
 
 
 def schedule_main(a):
-    """Iteration, threshold and schedule variants of the blockBP decoder (6x6 blocks, chi 32, eta 0.1) on 4096
+    """Iteration, threshold, schedule and block-size variants of the blockBP decoder (chi 32, eta 0.1) on 4096
     syndromes at d=17 for p = 0.05 and 0.10, each judged against the single-block limit (bMPS, chi 16) on the
     same syndromes: throughput of one eager decode after a warm-up, mean iterations per coset, decisions
     equal to the reference, logical failures against the sampled errors."""
@@ -542,11 +546,10 @@ def schedule_main(a):
         rows.append(dict(p=p, variant="reference: single block (bMPS, chi 16)",
                          logical_failures=int(fr.sum())))
         del ref
-        ws = None
-        for label, max_iter, d0, d1, fixed, gate in SCHEDULE_VARIANTS:
-            opts = bbp.default_opts(block=6, chi=32, max_iter=max_iter, delta0=d0, delta1=d1, damping=0.1,
+        for label, block, max_iter, d0, d1, fixed, gate in SCHEDULE_VARIANTS:
+            opts = bbp.default_opts(block=block, chi=32, max_iter=max_iter, delta0=d0, delta1=d1, damping=0.1,
                                     fixed_iters=fixed, gate=gate)
-            out = bbp.decode_device(d, p, s, opts, workspace=ws)
+            out = bbp.decode_device(d, p, s, opts)
             ws = out["workspace"]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
