@@ -191,6 +191,9 @@ def main():
                     help="skip the launch-variant autotuner (job-major items, one stream): for profiler runs, "
                          "whose kernel statistics should hold the timed decodes only")
     ap.add_argument("--warm-d", type=int, default=25, help="distance of the warm-start comparison (default 25)")
+    ap.add_argument("--bmps-d", type=int, default=17,
+                    help="distance of the single-block (bMPS) workload (default 17, the d17 syndromes; other "
+                         "distances draw their own seeded syndromes at p=0.10)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a known-size reference dispatch "
                          "for hardware byte counters)")
@@ -456,7 +459,7 @@ def bmps_main(a):
     import paper_2402_04834_amd as bbp
     from paper_2402_04834_amd import workload
 
-    d, p, chi, count = 17, 0.10, 16, a.batch
+    d, p, chi, count = a.bmps_d, 0.10, 16, a.batch
     errors, syn = workload.make_batch(d, p, count, workload="d17")
     dev = torch.device("cuda:0")
     s = torch.from_numpy(syn).to(dev)
@@ -483,12 +486,13 @@ def bmps_main(a):
     fb = logical_failures(d, errors, out["correction"].cpu().numpy())
     fr = logical_failures(d, errors, ref["correction"].cpu().numpy())
     line = dict(
-        metric="syndromes decoded/s at d=17 by the single-block limit (bMPS, chi 16; 1 GPU)",
+        metric=f"syndromes decoded/s at d={d} by the single-block limit (bMPS, chi 16; 1 GPU)",
         value=count * a.steps / elapsed, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
         ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64", data="synthetic",
-        config=dict(workload=f"{count} syndromes, d=17, p=0.10 (the d17 syndromes), one block = the whole "
-                             "network, boundary MPS chi 16, FP64", batch=count, parallelism="single GPU"),
+        config=dict(workload=f"{count} syndromes, d={d}, p=0.10 (seeded, the d17 workload's generator), one "
+                             "block = the whole network, boundary MPS chi 16, FP64", batch=count,
+                    parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                       frac=achieved / PEAK_FP64_TFLOPS, traffic=None, kernel="bmps_kernel<double>",
                       avg_launch_ms=avg_ms, flops_per_launch=flops),
