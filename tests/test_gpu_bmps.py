@@ -182,3 +182,18 @@ def test_full_size_sampled(dev):
     _say(f"   NaN estimates: {int(np.isnan(ll).sum())} of {ll.size}")
     assert np.all(np.isfinite(best))
     assert np.all(np.isnan(ll).sum(axis=1) < 4)
+
+
+def test_biased_truncated_against_oracle(dev):
+    """Biased noise where chi truncates (d=9, chi 8) against the oracle's bMPS with the same Pauli table."""
+    d, chi = 9, 8
+    probs = workload.biased_probs(0.10, 10.0)
+    _, syn = workload.make_batch_pauli(d, probs, 6, p_index=9)
+    _say(f"[bmps biased truncated] d={d} chi={chi}")
+    got = _gpu(dev, d, probs, syn, chi)
+    pI, pX, pZ, pY = probs
+    ref = bmps.bmps_coset_loglik(d, syn, np.array([[pI, pZ], [pX, pY]]), chi)
+    _report("biased gpu vs oracle bMPS", got["loglik"], ref)
+    _check_fp64(got["loglik"], ref)
+    _check_decisions(got, ref, 1e-5)
+    _check_correction(d, syn, got)
