@@ -305,26 +305,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
       for (int sw = 0; sw < Tol<T>::sweeps; ++sw) {
         int rotated = 0;
         T c2max = T(0);   // largest squared cosine of a pair above the noise threshold in this sweep
+        // squared norm of this lane's row, exact at the start of the sweep and then carried through the
+        // rotations (both lanes of a row hold the same value); it travels with the row in slot 16
+        T own = T(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) own += y[k] * y[k];
+        own += __shfl_xor(own, 1);
         for (int rd = 0; rd < 31; ++rd) {
           const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : (2 * rd - hi + 62) % 31;
 #pragma unroll
           for (int k = 0; k < 16; ++k) Xsh[ln * XSTRIDE + k] = y[k];
+          Xsh[ln * XSTRIDE + 16] = own;
           __syncthreads();
-          T z[16], aa = T(0), bb = T(0), gg = T(0);
+          T z[16], gg = T(0);
 #pragma unroll
           for (int k = 0; k < 16; ++k) {
             z[k] = Xsh[(2 * pl + par) * XSTRIDE + k];
-            aa += y[k] * y[k];
-            bb += z[k] * z[k];
             gg += y[k] * z[k];
           }
+          const T other = Xsh[(2 * pl + par) * XSTRIDE + 16];
           __syncthreads();   // every lane has read its partner before the next round's writes
-          aa += __shfl_xor(aa, 1);
-          bb += __shfl_xor(bb, 1);
           gg += __shfl_xor(gg, 1);
           // (alpha, beta) = squared norms of the lower- and higher-numbered row of the pair
           const bool lower = hi < pl;
-          const T al = lower ? aa : bb, be = lower ? bb : aa;
+          const T al = lower ? own : other, be = lower ? other : own;
           // squared cosine of the pair (approximate reciprocal: it only decides whether to rotate)
           const T c2 = (al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : T(0);
           c2max = c2 > c2max ? c2 : c2max;
@@ -343,6 +347,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
             // lower row p: c p - s q; higher row q: s p + c q
 #pragma unroll
             for (int k = 0; k < 16; ++k) y[k] = lower ? (cs * y[k] - sn * z[k]) : (sn * z[k] + cs * y[k]);
+            // squared norms after this rotation: c^2 (alpha -+ 2 t gamma + t^2 beta) for the lower row and
+            // c^2 (beta +- ...) for the higher one, exact for the c and s applied
+            const T cc = cs * cs;
+            own = lower ? cc * (al - T(2) * tt * gg + tt * tt * be) : cc * (be + T(2) * tt * gg + tt * tt * al);
             rotated = 1;
           }
         }
