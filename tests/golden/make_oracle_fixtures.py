@@ -3,7 +3,11 @@ seeded input generator). The GPU tests and the benchmark's agreement figure read
 them comes from the HIP path.
 
     python tests/golden/make_oracle_fixtures.py --workload d17 --d 17 --p 0.10 --block 6 --chi 32 \
-        --count 256 --procs 6 --out tests/golden/d17_p010_k6_chi32.json
+        --count 4096 --chunk 4 --procs 7 --out tests/golden/d17_p010_k6_chi32.json
+
+An existing file with the same parameters is extended (records already present are kept), so a long run can
+be resumed. The committed d=17 file holds all 4096 syndromes of the benchmark batch (about 12 hours of oracle
+time on one core).
 """
 from __future__ import annotations
 
