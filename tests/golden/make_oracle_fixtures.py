@@ -6,8 +6,8 @@ them comes from the HIP path.
         --count 4096 --chunk 4 --procs 7 --out tests/golden/d17_p010_k6_chi32.json
 
 An existing file with the same parameters is extended (records already present are kept), so a long run can
-be resumed. The committed d=17 file holds all 4096 syndromes of the benchmark batch (about 12 hours of oracle
-time on one core).
+be resumed. The committed d=17 file holds all 4096 syndromes of the benchmark batch (about 21 hours of oracle
+time summed over the worker processes).
 """
 from __future__ import annotations
 
