@@ -23,16 +23,17 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/c
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
 GOLDEN = os.path.join(ROOT, "tests", "golden", "d17_p010_k6_chi32.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "sweep_kernel_d17_b4096_traffic.txt")
+BMPS_TRAFFIC = os.path.join(ROOT, "profiles", "bmps_kernel_d17_b4096_traffic.txt")
 
 
-def traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counter summary (each
+def traffic(kernel, path=TRAFFIC):
+    """HBM bytes per launch of `kernel` from a committed FETCH_SIZE / WRITE_SIZE counter summary (each
     scaled by what the counter reads for a 1 GiB copy), or None when no summary covers it or the kernel
     sources changed since the counters were taken."""
     import hashlib
-    if not os.path.exists(TRAFFIC):
+    if not os.path.exists(path):
         return None
-    t = json.load(open(TRAFFIC))
+    t = json.load(open(path))
     h = hashlib.sha256()
     for f in t["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -44,21 +45,27 @@ def traffic(kernel):
 
 TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/geom.hpp", "paper_2402_04834_amd/csrc/sweep_launch.hpp",
                    "paper_2402_04834_amd/csrc/wave_sweep.hpp", "paper_2402_04834_amd/csrc/sweep_kernel.hip"]
+BMPS_TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/bmps_launch.hpp", "paper_2402_04834_amd/csrc/bmps.hip"]
 
 
 def _short_kernel_name(name):
     """'void bbp::(anonymous namespace)::sweep_kernel<float, 6, true, true, false, true, false>(...)' ->
     'sweep_kernel<6, true, true, false, true>' (the name bbp_timing reports for the FP32 depolarizing
-    kernels); other kernels keep their name."""
+    kernels); 'bmps_kernel<double>'; other kernels keep their name."""
     import re
     m = re.search(r"sweep_kernel<float, (\d+(?:, (?:true|false)){4}), false>", name)
-    return f"sweep_kernel<{m.group(1)}>" if m else name
+    if m:
+        return f"sweep_kernel<{m.group(1)}>"
+    return "bmps_kernel<double>" if "bmps_kernel<double>" in name else name
 
 
-def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of every FP32 sweep kernel from two rocprofv3 --pmc
-    counter CSVs of `bench.py --calibrate-copy MIB`, with the scale factors that make the calibration
-    copy read and write exactly its size; stamped with the hash of the kernel sources."""
+def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024, target="sweep"):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of every FP32 sweep kernel (target "sweep") or of the
+    boundary-MPS kernel (target "bmps") from two rocprofv3 --pmc counter CSVs of `bench.py --calibrate-copy
+    MIB`, with the scale factors that make the calibration copy read and write exactly its size; stamped
+    with the hash of the kernel sources."""
+    sources, path, prefix = ((TRAFFIC_SOURCES, TRAFFIC, "sweep_kernel<") if target == "sweep" else
+                             (BMPS_TRAFFIC_SOURCES, BMPS_TRAFFIC, "bmps_kernel<"))
     import collections
     import csv
     import hashlib
@@ -78,19 +85,19 @@ def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024):
     write = {k: (sum(d.values()) / len(d), len(d)) for k, d in write.items()}
     size_kib = copy_mib * 1024.0
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     kernels = {}
     for k, (v, n) in fetch.items():
         short = _short_kernel_name(k)
-        if short.startswith("sweep_kernel<") and k in write:
+        if short.startswith(prefix) and k in write:
             kernels[short] = dict(fetch_kib=v, write_kib=write[k][0], dispatches=n)
-    out = dict(source_sha256=h.hexdigest(), sources=TRAFFIC_SOURCES, fetch_scale=round(size_kib / cf, 4),
+    out = dict(source_sha256=h.hexdigest(), sources=sources, fetch_scale=round(size_kib / cf, 4),
                write_scale=round(size_kib / cw, 4),
                calibration=f"plain device copy of {copy_mib} MiB (bench.py --calibrate-copy {copy_mib}): FETCH_SIZE "
                            f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB",
                kernels=kernels)
-    with open(TRAFFIC, "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
     return out
 
@@ -200,9 +207,11 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of the sweep kernels from two rocprofv3 counter files "
                          "(FETCH_SIZE and WRITE_SIZE runs of this benchmark with --calibrate-copy 1024) and exit")
+    ap.add_argument("--traffic-target", choices=("sweep", "bmps"), default="sweep",
+                    help="kernels the traffic summary covers: the sweep kernels (default) or the bMPS kernel")
     a = ap.parse_args()
     if a.traffic_summary:
-        out = write_traffic_summary(*a.traffic_summary)
+        out = write_traffic_summary(*a.traffic_summary, target=a.traffic_target)
         print(json.dumps({k: v for k, v in out.items() if k != "kernels"}))
         return
     if a.gpus != 1:
@@ -214,6 +223,13 @@ def main():
     import paper_2402_04834_amd as bbp
     from paper_2402_04834_amd import _lib, workload
 
+    if a.calibrate_copy > 0:
+        n = a.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if a.workload == "mixed":
         return mixed_main(a)
     if a.workload == "warm":
@@ -224,13 +240,6 @@ def main():
         return bmps_main(a)
     if a.workload == "schedule":
         return schedule_main(a)
-    if a.calibrate_copy > 0:
-        n = a.calibrate_copy << 20
-        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     d, p, block, chi, max_iter = 17, 0.10, a.block, 32, 20
     errors, syn = workload.make_batch(d, p, a.batch, workload="d17")
@@ -494,7 +503,9 @@ def bmps_main(a):
                              "block = the whole network, boundary MPS chi 16, FP64", batch=count,
                     parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP64_TFLOPS, traffic=None, kernel="bmps_kernel<double>",
+                      frac=achieved / PEAK_FP64_TFLOPS,
+                      traffic=traffic("bmps_kernel<double>", BMPS_TRAFFIC) if d == 17 and count == 4096 else None,
+                      kernel="bmps_kernel<double>",
                       avg_launch_ms=avg_ms, flops_per_launch=flops),
         decisions_equal_to_blockbp=float((cb == cr).mean()),
         logical_failures=dict(bmps=[int(fb.sum()), count, list(wilson(int(fb.sum()), count))],
