@@ -259,9 +259,16 @@ def main():
         tune = bbp.autotune(d, p, syn_dev, opts, workspace=ws)
     bbp.set_tuning(d, opts, tune.order, tune.streams)
     events_in_timed = tune.streams == 1
-    out = bbp.decode_device(d, p, syn_dev, opts, workspace=ws)
+    # With the tuned multi-stream variant the timed steps replay the decode as one HIP graph (captured by the
+    # library on the first call, on a stream of its own): no host work per launch.
+    timed_opts, timed_stream = opts, None
+    if not events_in_timed:
+        timed_opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
+                                      damping=0.1, precision=a.precision, graph=1)
+        timed_stream = torch.cuda.Stream()
+    out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream)
     for _ in range(a.warmup):
-        out = bbp.decode_device(d, p, syn_dev, opts, workspace=ws, out=out)
+        out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream, out=out)
     torch.cuda.synchronize()
     upd_ms = upd_flops = bethe_ms = other_ms = 0.0
     launches = 0
@@ -285,7 +292,7 @@ def main():
             res = bbp.decode_device(d, p, syn_dev, opts, workspace=ws, timing=True)
             account(res["timing"])
         else:
-            out = bbp.decode_device(d, p, syn_dev, opts, workspace=ws, out=out)
+            out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream, out=out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = a.batch * a.steps / elapsed
@@ -321,6 +328,7 @@ def main():
         kernel_ms_per_step=dict(update=upd_ms / a.steps, bethe=bethe_ms / a.steps, other=other_ms / a.steps),
         mean_iterations_per_coset=iters,
         launch_tuning=dict(order=("sweep-major", "job-major")[tune.order], timed_streams=tune.streams,
+                           timed_as=("eager launches" if events_in_timed else "one HIP graph per step"),
                            tuning_decode_ms=tune.ms,
                            roofline_measured_on=("the timed decodes" if events_in_timed else
                                                  f"{a.steps} separate single-stream decodes")),
