@@ -328,3 +328,60 @@ def test_residual_gate_keeps_decisions():
     np.testing.assert_array_equal(a["coset"], b["coset"])
     assert np.nanmax(np.abs(a["loglik"] - b["loglik"])) < 0.05
     assert b["iters"].mean() < a["iters"].mean()
+
+
+def _dense_bp_by_hand(plan, tensors, eta, iters):
+    """Two-colour BP written out with dense messages and the dense block contraction above, independent of
+    run_bp: every message starts uniform (remark 2); in a round each block of that colour sends to every
+    neighbour the contraction of itself with the messages on its other sides, scaled to unit norm
+    (remark 3), then mixed as (1 - eta) * new + eta * old and scaled to unit norm again (remark 7); the
+    distance of an iteration is (1/M) * sqrt(sum over all M messages of 2 - 2 <new, old>^2) (remark 4).
+    Returns (messages, distances)."""
+    msgs = {}
+    for (src, dst, _) in plan.edges:
+        K = plan.msg_len(src, dst)
+        msgs[(src, dst)] = np.full(2 ** K, 2.0 ** (-K / 2))
+    dists = []
+    for _ in range(iters):
+        before = dict(msgs)
+        for colour in (0, 1):
+            fresh = {}
+            for (src, dst, dname) in plan.edges:
+                if (src[0] + src[1]) % 2 != colour:
+                    continue
+                dense_in = {}
+                for side, (dI, dJ) in blockbp.DIRS.items():
+                    nb = (src[0] + dI, src[1] + dJ)
+                    dense_in[side] = msgs[(nb, src)] if (side != dname and plan.has(nb)) else None
+                new = _block_einsum(tensors, plan, src[0], src[1], dname, dense_in)
+                new = new / np.linalg.norm(new)
+                mixed = (1.0 - eta) * new + eta * msgs[(src, dst)]
+                fresh[(src, dst)] = mixed / np.linalg.norm(mixed)
+            msgs.update(fresh)
+        acc = sum(2.0 - 2.0 * float(msgs[k] @ before[k]) ** 2 for k in msgs)
+        dists.append(np.sqrt(acc) / plan.M)
+    return msgs, dists
+
+
+@pytest.mark.parametrize("iters", [1, 2])
+@pytest.mark.parametrize("d,block", [(3, (3, 3)), (5, (4, 2))])
+def test_damping_and_distance_by_hand(d, block, iters):
+    # remark 7 weights the OLD message by eta, and remark 4 takes the prefactor 1/M outside the square root:
+    # with eta = 0.3 (not 1/2, so that eta and 1 - eta differ) and M > 1 swapping either reading changes
+    # both the messages and Delta well beyond rounding
+    eta = 0.3
+    _, s = workload.make_batch(d, 0.1, 1)
+    tensors = _coset_tensors(d, s, 0.1)
+    plan = blockbp.Plan(d, *block)
+    assert plan.M > 4
+    for job in (0, 2):
+        tj = [[t[job:job + 1] for t in row] for row in tensors]
+        want, dists = _dense_bp_by_hand(plan, tj, eta, iters)
+        msgs, delta, it = blockbp.run_bp(plan, tj, chi=64, max_iter=iters, delta0=1e-4, eta=eta, fixed_iters=True)
+        assert it[0] == iters
+        for key, v in want.items():
+            got = mps.to_dense(msgs[key])[0].reshape(-1)
+            np.testing.assert_allclose(got, v, atol=1e-12)
+        np.testing.assert_allclose(delta[0], dists[-1], rtol=1e-10)
+        # the readings the pin excludes are far away
+        assert abs(dists[-1] * np.sqrt(plan.M) - delta[0]) > 0.1 * delta[0]

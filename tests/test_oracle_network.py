@@ -142,3 +142,23 @@ def test_stabilizer_multiplication_leaves_coset_unchanged():
             else:
                 x2[..., rr, cc] ^= 1
     np.testing.assert_allclose(network.exact_log_contraction(d, x2, z2, pi), base, rtol=1e-12)
+
+
+# Coset probabilities at d = 3, eps = 0.1 (order I, X, Y, Z) for four syndromes, from an independent
+# enumeration of all 4^13 errors made when the method was surveyed (key = sum_i s_i 2^i, Z-checks first).
+# They fix the conventions of the syndrome order, the chains of f_s and the logical representatives
+# together: a transposed check order or a logical on the wrong boundary moves these values between columns.
+T1_D3_EPS010 = {
+    0: (2.542961146460e-01, 4.503023314070e-05, 4.059547115007e-07, 4.503023314070e-05),
+    1: (9.794635497390e-03, 3.918170363417e-04, 1.885841496142e-06, 1.676060097254e-05),
+    2608: (6.515426510093e-05, 3.537310818141e-04, 2.227326173760e-06, 2.303217803742e-06),
+    4095: (3.655236905926e-07, 1.207486874366e-07, 1.494542070982e-06, 1.207486874366e-07),
+}
+
+
+@pytest.mark.parametrize("key", sorted(T1_D3_EPS010))
+def test_literal_coset_probabilities_d3(key, bruteforce_d3):
+    want = np.array(T1_D3_EPS010[key])
+    s = ((key >> np.arange(12)) & 1).astype(np.uint8)[None]
+    np.testing.assert_allclose(bruteforce_d3[key], want, rtol=1e-11)
+    np.testing.assert_allclose(np.exp(network.exact_coset_loglik(3, s, 0.1))[0], want, rtol=1e-11)
