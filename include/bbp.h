@@ -152,6 +152,29 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
                       uint8_t* correction_dev, float* messages_dev, void* stream, bbp_timing* timing);
 
 /* ---------------------------------------------------------------------------------------------------
+ * Allocation-free decode, for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same semantics and results as bbp_decode_device
+ * (the same kernels, eager launches on `stream`, one stream, no timing, no message output), but the
+ * workspace and the plan's device tables live in a static device array of BBP_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends; the call itself allocates nothing (no
+ * hipMalloc, no hipFree, no allocating library routine) and enqueues the upload of the plan tables from
+ * host memory that the library keeps for the life of the process. The caller owns syndromes and outputs
+ * (device pointers, layouts as bbp_decode_device).
+ * Limit: the plan tables plus bbp_workspace_size(d, batch, opts) must fit in BBP_SCRATCH_BYTES;
+ * bbp_noalloc_max_batch gives the largest batch that fits (about 500 syndromes at d=17 with 6x6 blocks).
+ * Every call on a device shares that device's array, which keeps the last call's contents (nothing in it
+ * needs to start at zero: the decode writes every entry it reads): calls that overlap on one device race,
+ * so a caller serialises them (one stream, or events).
+ * Errors: BBP_EINVAL (arguments as bbp_decode_device; a batch beyond the limit, with the bytes it needs),
+ * BBP_EUNSUPPORTED, BBP_EHIP.
+ */
+#define BBP_SCRATCH_BYTES (64u << 20)
+int bbp_decode_device_noalloc(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch,
+                              const bbp_opts* opts, double* loglik_dev, double* delta_dev, int32_t* iters_dev,
+                              uint8_t* coset_dev, uint8_t* correction_dev, void* stream);
+int bbp_noalloc_max_batch(int32_t d, const bbp_opts* opts, int64_t* max_batch);
+
+/* ---------------------------------------------------------------------------------------------------
  * Mixed batches. A group is a batch of syndromes of one distance d (and bond dimension chi), each with its
  * noise rate p, resident in device memory, with the device arrays that receive its results (layouts as in
  * bbp_decode_device). One call

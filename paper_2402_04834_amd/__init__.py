@@ -14,6 +14,7 @@ from . import _lib
 from ._lib import BbpError, bbp_group, bbp_opts, bbp_plan_info, bbp_timing, bbp_tuning, default_opts
 
 __all__ = ["default_opts", "plan_query", "build_network", "workspace_size", "decode_device", "decode_groups",
+           "decode_device_noalloc", "noalloc_max_batch",
            "autotune", "set_tuning", "blockbp_decode", "reference_update_host", "BbpError", "bbp_opts",
            "bbp_timing", "bbp_tuning"]
 
@@ -108,6 +109,33 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
     if tm is not None:
         out["timing"] = tm
     out["workspace"] = workspace
+    return out
+
+
+def noalloc_max_batch(d: int, opts: bbp_opts) -> int:
+    """Largest batch that bbp_decode_device_noalloc accepts for distance d under opts."""
+    n = C.c_int64(0)
+    _lib.check(_lib.lib().bbp_noalloc_max_batch(d, C.byref(opts), C.byref(n)))
+    return n.value
+
+
+def decode_device_noalloc(d: int, p: float, syndromes, opts: bbp_opts, *, stream=None, out=None):
+    """The allocation-free decode (bbp_decode_device_noalloc) of a torch uint8 CUDA tensor [batch, m]: the
+    library's static device array holds its workspace; `out` (a dict of output tensors as returned by
+    decode_device) receives the results, else they are allocated here, before the call."""
+    import torch
+
+    assert syndromes.is_cuda and syndromes.dtype == torch.uint8 and syndromes.dim() == 2
+    syndromes = syndromes.contiguous()
+    batch = syndromes.shape[0]
+    dev = syndromes.device
+    n = d * d + (d - 1) * (d - 1)
+    if out is None:
+        out = _outputs(batch, n, dev)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    _lib.check(_lib.lib().bbp_decode_device_noalloc(
+        d, p, syndromes.data_ptr(), batch, C.byref(opts), out["loglik"].data_ptr(), out["delta"].data_ptr(),
+        out["iters"].data_ptr(), out["coset"].data_ptr(), out["correction"].data_ptr(), st))
     return out
 
 

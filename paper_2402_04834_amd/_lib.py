@@ -79,6 +79,10 @@ SIGNATURES = {
     "bbp_decode_device": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(bbp_timing)]),
+    "bbp_decode_device_noalloc": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+    "bbp_noalloc_max_batch": (C.c_int, [C.c_int32, C.POINTER(bbp_opts), C.POINTER(C.c_int64)]),
     "bbp_workspace_size_groups": (C.c_int, [C.POINTER(bbp_group), C.c_int32, C.POINTER(bbp_opts),
                                             C.POINTER(C.c_size_t)]),
     "bbp_decode_groups": (C.c_int, [C.POINTER(bbp_group), C.c_int32, C.POINTER(bbp_opts), C.c_void_p, C.c_size_t,

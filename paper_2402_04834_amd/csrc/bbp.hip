@@ -785,6 +785,143 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
   return BBP_OK;
 }
 
+// ------------------------------------------------------------------------------------------------
+// Allocation-free decode (bbp_decode_device_noalloc): the workspace and the plan's device tables live in
+// one static device array of BBP_SCRATCH_BYTES per device instead of caller or library allocations.
+// Layout of one call: [plan tables][workspace of bbp_workspace_size], both 256-byte aligned. Every call on a
+// device reuses the same array, so calls that overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[BBP_SCRATCH_BYTES];
+
+// Device address of this device's copy of `scratch`, looked up once per device with that device current.
+// The host-side name `scratch` is only a stand-in for the symbol; kernels and copies get this address.
+std::map<int, unsigned char*> g_scratch;
+
+int scratch_ptr(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(BBP_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    it = g_scratch.emplace(dev, (unsigned char*)ptr).first;
+  }
+  *out = it->second;
+  return BBP_OK;
+}
+
+// A plan whose device tables sit at the start of a device's scratch array: the host copies are kept for
+// the life of the process, because every call enqueues their upload (another call may have overwritten
+// the array since) and an enqueued copy reads its host source when it runs.
+struct ScratchPlan {
+  DevPlan dp;
+  std::vector<SweepDesc> lists[3];
+  std::vector<int32_t> edge_len, pairs;
+  size_t off[5] = {0, 0, 0, 0, 0};   // byte offsets of lists 0..2, edge_len, pairs
+  size_t bytes = 0;                  // total, 256-byte aligned
+};
+std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<ScratchPlan>> g_scratch_plans;
+
+int scratch_plan(int d, const bbp_opts* o, int dev, unsigned char* base, ScratchPlan** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(d, o->block_rows, o->block_cols, o->chi, dev);
+  auto it = g_scratch_plans.find(key);
+  if (it != g_scratch_plans.end()) { *out = it->second.get(); return BBP_OK; }
+  auto sp = std::make_unique<ScratchPlan>();
+  sp->dp.plan = host_plan(d, o);
+  sp->dp.device = dev;
+  const bbp::Plan& p = sp->dp.plan;
+  size_t off = 0;
+  for (int c = 0; c < 3; ++c) {
+    sp->lists[c] = (c < 2) ? p.round[c] : p.bethe;
+    sp->dp.runs[c] = by_class(sp->lists[c]);
+    sp->off[c] = off;
+    off = align256(off + sizeof(SweepDesc) * sp->lists[c].size());
+  }
+  sp->edge_len.assign(p.edge_len.begin(), p.edge_len.end());
+  sp->pairs.assign(p.pair_ids.begin(), p.pair_ids.end());
+  sp->off[3] = off;
+  off = align256(off + sizeof(int32_t) * sp->edge_len.size());
+  sp->off[4] = off;
+  off = align256(off + sizeof(int32_t) * sp->pairs.size());
+  sp->bytes = off;
+  sp->dp.round[0] = (SweepDesc*)(base + sp->off[0]);
+  sp->dp.round[1] = (SweepDesc*)(base + sp->off[1]);
+  sp->dp.bethe = (SweepDesc*)(base + sp->off[2]);
+  sp->dp.edge_len = (int32_t*)(base + sp->off[3]);
+  sp->dp.pairs = (int32_t*)(base + sp->off[4]);
+  *out = sp.get();
+  g_scratch_plans.emplace(key, std::move(sp));
+  return BBP_OK;
+}
+
+int decode_noalloc(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch, const bbp_opts* opts,
+                   double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
+                   uint8_t* correction_dev, void* stream) {
+  if (!opts) return fail(BBP_EINVAL, "opts is NULL");
+  bbp_opts o = *opts;
+  o.graph = 0;   // eager launches on the caller's stream (a caller may capture them)
+  bbp_group g;
+  std::memset(&g, 0, sizeof(g));
+  g.d = d;
+  g.p = p;
+  g.syndromes_dev = syndromes_dev;
+  g.batch = batch;
+  g.loglik_dev = loglik_dev;
+  g.delta_dev = delta_dev;
+  g.iters_dev = iters_dev;
+  g.coset_dev = coset_dev;
+  g.correction_dev = correction_dev;
+  std::vector<GroupRun> gr;
+  size_t total = 0;
+  int rc = resolve(&g, 1, &o, gr, &total, false);
+  if (rc) return rc;
+  const bbp::Plan& hp = host_plan(d, &gr[0].opts);
+  if (!hp.gpu_ok) return fail(BBP_EUNSUPPORTED, hp.why);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char* base = nullptr;
+  if ((rc = scratch_ptr(dev, &base))) return rc;
+  ScratchPlan* sp = nullptr;
+  if ((rc = scratch_plan(d, &gr[0].opts, dev, base, &sp))) return rc;
+  const size_t need = sp->bytes + total;
+  if (need > (size_t)BBP_SCRATCH_BYTES)
+    return fail(BBP_EINVAL, "the allocation-free decode needs " + std::to_string(need) +
+                                " bytes of scratch for this batch; its limit is " +
+                                std::to_string((size_t)BBP_SCRATCH_BYTES) + " bytes (use bbp_decode_device)");
+  if (batch == 0) return BBP_OK;
+  if (!syndromes_dev || !loglik_dev || !delta_dev || !iters_dev || !coset_dev || !correction_dev)
+    return fail(BBP_EINVAL, "a required pointer is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (int c = 0; c < 3; ++c)
+    if (!sp->lists[c].empty())
+      HIP_TRY(hipMemcpyAsync(base + sp->off[c], sp->lists[c].data(), sizeof(SweepDesc) * sp->lists[c].size(),
+                             hipMemcpyHostToDevice, st));
+  if (!sp->edge_len.empty())
+    HIP_TRY(hipMemcpyAsync(base + sp->off[3], sp->edge_len.data(), sizeof(int32_t) * sp->edge_len.size(),
+                           hipMemcpyHostToDevice, st));
+  if (!sp->pairs.empty())
+    HIP_TRY(hipMemcpyAsync(base + sp->off[4], sp->pairs.data(), sizeof(int32_t) * sp->pairs.size(),
+                           hipMemcpyHostToDevice, st));
+  GroupRun& G = gr[0];
+  G.dp = &sp->dp;
+  unsigned char* ws = base + sp->bytes;
+  G.labels = (uint8_t*)(ws + G.lay.labels);
+  G.msgs = (float*)(ws + G.lay.msgs);
+  G.terms = (double*)(ws + G.lay.terms);
+  G.lnw = (double*)(ws + G.lay.lnw);
+  G.conv = (int32_t*)(ws + G.lay.conv);
+  G.iters = (int32_t*)(ws + G.lay.iters);
+  G.delta = (double*)(ws + G.lay.delta);
+  Tune tn;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune.find(std::make_tuple(d, o.block_rows, o.block_cols, G.opts.chi, dev));
+    if (it != g_tune.end()) tn.order = it->second.order;
+  }
+  tn.streams = 1;   // auxiliary streams are not created here
+  return enqueue(gr, &o, tn, st, nullptr, nullptr);
+}
+
 }  // namespace
 
 struct bbp_net {
@@ -920,6 +1057,34 @@ int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t
   g.correction_dev = correction_dev;
   g.messages_dev = messages_dev;
   return decode_groups(&g, 1, opts, workspace, workspace_bytes, stream, timing, nullptr);
+}
+
+int bbp_decode_device_noalloc(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch,
+                              const bbp_opts* opts, double* loglik_dev, double* delta_dev, int32_t* iters_dev,
+                              uint8_t* coset_dev, uint8_t* correction_dev, void* stream) {
+  return decode_noalloc(d, p, syndromes_dev, batch, opts, loglik_dev, delta_dev, iters_dev, coset_dev,
+                        correction_dev, stream);
+}
+
+int bbp_noalloc_max_batch(int32_t d, const bbp_opts* opts, int64_t* max_batch) {
+  int rc = validate(d, opts);
+  if (rc) return rc;
+  if (!max_batch) return fail(BBP_EINVAL, "max_batch is NULL");
+  const bbp::Plan& p = host_plan(d, opts);
+  size_t tab = 0;
+  tab = align256(tab + sizeof(SweepDesc) * p.round[0].size());
+  tab = align256(tab + sizeof(SweepDesc) * p.round[1].size());
+  tab = align256(tab + sizeof(SweepDesc) * p.bethe.size());
+  tab = align256(tab + sizeof(int32_t) * p.edge_len.size());
+  tab = align256(tab + sizeof(int32_t) * p.pair_ids.size());
+  int64_t lo = 0, hi = (int64_t)1 << 24;
+  while (lo < hi) {   // largest batch whose tables and workspace fit
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (tab + layout(p, mid).total <= (size_t)BBP_SCRATCH_BYTES) lo = mid;
+    else hi = mid - 1;
+  }
+  *max_batch = lo;
+  return BBP_OK;
 }
 
 // ---- boundary-MPS decoder (single block) ----
