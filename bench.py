@@ -2,8 +2,9 @@
 
 Workload (one "step"): decode 4096 seeded syndromes of the d=17 planar surface code under i.i.d.
 depolarizing noise p=0.10 (X, Y, Z each p/3) -- blocks of 6x6 tensors, chi=32, at most 20 BP iterations
-with early exit (delta0 1e-4, delta1 1e-2, damping 0.1). The syndromes are resident in HBM before the
-timed region starts. Prints one JSON line.
+with early exit (delta0 1e-4, delta1 1e-2, damping 0.1), the contractions on the matrix cores in BF16 with
+FP32 accumulation and FP64 log-likelihoods (precision mode 1); the same decode in plain FP32 is timed beside
+it. The syndromes are resident in HBM before the timed region starts. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
@@ -49,13 +50,14 @@ BMPS_TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/bmps_launch.hpp", "paper_2402
 
 
 def _short_kernel_name(name):
-    """'void bbp::(anonymous namespace)::sweep_kernel<float, 6, true, true, false, true, false>(...)' ->
-    'sweep_kernel<6, true, true, false, true>' (the name bbp_timing reports for the FP32 depolarizing
-    kernels); 'bmps_kernel<double>'; other kernels keep their name."""
+    """'void bbp::(anonymous namespace)::sweep_kernel<false, 6, true, true, false, true, false>(...)' ->
+    'sweep_kernel<6, true, true, false, true>' (FP32 depolarizing kernels; the first template argument true
+    gives 'sweep_kernel_bf16<...>', as _lib.sweep_kernel_name names them); 'bmps_kernel<double>'; other kernels
+    keep their name."""
     import re
-    m = re.search(r"sweep_kernel<float, (\d+(?:, (?:true|false)){4}), false>", name)
+    m = re.search(r"sweep_kernel<(true|false), (\d+(?:, (?:true|false)){4}), false>", name)
     if m:
-        return f"sweep_kernel<{m.group(1)}>"
+        return f"sweep_kernel{'_bf16' if m.group(1) == 'true' else ''}<{m.group(2)}>"
     return "bmps_kernel<double>" if "bmps_kernel<double>" in name else name
 
 
@@ -102,21 +104,65 @@ def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024, target="sweep"):
     return out
 
 
-def cpu_baseline(d, p, block, chi, max_iter):
-    """The FP64 oracle on one syndrome of the same workload, one thread."""
+def _oracle_worker_init():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
+
+
+def _oracle_one(args):
+    """One syndrome of the workload through the FP64 oracle in this worker (one BLAS thread)."""
+    d, p, block, chi, max_iter, index = args
     from threadpoolctl import threadpool_limits
 
     from oracle import blockbp
     from paper_2402_04834_amd import workload
 
-    _, syn = workload.make_batch(d, p, 1, workload="d17")
+    _, syn = workload.make_batch(d, p, 1, workload="d17", start=index)
     with threadpool_limits(1):
         t0 = time.perf_counter()
         blockbp.decode(d, p, syn, block=(block, block), chi=chi, max_iter=max_iter)
-        dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="syndromes/s", cores=1, kind="oracle",
-                sample=f"syndrome 0 of the d={d} p={p} workload, all 4 cosets, {block}x{block} blocks, chi={chi}, "
-                       f"<= {max_iter} iterations with early exit, float64, one thread ({dt:.1f} s)")
+        return time.perf_counter() - t0
+
+
+def host_cores():
+    """Worker count for the CPU baseline: the cores this process may run on, at most 16 (a one-GPU share of
+    the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d, p, block, chi, max_iter):
+    """The FP64 oracle on the host's cores: a process pool of one worker per core (one BLAS thread each), one
+    syndrome of the workload per worker. Must run before anything in this process touches the GPU (the
+    workers are forked)."""
+    import multiprocessing as mp
+
+    cores = host_cores()
+    tasks = [(d, p, block, chi, max_iter, i) for i in range(cores)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_oracle_worker_init) as pool:
+        per = pool.map(_oracle_one, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    return dict(value=cores / wall, unit="syndromes/s", cores=cores, kind="oracle", cpu=cpu_model(),
+                per_core=dict(value=len(per) / sum(per), unit="syndromes/s"),
+                sample=f"syndromes 0..{cores - 1} of the d={d} p={p} workload, one per worker process, all 4 "
+                       f"cosets, {block}x{block} blocks, chi={chi}, <= {max_iter} iterations with early exit, "
+                       f"float64, one BLAS thread per worker; {wall:.1f} s wall")
 
 
 def wilson(k, n, z=1.959964):
@@ -184,8 +230,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", type=int, choices=(0, 1), default=0,
-                    help="0: FP32 products (default); 1: products of BF16-rounded inputs, FP32 sums")
+    ap.add_argument("--no-fp32-comparison", action="store_true",
+                    help="skip the plain-FP32 decode timed beside the headline (precision 1)")
+    ap.add_argument("--precision", type=int, choices=(0, 1), default=1,
+                    help="1 (default): the middle-site contractions on the matrix cores in BF16 with FP32 "
+                         "accumulation, FP32 elsewhere; 0: FP32 throughout")
     ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased", "bmps", "schedule"), default="d17",
                     help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance; warm: "
                          "learned warm start against the uniform start at d=25, p=0.10; biased: d=17 under "
@@ -217,6 +266,10 @@ def main():
     if a.gpus != 1:
         print("bench.py: this decoder runs on one GPU; only --gpus 1 is supported", file=sys.stderr)
         sys.exit(2)
+    # the CPU baseline forks its worker processes, so it runs before anything here touches the GPU
+    cpu = None
+    if a.workload == "d17" and a.block == 6 and not a.no_cpu_baseline:
+        cpu = cpu_baseline(17, 0.10, 6, 32, 20)
 
     import torch
 
@@ -245,8 +298,70 @@ def main():
     errors, syn = workload.make_batch(d, p, a.batch, workload="d17")
     dev = torch.device("cuda:0")
     syn_dev = torch.from_numpy(syn).to(dev)
+    head = d17_leg(a, d, p, block, chi, max_iter, syn_dev, a.precision)
+    other = None if a.no_fp32_comparison or a.precision == 0 else d17_leg(a, d, p, block, chi, max_iter, syn_dev, 0)
+    r = head
+    cls, (dom_ms, dom_launches, dom_flops) = max(r["top"].items(), key=lambda kv: kv[1][0])
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    kname = _lib.sweep_kernel_name(cls, a.precision)
+    all_achieved = r["upd_flops"] / (r["upd_ms"] * 1e-3) / 1e12 if r["upd_ms"] > 0 else 0.0
+    tune = r["tune"]
+    precision_text = ("FP32 products and sums",
+                      "the contractions with the side messages' middle sites on the matrix cores in BF16 "
+                      "(v_mfma_f32_4x4x4_16b_bf16) with FP32 accumulation, the other products FP32, "
+                      "FP64 convergence distance and log-likelihoods")[a.precision]
+    line = dict(
+        metric=METRIC, value=r["value"], unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=1e3 * r["elapsed"] / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=("f32", "bf16/f32")[a.precision], data="synthetic",
+        config=dict(workload=f"planar surface code d={d}, depolarizing p={p}, {a.batch} seeded syndromes, "
+                             f"{block}x{block} blocks, chi={chi}, <= {max_iter} BP iterations, early exit",
+                    d=d, p=p, batch=a.batch, block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
+                    damping=0.1, precision=precision_text, parallelism="single GPU"),
+        roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic(kname),
+                      kernel=kname, avg_launch_ms=dom_ms / max(dom_launches, 1),
+                      flops_per_launch=dom_flops / max(dom_launches, 1), launches=dom_launches,
+                      all_sweep_kernels=dict(achieved=all_achieved, frac=all_achieved / PEAK_FP32_TFLOPS,
+                                             ms_per_step=r["upd_ms"] / a.steps,
+                                             launches_per_step=r["launches"] / a.steps)),
+        kernel_ms_per_step=dict(update=r["upd_ms"] / a.steps, bethe=r["bethe_ms"] / a.steps,
+                                other=r["other_ms"] / a.steps),
+        mean_iterations_per_coset=r["out"]["iters"].double().mean().item(),
+        launch_tuning=dict(order=("sweep-major", "job-major")[tune.order], timed_streams=tune.streams,
+                           timed_as=("eager launches" if r["events_in_timed"] else "one HIP graph per step"),
+                           tuning_decode_ms=tune.ms,
+                           roofline_measured_on=("the timed decodes" if r["events_in_timed"] else
+                                                 f"{a.steps} separate single-stream decodes")),
+        plan=dict(messages_per_coset=r["info"].num_messages, exact_sweeps=bool(r["info"].exact_sweeps),
+                  max_boundary_rank=r["info"].max_boundary_rank),
+        agreement=agreement(r["out"], a.batch, errors, d) if block == 6 else None,
+    )
+    if other is not None:
+        ocls, (oms, ol, ofl) = max(other["top"].items(), key=lambda kv: kv[1][0])
+        line["fp32_comparison"] = dict(
+            value=other["value"], unit="syndromes/s", ms_per_step=1e3 * other["elapsed"] / a.steps,
+            speedup=r["value"] / other["value"], kernel=_lib.sweep_kernel_name(ocls, 0),
+            avg_launch_ms=oms / max(ol, 1), achieved_tflops=ofl / (oms * 1e-3) / 1e12 if oms > 0 else 0.0,
+            mean_iterations_per_coset=other["out"]["iters"].double().mean().item(),
+            agreement=agreement(other["out"], a.batch, errors, d) if block == 6 else None,
+            note="the same workload and launch set-up in plain FP32 (precision 0), timed right after the headline")
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def d17_leg(a, d, p, block, chi, max_iter, syn_dev, precision):
+    """Autotune, warm up and time a.steps decodes of the d17 batch at `precision`; kernel rates from HIP events
+    (in the timed decodes when the tuned variant is one stream, else from as many single-stream decodes after
+    the timed region)."""
+    import torch
+
+    import paper_2402_04834_amd as bbp
+
+    dev = syn_dev.device
     opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2, damping=0.1,
-                            precision=a.precision)
+                            precision=precision)
     info = bbp.plan_query(d, opts)
     ws = torch.empty(bbp.workspace_size(d, a.batch, opts), dtype=torch.uint8, device=dev)
     # The library's autotuner picks the launch variant for (d, blocks, chi) on this batch (untimed set-up), and
@@ -264,24 +379,22 @@ def main():
     timed_opts, timed_stream = opts, None
     if not events_in_timed:
         timed_opts = bbp.default_opts(block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
-                                      damping=0.1, precision=a.precision, graph=1)
+                                      damping=0.1, precision=precision, graph=1)
         timed_stream = torch.cuda.Stream()
     out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream)
     for _ in range(a.warmup):
         out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream, out=out)
     torch.cuda.synchronize()
-    upd_ms = upd_flops = bethe_ms = other_ms = 0.0
-    launches = 0
-    top = {}
+    r = dict(upd_ms=0.0, upd_flops=0.0, bethe_ms=0.0, other_ms=0.0, launches=0, top={}, tune=tune, info=info,
+             events_in_timed=events_in_timed)
 
     def account(tm):
-        nonlocal upd_ms, upd_flops, bethe_ms, other_ms, launches
-        upd_ms += tm.update_ms
-        upd_flops += tm.update_flops
-        bethe_ms += tm.bethe_ms
-        other_ms += tm.other_ms
-        launches += tm.update_launches
-        t = top.setdefault(tm.top_class, [0.0, 0, 0.0])
+        r["upd_ms"] += tm.update_ms
+        r["upd_flops"] += tm.update_flops
+        r["bethe_ms"] += tm.bethe_ms
+        r["other_ms"] += tm.other_ms
+        r["launches"] += tm.update_launches
+        t = r["top"].setdefault(tm.top_class, [0.0, 0, 0.0])
         t[0] += tm.top_ms
         t[1] += tm.top_launches
         t[2] += tm.top_flops
@@ -294,8 +407,8 @@ def main():
         else:
             out = bbp.decode_device(d, p, syn_dev, timed_opts, workspace=ws, stream=timed_stream, out=out)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = a.batch * a.steps / elapsed
+    r["elapsed"] = time.perf_counter() - t0
+    r["value"] = a.batch * a.steps / r["elapsed"]
     if events_in_timed:
         out = res
     else:
@@ -304,41 +417,9 @@ def main():
             res = bbp.decode_device(d, p, syn_dev, opts, workspace=ws, timing=True)
             account(res["timing"])
         torch.cuda.synchronize()
-    # dominant kernel: the sweep instantiation with the largest summed time
-    cls, (dom_ms, dom_launches, dom_flops) = max(top.items(), key=lambda kv: kv[1][0])
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-    kname = _lib.sweep_kernel_name(cls)
-    all_achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
-    iters = out["iters"].double().mean().item()
-    line = dict(
-        metric=METRIC, value=value, unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
-        ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype=("f32", "bf16-in/f32-acc")[a.precision], data="synthetic",
-        config=dict(workload=f"planar surface code d={d}, depolarizing p={p}, {a.batch} seeded syndromes, "
-                             f"{block}x{block} blocks, chi={chi}, <= {max_iter} BP iterations, early exit",
-                    d=d, p=p, batch=a.batch, block=block, chi=chi, max_iter=max_iter, delta0=1e-4, delta1=1e-2,
-                    damping=0.1, precision=("FP32 products", "BF16-rounded inputs, FP32 sums")[a.precision],
-                    parallelism="single GPU"),
-        roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic(kname),
-                      kernel=kname, avg_launch_ms=dom_ms / max(dom_launches, 1),
-                      flops_per_launch=dom_flops / max(dom_launches, 1), launches=dom_launches,
-                      all_sweep_kernels=dict(achieved=all_achieved, frac=all_achieved / PEAK_FP32_TFLOPS,
-                                             ms_per_step=upd_ms / a.steps, launches_per_step=launches / a.steps)),
-        kernel_ms_per_step=dict(update=upd_ms / a.steps, bethe=bethe_ms / a.steps, other=other_ms / a.steps),
-        mean_iterations_per_coset=iters,
-        launch_tuning=dict(order=("sweep-major", "job-major")[tune.order], timed_streams=tune.streams,
-                           timed_as=("eager launches" if events_in_timed else "one HIP graph per step"),
-                           tuning_decode_ms=tune.ms,
-                           roofline_measured_on=("the timed decodes" if events_in_timed else
-                                                 f"{a.steps} separate single-stream decodes")),
-        plan=dict(messages_per_coset=info.num_messages, exact_sweeps=bool(info.exact_sweeps),
-                  max_boundary_rank=info.max_boundary_rank),
-        agreement=agreement(out, a.batch, errors, d) if block == 6 else None,
-    )
-    if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d, p, block, chi, max_iter)
-    print(json.dumps(line), flush=True)
+    r["out"] = out
+    del ws
+    return r
 
 
 def mixed_main(a):

@@ -45,7 +45,10 @@ typedef struct bbp_opts {
   double damping;       /* eta of remark 7: m <- (1-eta) m_new + eta m_old; 0 <= eta < 1 */
   int32_t rule;         /* 0 = rule of Alg. 1 / remark 6, 1 = plain argmax of the Bethe estimates */
   int32_t fixed_iters;  /* 1 = always run max_iter iterations (no early exit) */
-  int32_t precision;    /* 0 = FP32 block contractions (FP64 convergence distance and Bethe sums) */
+  int32_t precision;    /* 0 = FP32 block contractions; 1 = the contractions with the side messages' middle sites
+                           that run on the matrix cores (sweeps of 5 and 6 steps) take BF16 operands with FP32
+                           accumulation, the qubit tensor of an adjacent end site folded into the message operand;
+                           every other product stays FP32. Both: FP64 convergence distance and Bethe sums */
   int32_t graph;        /* 1 = capture the decode of a call into a HIP graph on first use and replay it on
                            later calls with identical arguments (pointers, sizes, options, stream); needs a
                            stream other than the default stream; ignored when timing is requested. At most

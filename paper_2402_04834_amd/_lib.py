@@ -59,11 +59,12 @@ class bbp_timing(C.Structure):
     ]
 
 
-def sweep_kernel_name(cls: int) -> str:
-    """Kernel instantiation of a sweep class code (see bbp_timing.top_class)."""
+def sweep_kernel_name(cls: int, precision: int = 0) -> str:
+    """Kernel instantiation of a sweep class code (see bbp_timing.top_class): sweep_kernel<...> for FP32,
+    sweep_kernel_bf16<...> for the BF16 matrix-core variant of precision mode 1."""
     q00, single, bot, top, kt = cls & 1, (cls >> 1) & 1, (cls >> 2) & 1, (cls >> 3) & 1, (cls >> 4) + 1
     b = lambda v: "true" if v else "false"
-    return f"sweep_kernel<{kt}, {b(top)}, {b(bot)}, {b(single)}, {b(q00)}>"
+    return f"sweep_kernel{'_bf16' if precision else ''}<{kt}, {b(top)}, {b(bot)}, {b(single)}, {b(q00)}>"
 
 
 # exported symbol -> (restype, argtypes)

@@ -285,7 +285,7 @@ int validate(int32_t d, const bbp_opts* o) {
   if (!(o->delta0 <= o->delta1)) return fail(BBP_EINVAL, "delta0 must not exceed delta1");
   if (!(o->damping >= 0.0 && o->damping < 1.0)) return fail(BBP_EINVAL, "damping must be in [0, 1)");
   if (o->rule != 0 && o->rule != 1) return fail(BBP_EINVAL, "rule must be 0 or 1");
-  if (o->precision != 0 && o->precision != 1) return fail(BBP_EINVAL, "precision must be 0 (FP32) or 1 (BF16 inputs)");
+  if (o->precision != 0 && o->precision != 1) return fail(BBP_EINVAL, "precision must be 0 (FP32) or 1 (BF16 matrix-core contractions)");
   if (o->graph != 0 && o->graph != 1) return fail(BBP_EINVAL, "graph must be 0 or 1");
   if (!(o->gate >= 0.0 && o->gate < INFINITY)) return fail(BBP_EINVAL, "gate must be finite and >= 0");
   return BBP_OK;

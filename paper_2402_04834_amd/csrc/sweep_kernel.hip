@@ -30,10 +30,10 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // entry index of a K-leg dense message with its legs in reverse order
 __device__ __forceinline__ int reverse_legs(int idx, int K) { return (int)(__brev((unsigned)idx) >> (32 - K)); }
 
-// V = float: FP32 products (precision 0); V = bfin: products of BF16-rounded inputs, FP32 sums (precision 1).
-// BIASED: some group of the launch has biased Pauli noise (otherwise the depolarizing entries are compiled
-// in and the biased selection is removed).
-template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, bool BIASED>
+// BF: the contractions with the side messages' middle sites take BF16 operands on the matrix cores (precision
+// mode 1; FP32 everywhere else), else FP32 throughout (precision 0). BIASED: some group of the launch has
+// biased Pauli noise (otherwise the depolarizing entries are compiled in and the biased selection is removed).
+template <bool BF, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, bool BIASED>
 __global__ __launch_bounds__(SWEEP_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BBP_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs a) {
   const int lane = (int)__lane_id();
@@ -64,6 +64,7 @@ void sweep_kernel(SweepArgs a) {
       return;
     }
   }
+  using V = float;
   const int L = 2 * G.d - 1, kp = s.kp, H = 1 << kp;
   const bool valid = lane < H;
 
@@ -113,7 +114,7 @@ void sweep_kernel(SweepArgs a) {
     x0 = ((lane & ~ia) == 0) ? 1.0f : 0.0f;
   }
 
-  float fin = wave::tof(wave::sweep<V, KT, TOP, BOT, SINGLE, Q00>(V{x0}, c));
+  float fin = wave::sweep<V, KT, TOP, BOT, SINGLE, Q00, BF>(x0, c);
   fin = valid ? fin : 0.0f;
 
   if (a.mode == 1) {
@@ -144,15 +145,15 @@ void sweep_kernel(SweepArgs a) {
 #define BBP_CAT(a, b) BBP_CAT2(a, b)
 
 namespace {
-// variants 0..47: bit 4 BF16-input products, bit 5 biased noise (FP32 products only)
+// variants 0..47: bit 4 BF16 middle-site contractions (precision 1), bit 5 biased noise (FP32 only)
 template <int V>
 void launch_variant(dim3 grid, hipStream_t st, const SweepArgs& a) {
   constexpr bool TOP = (V >> 3) & 1, BOT = (V >> 2) & 1, SINGLE = (V >> 1) & 1, Q00 = V & 1;
   constexpr bool BF = (V >> 4) & 1, BIASED = (V >> 5) & 1;
   if constexpr (BF)
-    sweep_kernel<wave::bfin, BBP_KT, TOP, BOT, SINGLE, Q00, false><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+    sweep_kernel<true, BBP_KT, TOP, BOT, SINGLE, Q00, false><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
   else
-    sweep_kernel<float, BBP_KT, TOP, BOT, SINGLE, Q00, BIASED><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
+    sweep_kernel<false, BBP_KT, TOP, BOT, SINGLE, Q00, BIASED><<<grid, dim3(SWEEP_WAVES * 64), 0, st>>>(a);
 }
 
 template <int... I>

@@ -32,6 +32,16 @@
 // its own state value; each v_mfma_f32_4x4x1f32 is one step a of the sum for all four new cap values,
 // which land in the lane's four accumulator registers. FP32 products and FP32 accumulation throughout.
 //
+// BF16 variant (BF = true, precision mode 1): these middle-site contractions take BF16 operands on
+// v_mfma_f32_4x4x4_16b_bf16 (K = 4 terms per instruction, FP32 accumulation). Where the end site is a
+// qubit, its transform is folded into the message operand, A[n][(a, own / partner)] = sum_v m(a, v, n) c_v,
+// with B the lane's state value and its partner's: the coefficients c_v depend only on the neighbouring
+// check bit, a lane bit >= 2 when kp >= 3, so they are the same for the four lanes of an MFMA block (for
+// kp < 3 the transform stays on the VALU and only the message contraction is BF16). Every other product
+// -- the qubit transforms of the other columns, the routing caps -- stays FP32: on the VALU a BF16 dot
+// product (v_dot2c_f32_bf16) needs its pair packed and its accumulator zeroed, three instructions where the
+// FP32 transform takes two, so BF16 pays only on the matrix cores.
+//
 // Scaling: after every second column (odd steps, never the last) the state is rescaled by an exact power of
 // two chosen from its norm (the exponent is accumulated), and the factor is folded into the first qubit
 // transform of the next column, so normalisation costs one multiply-add per state entry and a wave
@@ -57,18 +67,20 @@ __device__ __forceinline__ void sfor(F&& f) {
   sfor_(f, std::make_integer_sequence<int, N>{});
 }
 
-// Value type of the BF16-input variant (precision mode 1): every product rounds both of its inputs to
-// bfloat16 (round to nearest even) and forms the product exactly in FP32; sums accumulate in FP32. The
-// state itself stays FP32 between operations.
-struct bfin {
-  float v;
-};
-__device__ __forceinline__ float bfr(float x) { return (float)(__bf16)x; }
-__device__ __forceinline__ bfin operator*(bfin a, bfin b) { return bfin{bfr(a.v) * bfr(b.v)}; }
-__device__ __forceinline__ bfin operator+(bfin a, bfin b) { return bfin{a.v + b.v}; }
-__device__ __forceinline__ bfin& operator+=(bfin& a, bfin b) {
-  a.v += b.v;
-  return a;
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+// (lo, hi) rounded to BF16 (round to nearest even) in one register: one v_cvt_pk_bf16_f32. Converting the
+// pair as a vector is what makes the compiler emit the two-operand form (element-wise casts become two
+// conversions and a v_perm), and it keeps the instruction visible to the compiler's MFMA hazard checks.
+__device__ __forceinline__ unsigned cvt_pk_bf16(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){lo, hi}, bf2));
+}
+// (a, b, c, d) as the four BF16 values of a 4x4x4 MFMA operand, in k order
+__device__ __forceinline__ bf4 pk4(float a, float b, float c, float d) {
+  const u2 w = {cvt_pk_bf16(a, b), cvt_pk_bf16(c, d)};
+  return __builtin_bit_cast(bf4, w);
 }
 
 template <class V>
@@ -78,10 +90,8 @@ __device__ __forceinline__ V vfrom(int i) { return __builtin_bit_cast(V, i); }
 template <class V>
 __device__ __forceinline__ V splat(float x) { return V{x}; }
 __device__ __forceinline__ float tof(float x) { return x; }
-__device__ __forceinline__ float tof(bfin x) { return x.v; }
 // a * b + c, fused
 __device__ __forceinline__ float fmav(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ bfin fmav(bfin a, bfin b, bfin c) { return bfin{__builtin_fmaf(bfr(a.v), bfr(b.v), c.v)}; }
 
 // value of x in lane (lane ^ M)
 template <int M, class V>
@@ -114,6 +124,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // One rank-1 step of 16 independent 4x4 products (v_mfma_f32_4x4x1f32): lanes 4b..4b+3 form block b;
 // lane 4b+i supplies a (row i), lane 4b+j supplies b (column j) and holds acc[i] = D[i][j].
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 acc) { return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 0, 0, 0); }
+// The same 16 blocks with K = 4 in BF16 (v_mfma_f32_4x4x4_16b_bf16): lane 4b+i supplies row i of A as four
+// BF16 values (k = 0..3), lane 4b+j column j of B, and holds acc[i] = D[i][j] in FP32.
+__device__ __forceinline__ f4 mfma4b(bf4 a, bf4 b, f4 acc) { return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, acc, 0, 0, 0); }
 
 __device__ __forceinline__ float wave_sum(float v) {
   sfor<6>([&](auto k) { v += xchg<(1 << k)>(v); });
@@ -180,7 +193,7 @@ __device__ __forceinline__ auto phi2(G0&& g0, G1&& g1, Msg&& m) {
 }
 
 // ------------------------------------------------------------------------------------- sweep context
-// V = float (FP32 products) or bfin (BF16-input products).
+// V = float: the value type of the state.
 template <class V>
 struct Ctx {
   int h;                // lane = crossing-bond configuration (lane-bit layout above)
@@ -278,7 +291,7 @@ __device__ __forceinline__ void project_out_edge(V (&Y)[N], const Ctx<V>& c, int
 }
 
 // --------------------------------------------------------------------------------- column, kp >= 2
-template <class V, int KT, bool TOP, bool BOT, bool Q00, int T>
+template <class V, int KT, bool TOP, bool BOT, bool Q00, bool BF, int T>
 __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO],
                                              V (&Y)[Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN], Ctx<V>& c,
                                              V sc) {
@@ -306,7 +319,50 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
     const QC<V> q0 = qcoefs(c, T, 0, swap, vo, ho, in_abs, out_abs, sc0);
     QC<V> q1 = qcoefs(c, T, 0, swap, vo ^ 1, ho, in_abs, out_abs, sc0);
     if (c.geo & GEO_TOP_EDGE) q1.cs = q1.cf = splat<V>(0.0f);
-    if constexpr (std::is_same<V, float>::value && CT::kind == K_EQ && PTN == 4) {
+    if constexpr (BF && CT::kind == K_EQ && PTN == 4) {
+      // T is the middle step (never the first or last), so no edge absorption depends on the lane's own bit
+      static_assert(PTO % 2 == 0, "pairs of old cap values per MFMA");
+      if (kp >= 3) {
+        // coefficients uniform over each block of four lanes: fold them into A, B = (x, x') per old cap value
+        bf4 A[PTO / 2];
+        sfor<PTO / 2>([&](auto k) {
+          float ao[2], ap[2];
+          sfor<2>([&](auto u) {
+            const float m0 = lane_get(c.mtv, CT::idx(2 * k + u, 0, 0) + (h & 3));
+            const float m1 = lane_get(c.mtv, CT::idx(2 * k + u, 1, 0) + (h & 3));
+            ao[u] = m0 * q0.cs + m1 * q1.cs;
+            ap[u] = m0 * q0.cf + m1 * q1.cf;
+          });
+          A[k] = pk4(ao[0], ap[0], ao[1], ap[1]);
+        });
+        sfor<PSO>([&](auto s) {
+          f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          sfor<PTO / 2>([&](auto k) {
+            const float x0 = X[(2 * k) * PSO + s], x1 = X[(2 * k + 1) * PSO + s];
+            acc = mfma4b(A[k], pk4(x0, xchg<1>(x0), x1, xchg<1>(x1)), acc);
+          });
+          sfor<4>([&](auto n) { Z[n * PSO + s] = acc[(int)n]; });
+        });
+      } else {
+        // FP32 transform per lane, BF16 contraction with the message: K = (a, v) for two old cap values
+        bf4 A[PTO / 2];
+        sfor<PTO / 2>([&](auto k) {
+          A[k] = pk4(lane_get(c.mtv, CT::idx(2 * k, 0, 0) + (h & 3)), lane_get(c.mtv, CT::idx(2 * k, 1, 0) + (h & 3)),
+                     lane_get(c.mtv, CT::idx(2 * k + 1, 0, 0) + (h & 3)),
+                     lane_get(c.mtv, CT::idx(2 * k + 1, 1, 0) + (h & 3)));
+        });
+        sfor<PSO>([&](auto s) {
+          f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          sfor<PTO / 2>([&](auto k) {
+            const V x0 = X[(2 * k) * PSO + s], xf0 = xchg<1>(x0);
+            const V x1 = X[(2 * k + 1) * PSO + s], xf1 = xchg<1>(x1);
+            acc = mfma4b(A[k], pk4(q0.cs * x0 + q0.cf * xf0, q1.cs * x0 + q1.cf * xf0, q0.cs * x1 + q0.cf * xf1,
+                                   q1.cs * x1 + q1.cf * xf1), acc);
+          });
+          sfor<4>([&](auto n) { Z[n * PSO + s] = acc[(int)n]; });
+        });
+      }
+    } else if constexpr (CT::kind == K_EQ && PTN == 4) {
       float mA[PTO][2];
       sfor<PTO>([&](auto a) {
         mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
@@ -351,7 +407,30 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
     }
   } else {
     const bool v1 = !(c.geo & GEO_TOP_EDGE) && bit(h, 0);
-    if constexpr (std::is_same<V, float>::value && CT::kind == K_EQ && PTN == 4) {
+    if constexpr (BF && CT::kind == K_EQ && PTN == 4) {
+      // K = four old cap values per MFMA, one accumulator per value of the emitted bond (the check's bit v1)
+      static_assert(PTO % 4 == 0, "quads of old cap values per MFMA");
+      bf4 A0[PTO / 4], A1[PTO / 4];
+      sfor<PTO / 4>([&](auto k) {
+        float m[2][4];
+        sfor<4>([&](auto u) {
+          m[0][u] = lane_get(c.mtv, CT::idx(4 * k + u, 0, 0) + (h & 3));
+          m[1][u] = lane_get(c.mtv, CT::idx(4 * k + u, 1, 0) + (h & 3));
+        });
+        A0[k] = pk4(m[0][0], m[0][1], m[0][2], m[0][3]);
+        A1[k] = pk4(m[1][0], m[1][1], m[1][2], m[1][3]);
+      });
+      sfor<PSO>([&](auto s) {
+        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PTO / 4>([&](auto k) {
+          const bf4 B = pk4(X[(4 * k) * PSO + s], X[(4 * k + 1) * PSO + s], X[(4 * k + 2) * PSO + s],
+                            X[(4 * k + 3) * PSO + s]);
+          acc0 = mfma4b(A0[k], B, acc0);
+          acc1 = mfma4b(A1[k], B, acc1);
+        });
+        sfor<4>([&](auto n) { Z[n * PSO + s] = v1 ? acc1[(int)n] : acc0[(int)n]; });
+      });
+    } else if constexpr (CT::kind == K_EQ && PTN == 4) {
       float mA[PTO][2];
       sfor<PTO>([&](auto a) {
         mA[a][0] = lane_get(c.mtv, CT::idx(a, 0, 0) + (h & 3));
@@ -417,7 +496,48 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
     const QC<V> q0 = qcoefs(c, T, kp - 1, swap, vi, ho, in_abs, out_abs, scl);
     QC<V> q1 = qcoefs(c, T, kp - 1, swap, vi ^ 1, ho, in_abs, out_abs, scl);
     if (c.geo & GEO_BOT_EDGE) q1.cs = q1.cf = splat<V>(0.0f);
-    if constexpr (std::is_same<V, float>::value && CB::kind == K_EQ && PSN == 4) {
+    if constexpr (BF && CB::kind == K_EQ && PSN == 4) {
+      // as for the top cap; with kp >= 3 the coefficients depend on lane bit kp-1 >= 2 only (vi)
+      static_assert(PSO % 2 == 0, "pairs of old cap values per MFMA");
+      if (kp >= 3) {
+        bf4 A[PSO / 2];
+        sfor<PSO / 2>([&](auto k) {
+          float ao[2], ap[2];
+          sfor<2>([&](auto u) {
+            const float m0 = lane_get(c.mbv, CB::idx(2 * k + u, 0, 0) + (h & 3));
+            const float m1 = lane_get(c.mbv, CB::idx(2 * k + u, 1, 0) + (h & 3));
+            ao[u] = m0 * q0.cs + m1 * q1.cs;
+            ap[u] = m0 * q0.cf + m1 * q1.cf;
+          });
+          A[k] = pk4(ao[0], ap[0], ao[1], ap[1]);
+        });
+        sfor<PTN>([&](auto n) {
+          f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          sfor<PSO / 2>([&](auto k) {
+            const float z0 = Z[n * PSO + 2 * k], z1 = Z[n * PSO + 2 * k + 1];
+            acc = mfma4b(A[k], pk4(z0, xchg<2>(z0), z1, xchg<2>(z1)), acc);
+          });
+          sfor<4>([&](auto sp) { Y[n * PSN + sp] = acc[(int)sp]; });
+        });
+      } else {
+        bf4 A[PSO / 2];
+        sfor<PSO / 2>([&](auto k) {
+          A[k] = pk4(lane_get(c.mbv, CB::idx(2 * k, 0, 0) + (h & 3)), lane_get(c.mbv, CB::idx(2 * k, 1, 0) + (h & 3)),
+                     lane_get(c.mbv, CB::idx(2 * k + 1, 0, 0) + (h & 3)),
+                     lane_get(c.mbv, CB::idx(2 * k + 1, 1, 0) + (h & 3)));
+        });
+        sfor<PTN>([&](auto n) {
+          f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          sfor<PSO / 2>([&](auto k) {
+            const V z0 = Z[n * PSO + 2 * k], zf0 = xchg<2>(z0);
+            const V z1 = Z[n * PSO + 2 * k + 1], zf1 = xchg<2>(z1);
+            acc = mfma4b(A[k], pk4(q0.cs * z0 + q0.cf * zf0, q1.cs * z0 + q1.cf * zf0, q0.cs * z1 + q0.cf * zf1,
+                                   q1.cs * z1 + q1.cf * zf1), acc);
+          });
+          sfor<4>([&](auto sp) { Y[n * PSN + sp] = acc[(int)sp]; });
+        });
+      }
+    } else if constexpr (CB::kind == K_EQ && PSN == 4) {
       float mB[PSO][2];
       sfor<PSO>([&](auto b) {
         mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
@@ -460,7 +580,28 @@ __device__ __forceinline__ void column_multi(const V (&X)[Cap<TOP, KT, T>::PO * 
     }
   } else {
     const bool v1 = !(c.geo & GEO_BOT_EDGE) && bit(h, 1);
-    if constexpr (std::is_same<V, float>::value && CB::kind == K_EQ && PSN == 4) {
+    if constexpr (BF && CB::kind == K_EQ && PSN == 4) {
+      static_assert(PSO % 4 == 0, "quads of old cap values per MFMA");
+      bf4 A0[PSO / 4], A1[PSO / 4];
+      sfor<PSO / 4>([&](auto k) {
+        float m[2][4];
+        sfor<4>([&](auto u) {
+          m[0][u] = lane_get(c.mbv, CB::idx(4 * k + u, 0, 0) + (h & 3));
+          m[1][u] = lane_get(c.mbv, CB::idx(4 * k + u, 1, 0) + (h & 3));
+        });
+        A0[k] = pk4(m[0][0], m[0][1], m[0][2], m[0][3]);
+        A1[k] = pk4(m[1][0], m[1][1], m[1][2], m[1][3]);
+      });
+      sfor<PTN>([&](auto n) {
+        f4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        sfor<PSO / 4>([&](auto k) {
+          const bf4 B = pk4(Z[n * PSO + 4 * k], Z[n * PSO + 4 * k + 1], Z[n * PSO + 4 * k + 2], Z[n * PSO + 4 * k + 3]);
+          acc0 = mfma4b(A0[k], B, acc0);
+          acc1 = mfma4b(A1[k], B, acc1);
+        });
+        sfor<4>([&](auto sp) { Y[n * PSN + sp] = v1 ? acc1[(int)sp] : acc0[(int)sp]; });
+      });
+    } else if constexpr (CB::kind == K_EQ && PSN == 4) {
       float mB[PSO][2];
       sfor<PSO>([&](auto b) {
         mB[b][0] = lane_get(c.mbv, CB::idx(b, 0, 0) + (h & 3));
@@ -580,19 +721,19 @@ __device__ __forceinline__ V pow2_scale(float ss, Ctx<V>& c) {
 }
 
 // Absorb columns T .. KT-1 into the state X (pending scale sc); returns the final state of this lane.
-template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, int T>
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, bool BF, int T>
 __device__ __forceinline__ V run(const V (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT, T>::PO], Ctx<V>& c, V sc) {
   constexpr int NY = Cap<TOP, KT, T>::PN * Cap<BOT, KT, T>::PN;
   V Y[NY];
   if constexpr (SINGLE) column_single<V, KT, TOP, BOT, Q00, T>(X, Y, c, sc);
-  else column_multi<V, KT, TOP, BOT, Q00, T>(X, Y, c, sc);
+  else column_multi<V, KT, TOP, BOT, Q00, BF, T>(X, Y, c, sc);
   if constexpr (T + 1 < KT) {
     if constexpr (T & 1) {
       float ss = 0.0f;
       sfor<NY>([&](auto e) { ss += tof(Y[e]) * tof(Y[e]); });
-      return run<V, KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
+      return run<V, KT, TOP, BOT, SINGLE, Q00, BF, T + 1>(Y, c, pow2_scale(wave_sum(ss), c));
     } else {
-      return run<V, KT, TOP, BOT, SINGLE, Q00, T + 1>(Y, c, splat<V>(1.0f));
+      return run<V, KT, TOP, BOT, SINGLE, Q00, BF, T + 1>(Y, c, splat<V>(1.0f));
     }
   } else {
     return Y[0];
@@ -600,11 +741,11 @@ __device__ __forceinline__ V run(const V (&X)[Cap<TOP, KT, T>::PO * Cap<BOT, KT,
 }
 
 // The whole sweep from the entering state x0 (one value per lane). SINGLE: one position across
-// (kp == 1); Q00: the first site of the first column is a qubit.
-template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00>
+// (kp == 1); Q00: the first site of the first column is a qubit; BF: the middle-site contractions in BF16.
+template <class V, int KT, bool TOP, bool BOT, bool SINGLE, bool Q00, bool BF>
 __device__ __forceinline__ V sweep(V x0, Ctx<V>& c) {
   const V X[1] = {x0};
-  return run<V, KT, TOP, BOT, SINGLE, Q00, 0>(X, c, splat<V>(1.0f));
+  return run<V, KT, TOP, BOT, SINGLE, Q00, BF, 0>(X, c, splat<V>(1.0f));
 }
 
 }  // namespace wave

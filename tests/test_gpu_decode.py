@@ -199,14 +199,15 @@ def test_d5_configuration_against_oracle(dev):
 @pytest.mark.parametrize("tag", ["p005", "p010", "p015"])
 def test_d11_configuration_against_oracle_fixture(dev, tag):
     """Plain FP32 blockBP at d=11 (p 0.05, 0.10, 0.15; 1024 syndromes each, 4x4 blocks, chi=16, 20
-    iterations, damping 0.5): the whole batch is decoded, the first 48 syndromes are checked against the
-    committed oracle fixture (tests/golden/d11_<p>_k4_chi16_eta05.json, from oracle/ only)."""
+    iterations, damping 0.5): the whole batch is decoded and every syndrome is checked against the committed
+    oracle fixture (tests/golden/d11_<p>_k4_chi16_eta05.json, all 1024 syndromes, from oracle/ only)."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"d11_{tag}_k4_chi16_eta05.json")
     g = json.load(open(path))
     meta = g["meta"]
     assert (meta["d"], meta["block"], meta["chi"], meta["max_iter"], meta["eta"]) == (11, 4, 16, 20, 0.5)
+    assert sorted(r["index"] for r in g["records"]) == list(range(1024))
     _say(f"[d=11] p={meta['p']} batch=1024, {len(g['records'])} oracle records")
     _, syn = workload.make_batch(11, meta["p"], 1024, workload=meta["workload"], p_index=meta["p_index"])
     got = _gpu_decode(dev, 11, meta["p"], syn, messages=False, block=4, chi=16, max_iter=20,
@@ -228,12 +229,12 @@ def test_d11_configuration_against_oracle_fixture(dev, tag):
 
 @pytest.mark.parametrize("d,p,k,chi,iters,count", [(5, 0.10, 3, 4, 10, 16), (7, 0.08, 6, 32, 5, 6), (9, 0.10, 6, 32, 4, 4)])
 def test_bf16_input_precision_against_oracle(dev, d, p, k, chi, iters, count):
-    """Precision mode 1 (every product takes BF16-rounded inputs, FP32 sums). Bound: each of the n qubit
-    factors and message entries of a coset's estimate enters through inputs rounded to 8 significant bits
-    (relative error <= 2^-8), two per product, so |d ln Z| <= n 2^-7 (+0.05 for the messages' own rounding);
-    the rounding of
-    the noise entries biases all four cosets alike and cancels in their differences, which are held to the
-    same bound (rather than twice it), and decisions must agree wherever the oracle's margin exceeds it."""
+    """Precision mode 1 (BF16 operands at the middle-site contractions on the matrix cores, FP32 elsewhere) in
+    fixed-iteration mode. Bound: no more than the n qubit factors and message entries of a coset's estimate
+    can enter through operands rounded to 8 significant bits (relative error <= 2^-8), two per product, so
+    |d ln Z| <= n 2^-7 (+0.05 for the messages' own rounding); coset differences are held to the same bound
+    and decisions must agree wherever the oracle's margin exceeds it. (d=5 with 3x3 blocks has no
+    middle-site contraction on the matrix cores: there mode 1 is FP32.)"""
     _say(f"[bf16 inputs] d={d} k={k} chi={chi} iters={iters} count={count}")
     _, syn = workload.make_batch(d, p, count, workload="test", p_index=40 + d)
     ref = blockbp.decode(d, p, syn, block=(k, k), chi=chi, max_iter=iters, fixed_iters=True)
@@ -247,6 +248,54 @@ def test_bf16_input_precision_against_oracle(dev, d, p, k, chi, iters, count):
     srt = np.sort(ref["loglik"], axis=1)
     clear = (srt[:, -1] - srt[:, -2]) > 0.2 * tol
     np.testing.assert_array_equal(got["coset"][clear], ref["coset"][clear])
+
+
+def test_bf16_d17_full_fixture(dev):
+    """Precision mode 1 at the benchmark's size (d=17, p=0.10, 4096 syndromes, 6x6 blocks, chi 32, <= 20
+    iterations with early exit) against the FP64 oracle fixture. In this mode BF16 enters only at the
+    contractions with the side messages' middle sites (one per cap per sweep): each operand there is rounded
+    to 8 significant bits (relative error <= 2^-8), so a product is within 2^-7 and, all terms being
+    non-negative, so is each contraction; a sweep with two caps is within 2^-6, entry by entry. At a BP fixed
+    point the Bethe estimate is stationary in the messages, so where both runs end at the same fixed point a
+    coset's estimate moves by at most the closing sweeps' and overlaps' own errors: |d ln Z| <= (blocks +
+    edges) 2^-6 (1.5 nats at d=17). That holds for every coset converged on both sides within 6 nats of its
+    syndrome's best coset (the ones a decision can turn on). A coset still drifting slowly when its distance
+    first falls below delta0 may stop at another point of its drift (seen far below the best coset); such
+    cosets further down must stay more than twice the bound below the GPU's best, so that no decision can
+    turn on them. Decisions must be equal wherever the oracle's margin exceeds twice the bound; the counts
+    and error quantiles are printed."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "d17_p010_k6_chi32.json")
+    g = json.load(open(path))
+    meta = g["meta"]
+    _say(f"[bf16 full size] d=17 batch=4096 precision 1, {len(g['records'])} oracle records")
+    _, syn = workload.make_batch(17, meta["p"], 4096, workload=meta["workload"], p_index=meta["p_index"])
+    got = _gpu_decode(dev, 17, meta["p"], syn, messages=False, block=6, chi=32, max_iter=20,
+                      damping=meta["eta"], delta0=meta["delta0"], delta1=meta["delta1"], precision=1)
+    idx = np.array([r["index"] for r in g["records"]])
+    ref_ll = np.array([r["loglik"] for r in g["records"]])
+    ref_dl = np.array([r["delta"] for r in g["records"]])
+    ref_cs = np.array([r["coset"] for r in g["records"]])
+    ll, dl, cs = got["loglik"][idx], got["delta"][idx], got["coset"][idx]
+    bound = (36 + 60) * 2.0 ** -6
+    conv = (ref_dl < meta["delta0"]) & (dl < meta["delta0"]) & np.isfinite(ref_ll)
+    best = np.max(np.where(np.isfinite(ref_ll), ref_ll, -np.inf), axis=1)
+    best_gpu = np.max(np.where(np.isfinite(ll), ll, -np.inf), axis=1)
+    near = conv & (best[:, None] - ref_ll < 6.0)
+    far = conv & ~near
+    err = np.abs(ll - ref_ll)
+    _say(f"   converged cosets {conv.sum()} ({near.sum()} within 6 nats of the best): |dlnZ| max "
+         f"{err[near].max():.3e} p99 {np.percentile(err[near], 99):.3e} median {np.median(err[near]):.3e}; "
+         f"further below: max {err[far].max():.3e}, {(err[far] > bound).sum()} beyond the bound")
+    assert err[near].max() <= bound
+    assert np.all((best_gpu[:, None] - ll)[far] > 2 * bound)
+    srt = np.sort(np.where(np.isfinite(ref_ll), ref_ll, -np.inf), axis=1)
+    clear = (srt[:, -1] - srt[:, -2]) > 2 * bound
+    _say(f"   decisions equal {(cs == ref_cs).sum()} / {len(idx)} (clear margins: {clear.sum()})")
+    np.testing.assert_array_equal(cs[clear], ref_cs[clear])
+    assert np.all(got["coset"] < 4)
+    np.testing.assert_array_equal(workload.syndrome_of(17, got["correction"]), syn)
 
 
 @pytest.mark.parametrize("d,k,iters", [(5, 3, 8), (7, 4, 5), (9, 6, 4)])
