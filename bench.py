@@ -66,7 +66,7 @@ def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024, target="sweep"):
     boundary-MPS kernel (target "bmps") from two rocprofv3 --pmc counter CSVs of `bench.py --calibrate-copy
     MIB`, with the scale factors that make the calibration copy read and write exactly its size; stamped
     with the hash of the kernel sources."""
-    sources, path, prefix = ((TRAFFIC_SOURCES, TRAFFIC, "sweep_kernel<") if target == "sweep" else
+    sources, path, prefix = ((TRAFFIC_SOURCES, TRAFFIC, "sweep_kernel") if target == "sweep" else
                              (BMPS_TRAFFIC_SOURCES, BMPS_TRAFFIC, "bmps_kernel<"))
     import collections
     import csv
