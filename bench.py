@@ -716,7 +716,10 @@ def warm_main(a):
     """Learned warm start against the uniform (cold) start: 4096 syndromes at d=25 (--warm-d), p=0.10, 6x6 blocks,
     chi 32, early exit at delta0 1e-4 within at most 60 iterations (so that iterations to convergence are
     measured, not the cap). The warm decode is the network's forward, the decode from its messages and the
-    cold rerun of the syndromes whose final distance stays at or above delta1; each is timed whole."""
+    cold rerun of the syndromes whose final distance stays at or above delta1 or whose decided coset was not
+    the fastest to converge; each is timed whole. Outside the distances the committed network was trained on
+    (13..21) the library decodes the whole batch cold ('warm'); 'unguarded' is the network used there anyway,
+    the measurement of what it would do."""
     import numpy as np
     import torch
 
@@ -745,11 +748,20 @@ def warm_main(a):
     cold, t_cold = timed(lambda o: bbp.decode_device(d, p, s, opts, workspace=ws, out=o))
     wws = [None]
 
-    def warm_step(o):
-        r = warm.decode(d, p, s, opts, theta, workspace=wws[0], out=o)
+    def warm_step(o, trained=None):
+        r = warm.decode(d, p, s, opts, theta, workspace=wws[0], out=o, trained=trained)
         wws[0] = r["workspace"]
         return r
     hot, t_warm = timed(warm_step)
+    lo, hi = warm.trained_range()
+    unguarded = None
+    if not lo <= d <= hi:
+        hu, t_u = timed(lambda o: warm_step(o, trained=(0, 0)))
+        uwi = hu["iters"].double()
+        unguarded = dict(value=count / t_u, ms_per_step=1e3 * t_u, mean_iterations_per_coset=float(uwi.mean()),
+                         fallback_syndromes=int(hu["fallback"]),
+                         decision_agreement_with_cold=float((hu["coset"] == cold["coset"]).double().mean()),
+                         logical_failure_rate=logical_failures(d, errors, hu["correction"].cpu().numpy()).mean())
     pred_ws = torch.empty(warm.workspace_size(d, count, opts, False), dtype=torch.uint8, device=dev)
     _, t_pred = timed(lambda o: warm.predict(d, p, s, opts, theta, workspace=pred_ws))
     ci, wi = cold["iters"].double(), hot["iters"].double()
@@ -773,7 +785,7 @@ def warm_main(a):
         decision_agreement_with_cold=float((hot["coset"] == cold["coset"]).double().mean()),
         logical_failure_rate=dict(cold=logical_failures(d, errors, cold["correction"].cpu().numpy()).mean(),
                                   warm=logical_failures(d, errors, hot["correction"].cpu().numpy()).mean()),
-        speedup=t_cold / t_warm,
+        speedup=t_cold / t_warm, trained_distances=[lo, hi], unguarded=unguarded,
     )
     print(json.dumps(line), flush=True)
 

@@ -326,14 +326,19 @@ int bbp_warm_adam(float* params_dev, const float* grad_dev, float* m_dev, float*
                   void* stream);
 
 /* Warm-started decode with cold fallback: the network's messages start BP (bbp_group.init_messages_dev);
- * every syndrome with a coset whose final distance is not below opts->delta1 is decoded again from the
- * uniform start, and its results replace the warm ones (its iteration counts are the sum of both runs).
- * Outputs as bbp_decode_device; *fallback_count (host, may be NULL) receives the number of reruns. The call
- * synchronises `stream` once (to size the fallback batch). precision: the network's, as bbp_warm_predict. */
+ * every syndrome with a coset whose final distance is not below opts->delta1, or whose decided coset took
+ * more iterations than another of its cosets (the right coset converges fastest, Sec. IV), is decoded again
+ * from the uniform start, and its results replace the warm ones (its iteration counts are the sum of both
+ * runs). [trained_d_min, trained_d_max] are the distances the parameters were trained on (both 0: no range):
+ * for d outside them the whole batch is decoded from the uniform start and *fallback_count = batch, because
+ * there the predicted starts lead BP to other fixed points that pass every convergence test. Outputs as
+ * bbp_decode_device; *fallback_count (host, may be NULL) receives the number of syndromes decoded from the
+ * uniform start. The call synchronises `stream` once (to size the fallback batch). precision: the network's,
+ * as bbp_warm_predict. Errors as bbp_warm_predict, BBP_EINVAL for a range with min > max or one bound 0. */
 int bbp_warm_decode_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* bytes);
 int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                    const bbp_opts* opts, const float* params_dev, int32_t precision, void* workspace,
-                    size_t workspace_bytes,
+                    const bbp_opts* opts, const float* params_dev, int32_t precision, int32_t trained_d_min,
+                    int32_t trained_d_max, void* workspace, size_t workspace_bytes,
                     double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
                     uint8_t* correction_dev, int64_t* fallback_count, void* stream);
 

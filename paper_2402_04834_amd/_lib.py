@@ -111,8 +111,8 @@ SIGNATURES = {
     "bbp_warm_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
     "bbp_warm_decode_workspace_size": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(bbp_opts), C.POINTER(C.c_size_t)]),
     "bbp_warm_decode": (C.c_int, [C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(bbp_opts),
-                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+                                  C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
 }
 
 _lib = None

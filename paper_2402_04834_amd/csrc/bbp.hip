@@ -362,7 +362,11 @@ struct Tune {
 };
 std::map<std::tuple<int, int, int, int, int>, Tune> g_tune;
 
-// Per-device auxiliary streams (default priority) and the events that fork and join them.
+// Per-device auxiliary streams (default priority) and the events that fork and join them. They are shared by
+// every caller on the device, so a decode that uses them enqueues (or captures) its whole work while holding
+// g_aux_mu: two callers' fork / join records cannot interleave, and a capture cannot pull another caller's
+// work on the auxiliary streams into its graph.
+std::mutex g_aux_mu;
 struct Aux {
   hipStream_t s[3] = {nullptr, nullptr, nullptr};
   hipEvent_t fork = nullptr;
@@ -723,9 +727,12 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
   if (tn.streams > 1 && (rc = aux_for(dev, &aux))) return rc;
   hipStream_t st = (hipStream_t)stream;
 
+  std::unique_lock<std::mutex> aux_lock(g_aux_mu, std::defer_lock);
+  if (aux) aux_lock.lock();
   if (timing) {
     std::vector<Mark> marks;
     rc = enqueue(gr, opts, tn, st, aux, &marks);
+    if (aux) aux_lock.unlock();
     if (rc == BBP_OK) {
       if (hipStreamSynchronize(st) != hipSuccess) rc = fail(BBP_EHIP, "stream synchronisation failed");
       else rc = collect_timing(gr, opts, marks, timing);
@@ -748,13 +755,17 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
                            u64(g.in.loglik_dev), u64(g.in.delta_dev), u64(g.in.iters_dev), u64(g.in.coset_dev),
                            u64(g.in.correction_dev), u64(g.in.init_messages_dev), u64(g.in.messages_dev),
                            u64(g.in.noise[0]), u64(g.in.noise[1]), u64(g.in.noise[2]), u64(g.in.noise[3])});
-  hipGraphExec_t exec = nullptr;
+  // a cached graph is launched under the cache lock, so that no eviction can destroy it in between
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) exec = it->second;
+    if (it != g_graphs.end()) {
+      HIP_TRY(hipGraphLaunch(it->second, st));
+      return BBP_OK;
+    }
   }
-  if (!exec) {
+  hipGraphExec_t exec = nullptr;
+  {
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     rc = enqueue(gr, opts, tn, st, aux, nullptr);
     hipGraph_t graph = nullptr;
@@ -767,6 +778,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(BBP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    if (aux) aux_lock.unlock();
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) {   // another thread captured the same decode meanwhile: keep one
@@ -780,8 +792,8 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
       }
       g_graphs[key] = exec;
     }
+    HIP_TRY(hipGraphLaunch(exec, st));
   }
-  HIP_TRY(hipGraphLaunch(exec, st));
   return BBP_OK;
 }
 

@@ -602,11 +602,20 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 
 // Fallback selection after a warm-started decode: syndromes with a coset whose final distance is at least
 // delta1 are listed (order of the list unspecified) for a cold rerun.
-__global__ void fallback_select_kernel(const double* __restrict__ delta, int64_t batch, double delta1,
+// Syndromes the warm run cannot vouch for: a coset whose final distance is not below delta1, or a decided
+// coset that was not among the fastest to converge (the right coset converges fastest, Sec. IV; a decided
+// coset that took longer than another points to a fixed point that the predicted start led to).
+__global__ void fallback_select_kernel(const double* __restrict__ delta, const int32_t* __restrict__ iters,
+                                       const uint8_t* __restrict__ coset, int64_t batch, double delta1,
                                        int64_t* __restrict__ list, int64_t* __restrict__ count) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < batch; b += (int64_t)gridDim.x * blockDim.x) {
     bool bad = false;
-    for (int k = 0; k < 4; ++k) bad |= !(delta[b * 4 + k] < delta1);
+    int fastest = iters[b * 4];
+    for (int k = 0; k < 4; ++k) {
+      bad |= !(delta[b * 4 + k] < delta1);
+      fastest = min(fastest, iters[b * 4 + k]);
+    }
+    bad |= iters[b * 4 + coset[b]] > fastest;
     if (bad) list[atomicAdd((unsigned long long*)count, 1ull)] = b;
   }
 }
@@ -977,14 +986,16 @@ int bbp_warm_decode_workspace_size(int32_t d, int64_t batch, const bbp_opts* opt
 }
 
 int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syndromes_dev, int64_t batch,
-                    const bbp_opts* opts, const float* params_dev, int32_t precision, void* workspace,
-                    size_t workspace_bytes,
+                    const bbp_opts* opts, const float* params_dev, int32_t precision, int32_t trained_d_min,
+                    int32_t trained_d_max, void* workspace, size_t workspace_bytes,
                     double* loglik_dev, double* delta_dev, int32_t* iters_dev, uint8_t* coset_dev,
                     uint8_t* correction_dev, int64_t* fallback_count, void* stream) {
   if (!opts || !params_dev || !syndromes_dev || !workspace || !loglik_dev || !delta_dev || !iters_dev ||
       !coset_dev || !correction_dev)
     return wfail(BBP_EINVAL, "a required pointer is NULL");
   if (batch < 1) return wfail(BBP_EINVAL, "batch must be >= 1");
+  if (trained_d_min < 0 || trained_d_max < trained_d_min || (trained_d_min == 0) != (trained_d_max == 0))
+    return wfail(BBP_EINVAL, "the trained distance range must be 0 <= min <= max, both 0 for no range");
   DLayout l;
   int rc = dlayout(d, batch, opts, p, &l);
   if (rc) return rc;
@@ -992,6 +1003,28 @@ int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syn
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const int m = 2 * d * (d - 1), nq = d * d + (d - 1) * (d - 1);
+  if (trained_d_min > 0 && (d < trained_d_min || d > trained_d_max)) {
+    // outside the distances the network was trained on its start messages can lead BP to fixed points that
+    // pass every convergence test with another decision: the whole batch is decoded from the uniform start
+    bbp_group g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    g.p = p;
+    g.p_dev = p_dev;
+    g.syndromes_dev = syndromes_dev;
+    g.batch = batch;
+    g.loglik_dev = loglik_dev;
+    g.delta_dev = delta_dev;
+    g.iters_dev = iters_dev;
+    g.coset_dev = coset_dev;
+    g.correction_dev = correction_dev;
+    bbp_opts co = *opts;
+    co.graph = 0;
+    if ((rc = bbp_decode_groups(&g, 1, &co, ws + l.dec, l.list - l.dec, stream, nullptr)))
+      return wfail(rc, std::string("cold decode: ") + bbp_last_error());
+    if (fallback_count) *fallback_count = batch;
+    return BBP_OK;
+  }
   float* msgs = (float*)(ws + l.msgs);
   if ((rc = bbp_warm_predict(d, p, p_dev, syndromes_dev, batch, opts, params_dev, precision, msgs, ws + l.pred,
                              l.msgs - l.pred, stream)))
@@ -1015,7 +1048,8 @@ int bbp_warm_decode(int32_t d, double p, const double* p_dev, const uint8_t* syn
   int64_t* list = (int64_t*)(ws + l.list);
   int64_t* cnt = (int64_t*)(ws + l.count);
   W_TRY(hipMemsetAsync(cnt, 0, 8, st));
-  fallback_select_kernel<<<grid1(batch), 256, 0, st>>>(delta_dev, batch, opts->delta1, list, cnt);
+  fallback_select_kernel<<<grid1(batch), 256, 0, st>>>(delta_dev, iters_dev, coset_dev, batch, opts->delta1, list,
+                                                       cnt);
   W_TRY(hipGetLastError());
   int64_t n = 0;
   W_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, st));

@@ -105,8 +105,9 @@ def _plan_messages(d, opts):
 
 
 def loss_grad(d: int, p, syndromes, opts: bbp_opts, params, targets, use, *, workspace=None, stream=None):
-    """(loss [1] float32, gradient [P] float32) of the mean of 1 - <m, t>^2 over the messages of the used
-    coset jobs; targets [batch, 4, M, 64] float32, use [batch * 4] uint8 (CUDA tensors)."""
+    """(loss [1] float32, gradient [P] float32) of the mean over the messages of the used coset jobs of
+    KL(q || softmax(s)), q the target message normalised to sum 1 and s the network's scores (the loss of
+    bbp_warm_loss_grad); targets [batch, 4, M, 64] float32, use [batch * 4] uint8 (CUDA tensors)."""
     import torch
     syndromes = syndromes.contiguous()
     b, dev = syndromes.shape[0], syndromes.device
@@ -136,10 +137,19 @@ def adam(params, grad, m, v, step: int, lr: float, *, stream=None) -> None:
                                              lr, _stream(stream, params.device)))
 
 
-def decode(d: int, p, syndromes, opts: bbp_opts, params, *, precision: int = 1, workspace=None, stream=None,
-           out=None):
-    """Warm-started decode with cold fallback (bbp_warm_decode). Returns the output dict of decode_device
-    plus 'fallback' (number of syndromes decoded again from the uniform start)."""
+def trained_range(path: str = WEIGHTS_PATH):
+    """(smallest, largest) distance the weights at `path` were trained on, from their metadata file."""
+    import json
+    meta = json.load(open(os.path.splitext(path)[0] + ".json"))
+    return min(meta["distances"]), max(meta["distances"])
+
+
+def decode(d: int, p, syndromes, opts: bbp_opts, params, *, precision: int = 1, trained=None, workspace=None,
+           stream=None, out=None):
+    """Warm-started decode with cold fallback (bbp_warm_decode). `trained` = (smallest, largest) distance the
+    parameters were trained on (default: the committed weights' range; None-equivalent (0, 0) disables the
+    check): outside it the whole batch is decoded from the uniform start. Returns the output dict of
+    decode_device plus 'fallback' (number of syndromes decoded from the uniform start)."""
     import torch
     from . import _outputs
     syndromes = syndromes.contiguous()
@@ -152,9 +162,10 @@ def decode(d: int, p, syndromes, opts: bbp_opts, params, *, precision: int = 1, 
         out = _outputs(b, d * d + (d - 1) * (d - 1), dev)
     pv, pt = _p_args(p, b)
     fb = C.c_int64()
+    lo, hi = trained_range() if trained is None else trained
     _lib.check_warm(_lib.lib().bbp_warm_decode(
         d, pv, pt.data_ptr() if pt is not None else None, syndromes.data_ptr(), b, C.byref(opts),
-        params.data_ptr(), precision, workspace.data_ptr(), workspace.numel(), out["loglik"].data_ptr(),
+        params.data_ptr(), precision, lo, hi, workspace.data_ptr(), workspace.numel(), out["loglik"].data_ptr(),
         out["delta"].data_ptr(),
         out["iters"].data_ptr(), out["coset"].data_ptr(), out["correction"].data_ptr(), C.byref(fb),
         _stream(stream, dev)))

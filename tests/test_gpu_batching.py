@@ -237,3 +237,48 @@ def test_mixed_distance_workload_one_graph(dev):
             assert srt[0] - srt[1] < 1e-3, (d, i, ref_ll[i], ref_dl[i])
         _say(f"[mixed workload] d={d}: {len(recs)} oracle records, decisions equal {int((~bad).sum())}, "
              f"max |dlnZ| {np.abs(ll[same] - ref_ll[same]).max():.2e}")
+
+def test_concurrent_multistream_decodes_match_serial(dev):
+    """Two host threads decoding at once with the four-stream launch variant (which shares the device's
+    auxiliary streams and events), eagerly and through captured graphs, each on its own stream: every result
+    is bitwise the serial decode's."""
+    import threading
+    import torch
+    import paper_2402_04834_amd as bbp
+    d, p = 9, 0.10
+    opts = bbp.default_opts(block=6, chi=32, max_iter=20)
+    gopts = bbp.default_opts(block=6, chi=32, max_iter=20, graph=1)
+    bbp.set_tuning(d, opts, 1, 4)
+    try:
+        syn = [torch.from_numpy(workload.make_batch(d, p, 48, workload="mixed", p_index=120 + k)[1]).to(dev)
+               for k in range(2)]
+        ref = [_np(bbp.decode_device(d, p, s, opts)) for s in syn]
+        torch.cuda.synchronize()
+        errors, results = [], [[], []]
+
+        def worker(k):
+            try:
+                st = torch.cuda.Stream(dev)
+                ws = torch.empty(bbp.workspace_size(d, 48, opts), dtype=torch.uint8, device=dev)
+                out = None
+                for rep in range(6):
+                    o = gopts if rep % 2 else opts
+                    out = bbp.decode_device(d, p, syn[k], o, workspace=ws, stream=st, out=out)
+                    st.synchronize()
+                    results[k].append(_np(out))
+            except Exception as e:   # reported by the main thread
+                errors.append(e)
+
+        _say("[concurrent] two threads, 4-stream variant, eager and graph")
+        th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        for k in range(2):
+            assert len(results[k]) == 6
+            for r in results[k]:
+                _same(r, ref[k], f"thread {k}")
+    finally:
+        bbp.set_tuning(d, opts, 0, 1)

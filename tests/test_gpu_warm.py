@@ -218,8 +218,9 @@ def test_uniform_given_messages_equal_default_start(dev):
 
 def test_warm_decode_fallback(dev):
     """bbp_warm_decode = predict + decode from the predicted messages, and every syndrome with a coset whose
-    final distance is not below delta1 decoded again cold: its results are the cold decode's and its
-    iteration counts the sum of both runs; the others keep the warm results."""
+    final distance is not below delta1, or whose decided coset took more iterations than another of its
+    cosets, decoded again cold: its results are the cold decode's and its iteration counts the sum of both
+    runs; the others keep the warm results. (No trained-range check: these parameters are a test network.)"""
     import torch
     import paper_2402_04834_amd as bbp
     from paper_2402_04834_amd import warm
@@ -234,10 +235,11 @@ def test_warm_decode_fallback(dev):
         cold = _np(bbp.decode_device(d, p, s, opts))
         init = warm.predict(d, p, s, opts, th)
         wo, _, _ = bbp.decode_groups([(d, p, s, 0, init)], opts)
-        res = warm.decode(d, p, s, opts, th)
+        res = warm.decode(d, p, s, opts, th, trained=(0, 0))
         torch.cuda.synchronize()
         only, got = _np(wo[0]), _np(res)
-        fb = np.any(~(only["delta"] < opts.delta1), axis=1)
+        slower = only["iters"][np.arange(b), only["coset"]] > only["iters"].min(axis=1)
+        fb = np.any(~(only["delta"] < opts.delta1), axis=1) | slower
         assert res["fallback"] == fb.sum()
         total_fb += int(fb.sum())
         for k in ("loglik", "delta", "coset", "correction"):
@@ -246,6 +248,52 @@ def test_warm_decode_fallback(dev):
         np.testing.assert_array_equal(got["iters"][fb], only["iters"][fb] + cold["iters"][fb])
         np.testing.assert_array_equal(got["iters"][~fb], only["iters"][~fb])
     assert total_fb > 0     # the fallback path ran
+
+
+def test_warm_decode_outside_trained_range_is_cold(dev):
+    """For a distance outside the parameters' trained range the warm decode is the cold decode, bitwise, and
+    reports every syndrome as decoded from the uniform start; a range with one bound 0 is refused."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm
+    d, p, b = 9, 0.1, 12
+    _, syn = workload.make_batch(d, p, b, workload="warm", p_index=415)
+    s = torch.from_numpy(syn).to(dev)
+    th = torch.from_numpy(_theta(5, head_scale=0.3)).to(dev)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=20)
+    _say("[warm range] d=9 against a network trained on 13..21")
+    cold = _np(bbp.decode_device(d, p, s, opts))
+    res = warm.decode(d, p, s, opts, th, trained=(13, 21))
+    torch.cuda.synchronize()
+    assert res["fallback"] == b
+    got = _np(res)
+    for k in ("loglik", "delta", "iters", "coset", "correction"):
+        np.testing.assert_array_equal(got[k], cold[k], err_msg=k)
+    with pytest.raises(bbp.BbpError):
+        warm.decode(d, p, s, opts, th, trained=(0, 21))
+
+
+def test_warm_in_distribution_agreement_d17(dev):
+    """Decision agreement of the warm decode (committed weights, trained on d 13..21) with the cold decode at
+    d=17, p=0.10, 4096 syndromes, <= 60 iterations (the benchmark's warm workload at a trained distance):
+    at least 99.9 % of the syndromes (measured without any fallback: 99.95 %)."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm
+    d, p, b = 17, 0.10, 4096
+    _, syn = workload.make_batch(d, p, b, workload="warm", p_index=10)
+    s = torch.from_numpy(syn).to(dev)
+    th = torch.from_numpy(warm.load()).to(dev)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=60)
+    _say("[warm d=17] 4096 syndromes, committed weights")
+    cold = _np(bbp.decode_device(d, p, s, opts))
+    res = warm.decode(d, p, s, opts, th)
+    torch.cuda.synchronize()
+    hot = _np(res)
+    agree = (hot["coset"] == cold["coset"]).mean()
+    _say(f"   agreement {agree:.5f}, fallback {res['fallback']}")
+    assert agree >= 0.999
+    np.testing.assert_array_equal(workload.syndrome_of(d, hot["correction"]), syn)
 
 
 def test_training_reduces_loss(dev):
