@@ -334,7 +334,7 @@ def main():
                            roofline_measured_on=("the timed decodes" if r["events_in_timed"] else
                                                  f"{a.steps} separate single-stream decodes")),
         plan=dict(messages_per_coset=r["info"].num_messages, exact_sweeps=bool(r["info"].exact_sweeps),
-                  max_boundary_rank=r["info"].max_boundary_rank),
+                  max_cut_rank=r["info"].max_cut_rank),
         agreement=agreement(r["out"], a.batch, errors, d) if block == 6 else None,
     )
     if other is not None:

@@ -101,7 +101,9 @@ typedef struct bbp_plan_info {
   int32_t num_messages;          /* M */
   int32_t updates_per_iter;      /* = M */
   int32_t exact_sweeps;          /* 1: chi never truncates (see above) */
-  int32_t max_boundary_rank;     /* largest generic Schmidt rank seen by the analysis */
+  int32_t max_cut_rank;          /* largest generic Schmidt rank among the cuts whose dimensions exceed chi on
+                                    both sides -- the only cuts where truncation to chi could act; 0 if none.
+                                    At or below chi it means truncation never acts (exact_sweeps = 1) */
   int32_t gpu_supported;         /* 1: bbp_decode_device accepts these options */
   double flops_per_iter;
   double flops_bethe;

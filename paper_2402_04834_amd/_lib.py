@@ -46,7 +46,7 @@ class bbp_plan_info(C.Structure):
         ("L", C.c_int32), ("n", C.c_int32), ("m", C.c_int32),
         ("block_grid_rows", C.c_int32), ("block_grid_cols", C.c_int32),
         ("num_messages", C.c_int32), ("updates_per_iter", C.c_int32), ("exact_sweeps", C.c_int32),
-        ("max_boundary_rank", C.c_int32), ("gpu_supported", C.c_int32),
+        ("max_cut_rank", C.c_int32), ("gpu_supported", C.c_int32),
         ("flops_per_iter", C.c_double), ("flops_bethe", C.c_double),
     ]
 

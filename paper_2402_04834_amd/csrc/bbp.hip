@@ -1024,7 +1024,7 @@ int bbp_plan_query(int32_t d, const bbp_opts* opts, bbp_plan_info* info) {
   info->num_messages = p.M;
   info->updates_per_iter = p.M;
   info->exact_sweeps = p.exact ? 1 : 0;
-  info->max_boundary_rank = p.max_rank;
+  info->max_cut_rank = p.max_rank;
   info->gpu_supported = p.gpu_ok ? 1 : 0;
   info->flops_per_iter = p.flops_iter;
   info->flops_bethe = p.flops_bethe;

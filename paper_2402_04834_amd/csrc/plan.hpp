@@ -33,7 +33,7 @@ struct Plan {
   std::vector<int32_t> pair_ids;                              // undirected edges: (u->v, v->u) ids
   int max_msg_len = 0;
   bool exact = false;        // no boundary state can exceed chi: truncation is the identity
-  int max_rank = 0;          // largest generic Schmidt rank found across cuts that could bind
+  int max_rank = 0;          // largest generic Schmidt rank among cuts whose dimensions exceed chi on both sides
   bool gpu_ok = false;
   std::string why;           // reason when !gpu_ok
   double flops_iter = 0.0, flops_bethe = 0.0;

@@ -45,7 +45,7 @@ def test_plan_matches_oracle_partition_and_is_exact(bbp, d, k, chi):
 
 def test_plan_detects_binding_truncation(bbp):
     info = bbp.plan_query(7, bbp.default_opts(block=6, chi=8))
-    assert info.exact_sweeps == 0 and info.max_boundary_rank == 16 and info.gpu_supported == 0
+    assert info.exact_sweeps == 0 and info.max_cut_rank == 16 and info.gpu_supported == 0
     info = bbp.plan_query(7, bbp.default_opts(block=6, chi=16))
     assert info.exact_sweeps == 1
 
