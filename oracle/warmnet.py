@@ -261,6 +261,42 @@ def loss_and_grad(theta, X0, d, plan, targets, msg_ids, ch=CHANNELS):
     return total / n, pack(grads, ch)
 
 
+def predict_stored(theta, X0, d, plan, store, ch=CHANNELS):
+    """Dense initial messages [M, 64] of one coset job in the arithmetic of the inference variant: the input
+    channels, both hidden activations and the first two convolutions' weights go through `store` (the
+    narrower storage format); the last convolution is composed with the head, i.e. for each direction the
+    features are projected on the six 96-row blocks of the head's weights that a site contributes as a_i,
+    b_i, a_{i+1} or b_{i+1} of a message (Wu's two halves, Wp's four quarters), the composed weights W3 Hc also
+    going through `store`; every sum is exact. With store = identity this equals predict()."""
+    prm = unpack(theta, ch)
+    X0 = store(X0)
+    A1 = store(np.maximum(conv(X0, store(prm["conv1.W"]), prm["conv1.b"]), 0.0))
+    A2 = store(np.maximum(conv(A1, store(prm["conv2.W"]), prm["conv2.b"]), 0.0))
+    C3 = ch[2]
+    proj = {}
+    for name, k in DIRECTIONS.items():
+        Wu, Wp = prm[f"head{k}.Wu"], prm[f"head{k}.Wp"]
+        Hc = np.concatenate([Wu[:C3], Wu[C3:], Wp[:C3], Wp[C3:2 * C3], Wp[2 * C3:3 * C3], Wp[3 * C3:]], axis=1)
+        proj[k] = conv(A2, store(prm["conv3.W"] @ Hc), prm["conv3.b"] @ Hc)      # [L, L, 20]
+    out = np.zeros((plan.M, 64))
+    for e in range(plan.M):
+        lg = legs(d, plan, e)
+        k = direction_of(plan, e)
+        P, K = proj[k], len(lg)
+        bu, bp = prm[f"head{k}.bu"], prm[f"head{k}.bp"]
+        u = [P[a][0:2] + P[b][2:4] + bu for a, b in lg]
+        pair = [P[lg[i][0]][4:8] + P[lg[i][1]][8:12] + P[lg[i + 1][0]][12:16] + P[lg[i + 1][1]][16:20] + bp
+                for i in range(K - 1)]
+        sc = np.zeros(2 ** K)
+        for idx in range(2 ** K):
+            bits = [(idx >> (K - 1 - i)) & 1 for i in range(K)]
+            sc[idx] = sum(u[i][bits[i]] for i in range(K)) + sum(pair[i][2 * bits[i] + bits[i + 1]]
+                                                                 for i in range(K - 1))
+        m = np.exp(sc - sc.max())
+        out[e, :2 ** K] = m / np.linalg.norm(m)
+    return out
+
+
 def predict(theta, X0, d, plan, ch=CHANNELS, store=None):
     """Dense initial messages [M, 64] of one coset job (store: see trunk)."""
     prm = unpack(theta, ch)

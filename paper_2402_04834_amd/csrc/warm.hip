@@ -100,7 +100,9 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 __device__ __forceinline__ void store_el(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_el(unsigned short* p, float v) { *p = f2bf(v); }
 
-template <class T>
+// CS: channels stored per site (C0, or 16 for the BF16 convolutions, whose K steps need 8-channel groups;
+// channels C0 .. CS-1 are zero)
+template <class T, int CS>
 __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict__ syn, const double* __restrict__ pdev,
                                                        float p, int d, T* __restrict__ X) {
   __shared__ uint8_t s[2 * 32 * 31];
@@ -177,8 +179,8 @@ __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict
     v[7] = 1.0f;
     v[8] = (float)bx;
     v[9] = (float)bz;
-    T* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * C0;
-    for (int k = 0; k < C0; ++k) store_el(o + k, v[k]);
+    T* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * CS;
+    for (int k = 0; k < CS; ++k) store_el(o + k, k < C0 ? v[k] : 0.0f);
   }
 }
 
@@ -313,88 +315,137 @@ __global__ __launch_bounds__(256) void conv_gemm(int L, int64_t rows, int cin, i
 }
 
 // Forward convolution in BF16 (inference): activations and weights stored as BF16, products and sums in FP32
-// on v_mfma_f32_16x16x16bf16 (lane l supplies A row l%16 and B column l%16, k = 4 (l/16) .. +3 of a 16-step).
-// Same gather as conv_gemm<G_FWD>; 64 x 64 output tile per workgroup of four waves (2 x 2 blocks of 16 x 16
-// each), K in chunks of 32 staged in LDS with k innermost for both operands (8-byte fragment reads).
-typedef short bf4 __attribute__((ext_vector_type(4)));
+// on v_mfma_f32_16x16x32_bf16 (lane l supplies row l%16 of A and column l%16 of B with k = 8 (l/16) .. +7 of
+// a 32-step, and holds D rows 4 (l/16) .. +3 of column l%16). Implicit GEMM with the gather of conv_gemm<G_FWD>:
+// Y[row][co] = act(sum_{t, ci} X[row + t][ci] Wt[co][t CIN + ci] + b[co]). One workgroup of four waves computes
+// 128 rows x all NT output channels (2 x 2 waves of 64 x NT/2, i.e. 4 x NT/32 MFMA blocks each), so every
+// gathered activation tile is read once; K advances in steps of 32 through double-buffered LDS tiles (one
+// barrier per step), the next step's global loads in flight during the current step's MFMAs. A 16-byte load
+// is 8 channels of one tap (CIN is a multiple of 16); the weights come transposed, Wt[co][k], k padded to a
+// multiple of the stage with zeros, so both LDS tiles are k-contiguous.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-__global__ void to_bf16_kernel(const float* __restrict__ src, unsigned short* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = f2bf(src[i]);
+// Wt[co][kp] (kp < kpad) = W[t cin + ci][co] for kp = t cs + ci with ci < cin, else 0 (BF16)
+__global__ void weights_t_kernel(const float* __restrict__ W, int cin, int cs, int cout, int kpad,
+                                 unsigned short* __restrict__ Wt) {
+  const int64_t n = (int64_t)cout * kpad;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(i / kpad), kp = (int)(i - (int64_t)co * kpad), t = kp / cs, ci = kp - t * cs;
+    Wt[i] = (t < 9 && ci < cin) ? f2bf(W[((int64_t)t * cin + ci) * cout + co]) : (unsigned short)0;
+  }
 }
 
-template <int RELU, bool OUT_BF>
-__global__ __launch_bounds__(256) void conv_fwd_bf16(int L, int64_t rows, int cin, int cout,
-                                                     const unsigned short* __restrict__ X,
-                                                     const unsigned short* __restrict__ W,
+#ifndef BBP_CONV_KS
+#define BBP_CONV_KS 32
+#endif
+constexpr int CONV_KS = BBP_CONV_KS;   // k per LDS stage of the BF16 convolutions (32 or 64)
+// k of a BF16 weight row: 9 cs padded to a multiple of the stage
+constexpr int kpad(int cs) { return (9 * cs + CONV_KS - 1) / CONV_KS * CONV_KS; }
+
+// WM: waves along M (2: wave tiles of 64 x NT/2, workgroup tiles of 128 x NT; 4: 64 x NT and 256 x NT, each
+// B fragment then serving four A fragments).
+template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
+__global__ __launch_bounds__(256) void conv_fwd_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
+                                                     const unsigned short* __restrict__ Wt,
                                                      const float* __restrict__ bias, void* __restrict__ Y) {
-  __shared__ __align__(16) unsigned short As[64][40];   // [row][k], 32 k + 8 pad
-  __shared__ __align__(16) unsigned short Bs[64][40];   // [n][k]
+  constexpr int KS = CONV_KS;                             // k per LDS stage (32 or 64: one or two MFMA steps)
+  constexpr int K = 9 * CIN, KP = kpad(CIN), S = KS + 8;   // LDS row stride: KS k + 8 (bank spread)
+  constexpr int MT = 64 * WM, WN = NT * WM / 4;           // workgroup rows, wave columns
+  constexpr int NJ = WN / 16;                             // 16-column blocks per wave
+  constexpr int G = KS / 8;                               // 8-k groups per row and stage
+  constexpr int UA = MT * G / 256, UB = (NT * G + 255) / 256;   // 16-byte chunks per thread and stage
+  static_assert(CIN % 16 == 0 && NT % 32 == 0 && NT <= 128 && (WM == 2 || WM == 4), "tile shape");
+  __shared__ __align__(16) unsigned short As[2][MT * S];
+  __shared__ __align__(16) unsigned short Bs[2][NT * S];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * 64;
-  const int n0 = blockIdx.y * 64;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  const int K = 9 * cin;
-  f4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  const int amm = tid >> 2, akq = (tid & 3) * 8;   // A: row amm, k = akq .. akq + 7 of the chunk
-  const bool arow_ok = m0 + amm < rows;
-  Site arow{0, 0, 0};
-  if (arow_ok) arow = site_of(m0 + amm, L);
-  const int bkk = tid >> 3, bnq = (tid & 7) * 8;   // B: k = bkk of the chunk, n = bnq .. bnq + 7
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    if ((cin & 7) == 0) {   // the 8 k of a thread lie in one tap: one 16-byte load
-      const int k = k0 + akq;
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  const int wm = (w / (4 / WM)) * 64, wn = (w % (4 / WM)) * WN;
+  // global -> LDS assignment: A chunk q = tid + 256 u: row q / G, k group q % G (8 k each); B chunk q
+  // (< NT * G): column q / G, k group q % G
+  Site arow[UA];
+  bool aok[UA];
+#pragma unroll
+  for (int u = 0; u < UA; ++u) {
+    const int64_t row = m0 + (tid + 256 * u) / G;
+    aok[u] = row < rows;
+    arow[u] = aok[u] ? site_of(row, L) : Site{0, 0, 0};
+  }
+  uint4 ra[UA], rb[UB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const int q = tid + 256 * u, k = k0 + 8 * (q % G);
       uint4 v = {0u, 0u, 0u, 0u};
-      if (arow_ok && k < K) {
-        const int tap = k / cin, ch = k - tap * cin;
-        const int64_t src = shifted(arow, tap, 1, L);
-        if (src >= 0) v = *(const uint4*)(X + src * cin + ch);
+      if (aok[u] && k < K) {
+        const int tap = k / CIN, ch = k - tap * CIN;
+        const int64_t src = shifted(arow[u], tap, 1, L);
+        if (src >= 0) v = *(const uint4*)(X + src * CIN + ch);
       }
-      *(uint4*)&As[amm][akq] = v;
-    } else {
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + akq + j;
-        unsigned short v = 0;
-        if (arow_ok && k < K) {
-          const int tap = k / cin, ch = k - tap * cin;
-          const int64_t src = shifted(arow, tap, 1, L);
-          if (src >= 0) v = X[src * cin + ch];
-        }
-        As[amm][akq + j] = v;
-      }
+      ra[u] = v;
     }
-    {
-      const int k = k0 + bkk;
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + bnq + j;
-        Bs[bnq + j][bkk] = (k < K && n < cout) ? W[(int64_t)k * cout + n] : (unsigned short)0;
-      }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int q = tid + 256 * u;
+      uint4 b = {0u, 0u, 0u, 0u};
+      if (q < NT * G) b = *(const uint4*)(Wt + (int64_t)(q / G) * KP + k0 + 8 * (q % G));
+      rb[u] = b;
     }
-    __syncthreads();
-    for (int ks = 0; ks < 2; ++ks) {
-      const int kk = ks * 16 + 4 * (lane >> 4);
-      bf4 a[2], b[2];
-      for (int i = 0; i < 2; ++i) a[i] = *(const bf4*)&As[wm + i * 16 + (lane & 15)][kk];
-      for (int j = 0; j < 2; ++j) b[j] = *(const bf4*)&Bs[wn + j * 16 + (lane & 15)][kk];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const int q = tid + 256 * u;
+      *(uint4*)&As[buf][(q / G) * S + 8 * (q % G)] = ra[u];
     }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int q = tid + 256 * u;
+      if (q < NT * G) *(uint4*)&Bs[buf][(q / G) * S + 8 * (q % G)] = rb[u];
+    }
+  };
+  f4 acc[4][NJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  load(0);
+  store(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int k0 = 0, buf = 0; k0 < KP; k0 += KS, buf ^= 1) {
+    const bool more = k0 + KS < KP;
+    if (more) load(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 32) {
+      bf8 a[4], b[NJ];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *(const bf8*)&As[buf][(wm + 16 * i + fr) * S + kk + fk];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = *(const bf8*)&Bs[buf][(wn + 16 * j + fr) * S + kk + fk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = wn + 16 * j + fr;
+      const float bc = bias[col];
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn + j * 16 + (lane & 15);
-        if (row >= rows || col >= cout) continue;
-        float v = acc[i][j][r] + bias[col];
+        const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (row >= rows) continue;
+        float v = acc[i][j][r] + bc;
         if (RELU) v = fmaxf(v, 0.0f);
-        if (OUT_BF) ((unsigned short*)Y)[row * cout + col] = f2bf(v);
-        else ((float*)Y)[row * cout + col] = v;
+        if (OUT_BF) ((unsigned short*)Y)[row * NT + col] = f2bf(v);
+        else ((float*)Y)[row * NT + col] = v;
       }
+    }
 }
 
 // db[c] = sum over rows of dY[row][c]; one workgroup per channel
@@ -519,6 +570,87 @@ __global__ __launch_bounds__(64) void head_kernel(const float* __restrict__ F, c
       atomicAdd(&dFj[(int64_t)site * C3 + (k < C3 ? k : k - C3)], g);
     }
   }
+}
+
+// Inference head over projections. The head is linear in the features up to its scores, so for BF16
+// inference the last convolution and the head's weights are composed: per direction (20 columns each),
+// the features of a site projected on Wu[0:C3] (2), Wu[C3:2C3] (2), Wp[0:C3] (4), Wp[C3:2C3] (4),
+// Wp[2C3:3C3] (4) and Wp[3C3:4C3] (4) -- the parts that a site contributes as a_i, b_i, a_{i+1} or
+// b_{i+1} of a message. The composed layer computes those 80 projections per site directly (W3 Hc, bias
+// b3 Hc), and a message's unary and pairwise outputs are sums of a few of them.
+constexpr int NPROJ = 20;                  // projections per direction
+constexpr int PROJ_CH = 96;                // composed layer's output channels: 4 x 20, padded to a multiple of 32
+
+// column o of the composed head matrix Hc, entry for feature channel c (o < 4 NPROJ)
+__device__ __forceinline__ float head_col(const float* prm, int o, int c) {
+  const int dir = o / NPROJ, j = o - dir * NPROJ;
+  const float* H = prm + OFF.head + (size_t)dir * HEAD;
+  const float *Wu = H, *Wp = H + 2 * C3 * 2 + 2;
+  if (j < 4) return Wu[((j >> 1) * C3 + c) * 2 + (j & 1)];
+  const int q = (j - 4) & 3, part = (j - 4) >> 2;
+  return Wp[(part * C3 + c) * 4 + q];
+}
+
+// Wt[o][kp] = bf16(sum_c W3[kp][c] Hc[c][o]) for o < 4 NPROJ, 0 for the padding columns; bc[o] = b3 . Hc[:, o]
+__global__ void compose_head_kernel(const float* __restrict__ prm, int kpad, unsigned short* __restrict__ Wt,
+                                    float* __restrict__ bc) {
+  const int64_t n = (int64_t)PROJ_CH * kpad;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(i / kpad), kp = (int)(i - (int64_t)o * kpad);
+    float v = 0.0f;
+    if (o < 4 * NPROJ && kp < 9 * C2)
+      for (int c = 0; c < C3; ++c) v += prm[OFF.w3 + (size_t)kp * C3 + c] * head_col(prm, o, c);
+    Wt[i] = f2bf(v);
+    if (kp == 0) {
+      float b = 0.0f;
+      if (o < 4 * NPROJ)
+        for (int c = 0; c < C3; ++c) b += prm[OFF.b3 + c] * head_col(prm, o, c);
+      bc[o] = b;
+    }
+  }
+}
+
+// one wavefront per (job, message): lanes 0 .. 2K+4(K-1)-1 form the head outputs from the projections of the
+// legs' sites, every lane then scores its configuration b as head_kernel does
+__global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__ Pj, const int32_t* __restrict__ legs,
+                                                       int M, int L, int64_t jobs, const float* __restrict__ prm,
+                                                       float* __restrict__ msgs) {
+  const int64_t job = blockIdx.x / M;
+  const int e = (int)(blockIdx.x - job * M), lane = threadIdx.x;
+  if (job >= jobs) return;
+  const int32_t* lg = legs + e * 14;
+  const int K = lg[0], dir = lg[1];
+  const float* H = prm + OFF.head + (size_t)dir * HEAD;
+  const float *bu = H + 2 * C3 * 2, *bp = bu + 2 + 4 * C3 * 4;
+  const float* P = Pj + job * (int64_t)L * L * PROJ_CH + dir * NPROJ;
+  auto proj = [&](int site, int j) { return P[(int64_t)site * PROJ_CH + j]; };
+  // output o = lane: unary 2 i + c, pairwise 2 MAXK + 4 i + q (as head_kernel)
+  float outv = 0.0f;
+  if (lane < 2 * MAXK) {
+    const int i = lane >> 1, c = lane & 1;
+    if (i < K) outv = proj(lg[2 + i], c) + proj(lg[2 + MAXK + i], 2 + c) + bu[c];
+  } else if (lane < NOUT) {
+    const int i = (lane - 2 * MAXK) >> 2, q = (lane - 2 * MAXK) & 3;
+    if (i < K - 1)
+      outv = proj(lg[2 + i], 4 + q) + proj(lg[2 + MAXK + i], 8 + q) + proj(lg[2 + i + 1], 12 + q) +
+             proj(lg[2 + MAXK + i + 1], 16 + q) + bp[q];
+  }
+  const int b = lane, nb = 1 << K;
+  const bool valid = b < nb;
+  float s = 0.0f;
+  for (int i = 0; i < MAXK; ++i) {
+    if (i >= K) break;
+    const int bi = (b >> (K - 1 - i)) & 1;
+    s += __shfl(outv, 2 * i + bi);
+    if (i < K - 1) {
+      const int bn = (b >> (K - 2 - i)) & 1;
+      s += __shfl(outv, 2 * MAXK + 4 * i + 2 * bi + bn);
+    }
+  }
+  const float mx = wmax(valid ? s : -INFINITY);
+  const float m = valid ? expf(s - mx) : 0.0f;
+  const float nrm = sqrtf(wsum(m * m));
+  msgs[(job * M + e) * 64 + lane] = m / nrm;
 }
 
 // Head weight gradients: workgroup (direction, slice of 64 input rows of Wu (3 slices) or Wp (6 slices));
@@ -705,6 +837,18 @@ int legs_for(int d, const bbp_opts* o, Legs* out) {
   return BBP_OK;
 }
 
+// BF16 input channels per site (C0 padded to 16) and the transposed, padded BF16 weights: [C1][KP1],
+// [C2][KP2], [C3][KP3]
+constexpr int CS0 = 16;
+#ifndef BBP_CONV_WM
+#define BBP_CONV_WM 2
+#endif
+constexpr int CONV_WM = BBP_CONV_WM;   // waves along M in the BF16 convolutions
+constexpr int KP1 = kpad(CS0), KP2 = kpad(C1), KP3 = kpad(C2);
+constexpr int64_t WB1 = (int64_t)C1 * KP1, WB2 = (int64_t)C2 * KP2, WB3 = (int64_t)PROJ_CH * KP3;
+constexpr int64_t WB_TOTAL = WB1 + WB2 + WB3;
+static_assert(CS0 * 2 <= C0 * 4, "BF16 input channels fit the FP32 input slot of the workspace");
+
 // syndromes per forward chunk of bbp_warm_predict (bounds its workspace)
 constexpr int64_t PREDICT_CHUNK = 512;
 
@@ -720,7 +864,7 @@ WLayout wlayout(int d, int64_t jobs, int M, bool train) {
   l.A1 = o; o = a256(o + rows * C1 * 4);
   l.A2 = o; o = a256(o + rows * C2 * 4);
   l.F = o; o = a256(o + rows * C3 * 4);
-  l.Wb = o; o = a256(o + (size_t)(9 * C0 * C1 + 9 * C1 * C2 + 9 * C2 * C3) * 2);   // BF16 convolution weights
+  l.Wb = o; o = a256(o + (size_t)WB_TOTAL * 2 + PROJ_CH * 4);   // BF16 weights (transposed, padded), bias
   if (train) {
     l.dF = o; o = a256(o + rows * C3 * 4);
     l.dA2 = o; o = a256(o + rows * C2 * 4);
@@ -761,27 +905,28 @@ struct Args {
 };
 
 // forward trunk of `jobs` coset jobs starting at syndrome syn / noise rates pdev: features F [rows][C3]
-template <int RELU, bool OUT_BF>
-int conv_bf16(int L, int64_t rows, int cin, int cout, const unsigned short* X, const unsigned short* W,
-              const float* bias, void* Y, hipStream_t st) {
-  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cout + 63) / 64));
-  conv_fwd_bf16<RELU, OUT_BF><<<grid, dim3(256), 0, st>>>(L, rows, cin, cout, X, W, bias, Y);
+template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
+int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short* Wt, const float* bias, void* Y,
+              hipStream_t st) {
+  conv_fwd_bf16<CIN, NT, WM, RELU, OUT_BF><<<dim3((unsigned)((rows + 64 * WM - 1) / (64 * WM))), dim3(256), 0, st>>>(
+      L, rows, X, Wt, bias, Y);
   W_TRY(hipGetLastError());
   return BBP_OK;
 }
 
-// BF16 copies of the convolution weights into the workspace (done per forward call: 199k values)
+// BF16 copies of the convolution weights into the workspace, transposed to [cout][k] with k padded to a
+// multiple of the stage, the last layer composed with the head (done per forward call: about 200k values)
 int weights_bf16(const float* prm, const WLayout& w, char* ws, hipStream_t st) {
   unsigned short* Wb = (unsigned short*)(ws + w.Wb);
-  const int64_t n1 = 9 * C0 * C1, n2 = 9 * C1 * C2, n3 = 9 * C2 * C3;
-  to_bf16_kernel<<<grid1(n1), 256, 0, st>>>(prm + OFF.w1, Wb, n1);
-  to_bf16_kernel<<<grid1(n2), 256, 0, st>>>(prm + OFF.w2, Wb + n1, n2);
-  to_bf16_kernel<<<grid1(n3), 256, 0, st>>>(prm + OFF.w3, Wb + n1 + n2, n3);
+  weights_t_kernel<<<grid1(WB1), 256, 0, st>>>(prm + OFF.w1, C0, CS0, C1, KP1, Wb);
+  weights_t_kernel<<<grid1(WB2), 256, 0, st>>>(prm + OFF.w2, C1, C1, C2, KP2, Wb + WB1);
+  compose_head_kernel<<<grid1(WB3), 256, 0, st>>>(prm, KP3, Wb + WB1 + WB2, (float*)(Wb + WB_TOTAL));
   W_TRY(hipGetLastError());
   return BBP_OK;
 }
 
-// forward trunk in BF16 storage with FP32 accumulation: input channels, A1 and A2 in BF16, F in FP32
+// forward trunk in BF16 storage with FP32 accumulation: input channels, A1 and A2 in BF16; the last layer
+// composed with the head gives the projections [rows][PROJ_CH] in FP32 (in the features' slot)
 int trunk_bf16(int d, const uint8_t* syn, const double* pdev, double p, int64_t jobs, char* ws, const WLayout& w,
                const float* prm, hipStream_t st) {
   const int L = 2 * d - 1;
@@ -789,13 +934,14 @@ int trunk_bf16(int d, const uint8_t* syn, const double* pdev, double p, int64_t 
   unsigned short *X0 = (unsigned short*)(ws + w.X0), *A1 = (unsigned short*)(ws + w.A1),
                  *A2 = (unsigned short*)(ws + w.A2), *Wb = (unsigned short*)(ws + w.Wb);
   float* F = (float*)(ws + w.F);
-  features_kernel<unsigned short><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
+  features_kernel<unsigned short, CS0><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
   W_TRY(hipGetLastError());
   int rc;
-  const int64_t n1 = 9 * C0 * C1, n2 = 9 * C1 * C2;
-  if ((rc = conv_bf16<1, true>(L, rows, C0, C1, X0, Wb, prm + OFF.b1, A1, st))) return rc;
-  if ((rc = conv_bf16<1, true>(L, rows, C1, C2, A1, Wb + n1, prm + OFF.b2, A2, st))) return rc;
-  if ((rc = conv_bf16<0, false>(L, rows, C2, C3, A2, Wb + n1 + n2, prm + OFF.b3, F, st))) return rc;
+  if ((rc = conv_bf16<CS0, C1, CONV_WM, 1, true>(L, rows, X0, Wb, prm + OFF.b1, A1, st))) return rc;
+  if ((rc = conv_bf16<C1, C2, CONV_WM, 1, true>(L, rows, A1, Wb + WB1, prm + OFF.b2, A2, st))) return rc;
+  if ((rc = conv_bf16<C2, PROJ_CH, CONV_WM, 0, false>(L, rows, A2, Wb + WB1 + WB2, (const float*)(Wb + WB_TOTAL), F,
+                                                       st)))
+    return rc;
   return BBP_OK;
 }
 
@@ -804,7 +950,7 @@ int trunk(int d, const uint8_t* syn, const double* pdev, double p, int64_t jobs,
   const int L = 2 * d - 1;
   const int64_t rows = jobs * L * L;
   float *X0 = (float*)(ws + w.X0), *A1 = (float*)(ws + w.A1), *A2 = (float*)(ws + w.A2), *F = (float*)(ws + w.F);
-  features_kernel<float><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
+  features_kernel<float, C0><<<dim3((unsigned)(jobs / 4)), dim3(256), 0, st>>>(syn, pdev, (float)p, d, X0);
   W_TRY(hipGetLastError());
   int rc;
   if ((rc = conv<G_FWD, 1>(L, rows, C0, C1, X0, prm + OFF.w1, A1, prm + OFF.b1, st))) return rc;
@@ -870,9 +1016,13 @@ int bbp_warm_predict(int32_t d, double p, const double* p_dev, const uint8_t* sy
                           : trunk(d, sb, pb, p, jobs, params_dev, (char*)workspace, w, a.st);
     if (rc) return rc;
     if (lg.M > 0) {
-      head_kernel<false><<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
-          (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, nullptr, nullptr, 0.0f,
-          messages_dev + b0 * 4 * lg.M * 64, nullptr, nullptr, nullptr);
+      if (precision == 1)
+        head_proj_kernel<<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
+            (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, messages_dev + b0 * 4 * lg.M * 64);
+      else
+        head_kernel<false><<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
+            (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, nullptr, nullptr, 0.0f,
+            messages_dev + b0 * 4 * lg.M * 64, nullptr, nullptr, nullptr);
       W_TRY(hipGetLastError());
     }
   }

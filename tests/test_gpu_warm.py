@@ -86,9 +86,10 @@ def test_forward_messages_against_oracle(dev, d, k):
 
 @pytest.mark.parametrize("d,k", [(5, 3), (9, 6)])
 def test_bf16_forward_against_oracle(dev, d, k):
-    """Inference precision: BF16 convolution weights, input channels and hidden activations, FP32 sums. The
-    oracle runs the FP64 network with the same BF16 weights and rounds to BF16 at the same storage points
-    (warmnet.trunk(store=round_bf16)). What remains is FP32 against FP64 summation (<= K 2^-24 of the
+    """Inference precision: BF16 convolution weights, input channels and hidden activations, FP32 sums, the last
+    convolution composed with the head (its per-site projections). The oracle runs the same arithmetic in FP64
+    and rounds to BF16 at the same storage points (warmnet.predict_stored(store=round_bf16)), from the FP32
+    parameters as the GPU does. What remains is FP32 against FP64 summation (<= K 2^-24 of the
     absolute sums, K <= 1152: about 1e-4 relative), which can also move a stored value across a BF16
     rounding midpoint -- one BF16 step, 2^-7 relative, at the rare positions where that happens. Both shift
     the scores s(b) by O(1e-3) nats, against score ranges of several nats here. Compared: log m(b) where the
@@ -100,10 +101,6 @@ def test_bf16_forward_against_oracle(dev, d, k):
     _, syn = workload.make_batch(d, 0.1, b, workload="warm", p_index=250 + d)
     ps = np.array([0.07, 0.13])
     th = _theta(d + 1)
-    parts = warmnet.unpack(th.astype(np.float64))
-    for n in ("conv1.W", "conv2.W", "conv3.W"):
-        parts[n] = warmnet.round_bf16(parts[n])
-    th_b = warmnet.pack(parts)
     opts = bbp.default_opts(block=k, chi=32)
     _say(f"[warm bf16 fwd] d={d} k={k}")
     got = warm.predict(d, torch.from_numpy(ps).to(dev), torch.from_numpy(syn).to(dev), opts,
@@ -112,7 +109,7 @@ def test_bf16_forward_against_oracle(dev, d, k):
     plan = blockbp.Plan(d, k, k)
     worst, span = 0.0, 0.0
     for j, X0 in enumerate(_oracle_jobs(d, syn, ps)):
-        ref = warmnet.predict(th_b, X0, d, plan, store=warmnet.round_bf16)
+        ref = warmnet.predict_stored(th.astype(np.float64), X0, d, plan, warmnet.round_bf16)
         g = got[j // 4, j % 4, :plan.M]
         for e in range(plan.M):
             K = len(warmnet.legs(d, plan, e))

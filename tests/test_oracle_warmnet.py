@@ -190,3 +190,20 @@ def test_trunk_store_identity_is_exact():
     a, _ = warmnet.trunk(prm, X0)
     b, _ = warmnet.trunk(prm, X0, store=lambda t: t)
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("d,k", [(5, 3), (7, 4)])
+def test_composed_last_layer_equals_the_network(d, k):
+    """predict_stored with exact storage (the last convolution composed with the head's weights, the head
+    then summing per-site projections) gives the network's own messages: the composition only regroups the
+    head's linear maps."""
+    rng = np.random.default_rng(11 + d)
+    X0, _, _, _ = _job(d, k=k, seed=d)
+    plan = blockbp.Plan(d, k, k)
+    theta = rng.normal(size=warmnet.count(TINY)) * 0.3
+    a = warmnet.predict(theta, X0, d, plan, TINY)
+    b = warmnet.predict_stored(theta, X0, d, plan, lambda t: t, TINY)
+    np.testing.assert_allclose(b, a, rtol=1e-10, atol=1e-13)
+    # and rounding the stored values changes them (the pin is not vacuous)
+    c = warmnet.predict_stored(theta, X0, d, plan, warmnet.round_bf16, TINY)
+    assert np.abs(c - a).max() > 1e-6
