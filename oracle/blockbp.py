@@ -9,8 +9,10 @@ Follows Alg. 1 of the paper (Sec. III.E) and its remarks:
   * a block's outgoing message is the BP update rule (eq. for m_{v->u}, Sec. III.C) evaluated by the
     boundary-MPS method with bond chi inside the block (Sec. III.D, Fig. 3): the sweep starts from the
     message entering on the side opposite the receiver, absorbs the block column by column, and the
-    messages on the two remaining sides enter as end caps of the boundary MPS, one site per column; after
-    every column the boundary MPS is compressed to chi (QR sweep, then truncated-SVD sweep);
+    messages on the two remaining sides enter as end caps of the boundary MPS, one site per column, in the
+    canonical form whose not-yet-absorbed part is an isometry (right-canonical when walked from the first
+    site, left-canonical from the last: this implementation's reading, see block_sweep); after every column
+    the boundary MPS is compressed to chi (QR sweep, then truncated-SVD sweep);
   * outgoing messages are made left-canonical with unit norm (remark 3), damped
     m <- (1-eta) m_new + eta m_old and renormalised (remark 7);
   * schedule: blocks are coloured as a chessboard, colour (I+J) even sends first, then the other colour
@@ -121,12 +123,22 @@ def block_sweep(plan: Plan, tensors, msgs, I: int, J: int, frame: str, chi: int,
     state = [one] + h + [one]
     logscale = np.zeros(batch)
 
+    # The side messages enter with the part still to be absorbed an isometry: a sweep that walks a message
+    # from its first site takes the right-canonical form (weight on site 0), one that walks it from its last
+    # site the stored left-canonical form (weight on the last site). The truncations then see the boundary
+    # state in the metric of the rest of the cap, and the result depends on the message only, not on the
+    # choice of its canonical form (a left-canonical form walked from its first site would put weightless
+    # completion directions -- e.g. those of the rank-1 uniform start -- into every truncation).
+    right = {}
+
     def cap_site(nb, t):
         if not plan.has(nb):
             return one
         m = msgs[(nb, me)]
         if forward:
-            return m[t]
+            if nb not in right:
+                right[nb] = mps.right_canonicalize(m)
+            return right[nb][t]
         return np.swapaxes(m[kt - 1 - t], -1, -3)   # consumed last-site-first: (b_{j+1}, 2, b_j)
 
     for t in range(kt):

@@ -4,7 +4,7 @@ An MPS is a list of site tensors of shape [..., D_left, p, D_right] (end bonds o
 arbitrary leading batch. These are the textbook operations the boundary-MPS method relies on
 (Sec. III.A of the paper; the compression "truncates the bond dimension back to chi using well-established
 MPS methods"):
-  * left_canonicalize: QR sweep from the first site to the last;
+  * left_canonicalize: QR sweep from the first site to the last; right_canonicalize the mirror image;
   * compress: left-canonicalize, then sweep back from the last site keeping, at every bond, the
     min(chi, available) largest singular values (a full SVD where truncation can act, an LQ step where the
     bond cannot exceed chi); the norm is split off as a log-scale;
@@ -51,6 +51,20 @@ def left_canonicalize(sites):
         q, r = np.linalg.qr(A.reshape(b + (Dl * p, Dr)))
         sites[i] = q.reshape(b + (Dl, p, q.shape[-1]))
         sites[i + 1] = np.einsum("...kd,...dpe->...kpe", r, sites[i + 1])
+    return sites
+
+
+def right_canonicalize(sites):
+    """LQ sweep last -> first; every site but the first becomes a co-isometry (right-canonical) and the
+    first carries the whole weight."""
+    sites = list(sites)
+    for i in range(len(sites) - 1, 0, -1):
+        A = sites[i]
+        b = A.shape[:-3]
+        Dl, p, Dr = A.shape[-3:]
+        q, r = np.linalg.qr(np.swapaxes(A.reshape(b + (Dl, p * Dr)), -1, -2))   # A = r^T q^T
+        sites[i] = np.swapaxes(q, -1, -2).reshape(b + (q.shape[-1], p, Dr))
+        sites[i - 1] = np.einsum("...apk,...jk->...apj", sites[i - 1], r)
     return sites
 
 

@@ -2,12 +2,16 @@
 code (test helper; not collected by pytest).
 
 The boundary state of the in-block sweep is held as one dense array psi[top cap][h_0 .. h_{k-1}][bottom cap]
-instead of an MPS. The side messages enter through their own legs: a K-site message m(v_0..v_{K-1}) is
-read as the product-of-identities MPS whose bond j carries the legs v_0..v_{j-1} for j <= K//2 and the legs
-v_j..v_{K-1} above that, with the whole vector sitting on site K//2. For j <= K/2 this bond basis is related
-to the left-canonical one by an orthogonal map, so truncations that act while both caps sit at such bonds
-give the same state as the canonical MPS algorithm. Truncation is applied cut by cut from the bottom end
-as best rank-chi approximations of the dense state (what the MPS compression computes).
+instead of an MPS. Two readings of the side messages' legs are offered:
+  * caps="open": a K-site message m(v_0..v_{K-1}) is read as the product-of-identities MPS whose bond j
+    carries the legs v_0..v_{j-1} for j <= K//2 and the legs v_j..v_{K-1} above that, with the whole vector
+    sitting on site K//2 (small caps; exact contractions only, i.e. while chi truncates nothing);
+  * caps="remaining": the cap index is the tuple of the message legs not yet absorbed, and the whole
+    message is applied when its first leg is absorbed. The part of the cap still to be absorbed is then
+    the identity -- an isometry -- so this is the gauge-free form of a cap whose remaining sites are
+    canonical, and the truncations below act in the metric of the rest of the cap.
+Truncation is applied cut by cut from the bottom end as best rank-chi approximations of the dense state
+(what the MPS compression computes).
 """
 import numpy as np
 
@@ -32,28 +36,37 @@ def frame_tensor(block, frame, t, i):
     return out
 
 
-def canonical_sites(msg, K):
-    """Left-canonical MPS of a dense K-site message with bonds min(2^j, 2^(K-j)) (successive QR)."""
-    sites = []
-    rest = np.asarray(msg, dtype=np.float64).reshape(1, -1)
-    for j in range(K - 1):
-        b = rest.shape[0]
-        q, r = np.linalg.qr(rest.reshape(2 * b, -1))
-        sites.append(q.reshape(b, 2, q.shape[1]))
-        rest = r
-    sites.append(rest.reshape(rest.shape[0], 2, 1))
-    return sites
+def remaining_cap_operator(msg, K, js, forward):
+    """caps="remaining": [old cap, emitted leg, new cap] with the cap index the legs still to be absorbed
+    (first leg most significant); the message itself is applied at the first absorbed site."""
+    m = np.asarray(msg, dtype=np.float64)
+    if forward:
+        if js == 0:                                   # () -> (v_1..v_{K-1})
+            return m.reshape(1, 2, 2 ** (K - 1))
+        r = 2 ** (K - js - 1)                         # (v_js..) -> (v_{js+1}..)
+        op = np.zeros((2 * r, 2, r))
+        for v in range(2):
+            for b in range(r):
+                op[v * r + b, v, b] = 1
+        return op
+    if js == K - 1:                                   # () -> (v_0..v_{K-2})
+        return np.transpose(m.reshape(2 ** (K - 1), 2, 1), (2, 1, 0))
+    r = 2 ** js                                       # (v_0..v_js) -> (v_0..v_{js-1})
+    op = np.zeros((2 * r, 2, r))
+    for a in range(r):
+        for v in range(2):
+            op[2 * a + v, v, a] = 1
+    return op
 
 
-def cap_operator(msg, K, js, forward, canonical=False):
+def cap_operator(msg, K, js, forward, caps="open"):
     """Operator [old cap, emitted leg, new cap] for absorbing site js of a K-site side message."""
     if msg is None:
         op = np.zeros((1, 2, 1))
         op[0, 0, 0] = 1.0
         return op
-    if canonical:
-        A = canonical_sites(msg, K)[js]
-        return A if forward else np.transpose(A, (2, 1, 0))
+    if caps == "remaining":
+        return remaining_cap_operator(msg, K, js, forward)
     D = K // 2
     m = np.asarray(msg, dtype=np.float64).reshape(2 ** D, 2, 2 ** (K - D - 1))
     if forward:
@@ -87,12 +100,10 @@ def cap_operator(msg, K, js, forward, canonical=False):
     return op
 
 
-def dense_update(block, frame, init, top, bottom, chi, canonical=False):
+def dense_update(block, frame, init, top, bottom, chi, caps="open"):
     """One BP message update of a block (its tensors block[r][c], legs (up, left, down, right)) toward side
-    `frame`, with incoming dense messages (None where the neighbour is absent). With canonical=True the side
-    messages enter through their left-canonical MPS sites (valid for any chi); otherwise through the
-    open-leg reading above (valid while no truncation acts with a cap past the middle bond).
-    Returns (outgoing dense message, natural log of the split-off scale)."""
+    `frame`, with incoming dense messages (None where the neighbour is absent), the side messages read as
+    `caps` says (module docstring). Returns (outgoing dense message, natural log of the split-off scale)."""
     kr, kc = len(block), len(block[0])
     kt, kp = (kc, kr) if frame in "EW" else (kr, kc)
     forward = frame in "ES"
@@ -105,14 +116,14 @@ def dense_update(block, frame, init, top, bottom, chi, canonical=False):
     logscale = 0.0
     for t in range(kt):
         js = t if forward else kt - 1 - t
-        psi = np.einsum("n...,nvq->qv...", psi, cap_operator(top, kt, js, forward, canonical))   # [n', v, h.., s]
+        psi = np.einsum("n...,nvq->qv...", psi, cap_operator(top, kt, js, forward, caps))   # [n', v, h.., s]
         for i in range(kp):
             F = frame_tensor(block, frame, t, i)
             src = "nv" + "".join(hl) + "s"
             dst = "nw" + "".join("o" if j == i else hl[j] for j in range(kp)) + "s"
             psi = np.einsum(f"{src},v{hl[i]}wo->{dst}", psi, F)
         psi = np.moveaxis(psi, 1, -2)                                               # [n', h', v, s]
-        psi = np.einsum("...vs,svq->...q", psi, cap_operator(bottom, kt, js, forward, canonical))
+        psi = np.einsum("...vs,svq->...q", psi, cap_operator(bottom, kt, js, forward, caps))
         shape = psi.shape
         for cut in range(kp + 1, 0, -1):
             mat = psi.reshape(int(np.prod(shape[:cut])), -1)

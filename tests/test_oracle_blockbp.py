@@ -167,16 +167,63 @@ def test_sixbysix_block_never_truncates_at_chi_16(frame, chi):
 
 @pytest.mark.parametrize("frame", ["E", "W", "S", "N"])
 @pytest.mark.parametrize("chi", [8, 12])
-def test_truncating_sweep_matches_dense_state_with_canonical_caps(frame, chi):
-    # below rank 16 the truncation acts; the MPS sweep must then equal the dense-state formulation whose
-    # side messages enter through their left-canonical sites (the cap metric of remark 3)
+def test_truncating_sweep_is_sequential_best_rank_truncation_of_the_dense_state(frame, chi):
+    # below rank 16 the truncation acts; the MPS sweep must then equal the dense state truncated cut by
+    # cut from the bottom to its best rank-chi approximation, with every cap indexed by the message legs it
+    # has not absorbed yet (the gauge-free form of a cap whose remaining part is an isometry)
     seed = 3 + chi + ord(frame)
     got, args, _ = _interior_6x6(chi, frame, seed)
-    dense, ld = dense_update(*args, chi, canonical=True)
+    dense, ld = dense_update(*args, chi, caps="remaining")
     scale = np.abs(got).max()
     np.testing.assert_allclose(got, dense * np.exp(ld), rtol=1e-7, atol=1e-9 * scale)
     exact, _, _ = _interior_6x6(4096, frame, seed)
     assert np.abs(exact - got).max() > 1e-6 * scale          # the truncation really acted
+
+
+def _uniform_caps(plan, I, J, chi, kind, rng):
+    """The uniform start message of every neighbour of block (I, J) in one of three exact left-canonical
+    forms: as the oracle builds it (zero-padded product), from the dense vector by successive QR, and the
+    first with a random orthogonal gauge on every bond."""
+    me = (I, J)
+    msgs = {}
+    for side, (dI, dJ) in blockbp.DIRS.items():
+        nb = (I + dI, J + dJ)
+        if not plan.has(nb):
+            continue
+        K = plan.msg_len(nb, me)
+        if kind == "dense":
+            v = np.full((1, 2 ** K), 2.0 ** (-K / 2))
+            msgs[(nb, me)], _ = mps.canonical_message(mps.from_dense(v, [2] * K), chi)
+            continue
+        m = [x.copy() for x in mps.uniform([2] * K, chi, (1,))]
+        if kind == "gauge":
+            for j in range(K - 1):
+                G, _ = np.linalg.qr(rng.normal(size=(m[j].shape[-1],) * 2))
+                m[j] = np.einsum("...apb,bc->...apc", m[j], G)
+                m[j + 1] = np.einsum("cb,...bpe->...cpe", G.T, m[j + 1])
+        msgs[(nb, me)] = m
+    return msgs
+
+
+@pytest.mark.parametrize("frame", ["E", "W", "S", "N"])
+def test_truncating_sweep_does_not_depend_on_the_canonical_form_of_its_caps(frame):
+    # the uniform start is rank 1 at every bond, so its left-canonical sites hold weightless completion
+    # directions that differ between exact constructions; the truncated sweep must not see them (chi = 4:
+    # with product caps the boundary rank stays within 8)
+    d, chi = 7, 4
+    _, s = workload.make_batch(d, 0.1, 1)
+    tensors = [[t[:1] for t in row] for row in _coset_tensors(d, s, 0.1)]
+    plan = blockbp.Plan(d, 6, 6)
+    rng = np.random.default_rng(ord(frame))
+    outs = []
+    for kind in ("pad", "dense", "gauge"):
+        out, ls = blockbp.block_sweep(plan, tensors, _uniform_caps(plan, 1, 1, chi, kind, rng), 1, 1, frame, chi, (1,))
+        outs.append(mps.to_dense(out)[0] * np.exp(ls[0]))
+    scale = np.abs(outs[0]).max()
+    for o in outs[1:]:
+        np.testing.assert_allclose(o, outs[0], rtol=0, atol=1e-11 * scale)
+    exact, _ = blockbp.block_sweep(plan, tensors, _uniform_caps(plan, 1, 1, 4096, "pad", rng), 1, 1, frame, 4096, (1,))
+    assert np.abs(mps.to_dense(exact)[0] * np.exp(_[0]) - outs[0]).max() > 1e-6 * scale   # truncation acted
 
 
 def test_lemma_matches_direct_bethe_free_energy():
