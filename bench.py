@@ -58,6 +58,8 @@ def _short_kernel_name(name):
     m = re.search(r"sweep_kernel<(true|false), (\d+(?:, (?:true|false)){4}), false>", name)
     if m:
         return f"sweep_kernel{'_bf16' if m.group(1) == 'true' else ''}<{m.group(2)}>"
+    if "trunc_sweep_kernel" in name:
+        return "trunc_sweep_kernel"
     return "bmps_kernel<double>" if "bmps_kernel<double>" in name else name
 
 
@@ -235,12 +237,17 @@ def main():
     ap.add_argument("--precision", type=int, choices=(0, 1), default=1,
                     help="1 (default): the middle-site contractions on the matrix cores in BF16 with FP32 "
                          "accumulation, FP32 elsewhere; 0: FP32 throughout")
-    ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased", "bmps", "schedule"), default="d17",
+    ap.add_argument("--workload", choices=("d17", "mixed", "warm", "biased", "bmps", "schedule", "trunc"),
+                    default="d17",
                     help="d17: the headline workload (default); mixed: 8192 syndromes of mixed distance; warm: "
                          "learned warm start against the uniform start at d=25, p=0.10; biased: d=17 under "
                          "Z-biased Pauli noise (p=0.10, bias 10); bmps: the single-block limit (boundary-MPS "
                          "decoder, chi 16) on the d17 syndromes; schedule: iteration and threshold variants "
-                         "at d=17, p=0.05 and 0.10, against the bMPS reference")
+                         "at d=17, p=0.05 and 0.10, against the bMPS reference; trunc: block sweeps with a "
+                         "binding chi (6x6 blocks at chi 8, 8x8 blocks at chi 16) on the first --trunc-batch "
+                         "d17 syndromes")
+    ap.add_argument("--trunc-batch", type=int, default=1024,
+                    help="syndromes of the trunc workload (default 1024, the first of the d17 batch)")
     ap.add_argument("--block", type=int, default=6, choices=range(1, 7),
                     help="block size k of the d17 workload (default 6; 1 = plain BP between single tensors)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -293,6 +300,8 @@ def main():
         return bmps_main(a)
     if a.workload == "schedule":
         return schedule_main(a)
+    if a.workload == "trunc":
+        return trunc_main(a)
 
     d, p, block, chi, max_iter = 17, 0.10, a.block, 32, 20
     errors, syn = workload.make_batch(d, p, a.batch, workload="d17")
@@ -602,6 +611,78 @@ def bmps_main(a):
     )
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = bmps_cpu_baseline(d, p, chi)
+    print(json.dumps(line), flush=True)
+
+
+def trunc_main(a):
+    """Block sweeps with a binding chi (Sec. III.D): the first --trunc-batch syndromes of the d=17, p=0.10
+    workload decoded with (i) 6x6 blocks at chi 8 -- the sweeps whose boundary rank (16) exceeds chi run the
+    truncating kernel, the others the exact dense kernels -- and (ii) 8x8 blocks at chi 16, where every sweep
+    truncates. Per variant: syndromes/s over --steps decodes (each with HIP events per launch), the truncating
+    kernel's FP64 rate (flops of the QR, reflection and SVD work at the padded sizes it executes, see
+    plan.cpp), decisions against the headline decoder (6x6 blocks, chi 32, exact) and logical failures."""
+    import numpy as np
+    import torch
+
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import _lib, workload
+
+    d, p, count = 17, 0.10, a.trunc_batch
+    errors, syn = workload.make_batch(d, p, 4096, workload="d17")
+    errors, syn = errors[:count], syn[:count]
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(np.ascontiguousarray(syn)).to(dev)
+    base = dict(max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
+    ref = bbp.decode_device(d, p, s, bbp.default_opts(block=6, chi=32, **base))
+    torch.cuda.synchronize()
+    cref = ref["coset"].cpu().numpy()
+    fref = logical_failures(d, errors, ref["correction"].cpu().numpy())
+    legs = []
+    for block, chi in [(6, 8), (8, 16)]:
+        opts = bbp.default_opts(block=block, chi=chi, **base)
+        info = bbp.plan_query(d, opts)
+        ws = torch.empty(bbp.workspace_size(d, count, opts), dtype=torch.uint8, device=dev)
+        out = bbp.decode_device(d, p, s, opts, workspace=ws)
+        for _ in range(a.warmup):
+            out = bbp.decode_device(d, p, s, opts, workspace=ws)
+        torch.cuda.synchronize()
+        tms = tfl = 0.0
+        tl = 0
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            out = bbp.decode_device(d, p, s, opts, workspace=ws, timing=True)
+            tm = out["timing"]
+            if tm.top_class == _lib.TRUNC_CLASS:
+                tms += tm.top_ms
+                tl += tm.top_launches
+                tfl += tm.top_flops
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        c = out["coset"].cpu().numpy()
+        f = logical_failures(d, errors, out["correction"].cpu().numpy())
+        ach = tfl / (tms * 1e-3) / 1e12 if tms > 0 else 0.0
+        legs.append(dict(
+            block=block, chi=chi, value=count * a.steps / elapsed, unit="syndromes/s",
+            ms_per_step=1e3 * elapsed / a.steps, truncating_sweeps=info.truncating_sweeps,
+            message_stride=info.message_stride, max_cut_rank=info.max_cut_rank,
+            mean_iterations_per_coset=out["iters"].double().mean().item(),
+            kernel=dict(name="trunc_sweep_kernel", bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                        frac=ach / PEAK_FP64_TFLOPS, avg_launch_ms=tms / max(tl, 1), launches=tl,
+                        flops_per_launch=tfl / max(tl, 1)),
+            decisions_equal_to_exact_chi32=float((c == cref).mean()),
+            logical_failures=[int(f.sum()), count, list(wilson(int(f.sum()), count))]))
+        del ws
+    line = dict(
+        metric=f"syndromes decoded/s at d={d} with truncating block sweeps (1 GPU)",
+        value=legs[0]["value"], unit="syndromes/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=legs[0]["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64 (truncating sweeps) / f32 (exact sweeps, messages)", data="synthetic",
+        config=dict(workload=f"the first {count} syndromes of the d17 workload (d={d}, p={p}); blockBP with 6x6 "
+                             "blocks at chi 8 (value) and 8x8 blocks at chi 16, <= 20 iterations, early exit",
+                    batch=count, parallelism="single GPU"),
+        variants=legs,
+        exact_chi32_logical_failures=[int(fref.sum()), count, list(wilson(int(fref.sum()), count))],
+    )
     print(json.dumps(line), flush=True)
 
 

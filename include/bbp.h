@@ -107,6 +107,11 @@ typedef struct bbp_plan_info {
   int32_t gpu_supported;         /* 1: bbp_decode_device accepts these options */
   double flops_per_iter;
   double flops_bethe;
+  int32_t truncating_sweeps;     /* sweeps (BP rounds and closing) that run in the truncating kernel: those whose
+                                    boundary MPS can exceed chi, and every sweep of a plan with blocks wider than
+                                    6; their flops count QR, reflection and SVD work (see below) */
+  int32_t message_stride;        /* S: floats per stored dense message, 2^max(6, widest block); the message
+                                    arrays of bbp_decode_device and bbp_group are [batch][4][M][S] */
 } bbp_plan_info;
 int bbp_plan_query(int32_t d, const bbp_opts* opts, bbp_plan_info* info);
 
@@ -143,13 +148,18 @@ typedef struct bbp_timing {
  *   iters_dev       [batch][4] int32: BP iterations run
  *   coset_dev       [batch] uint8: decided coset
  *   correction_dev  [batch][n] uint8: codes x + 2z of the correction f_s L*
- *   messages_dev    optional [batch][4][M][64] float32: final dense messages (unit norm; entry index
- *                   = crossing-bond values, first site most significant); NULL to skip
+ *   messages_dev    optional [batch][4][M][S] float32: final dense messages (unit norm; entry index
+ *                   = crossing-bond values, first site most significant; S = message_stride of
+ *                   bbp_plan_query, 64 unless a block is wider than 6); NULL to skip
  *   stream          hipStream_t on which all work is enqueued (NULL = default stream); the call
  *                   returns after enqueueing unless `timing` is non-NULL.
  * All pointers are caller-owned; nothing is allocated per call (plans are cached per (d, opts) on first
- * use). Errors: BBP_EINVAL (bad sizes, NULL required pointer, workspace too small), BBP_EUNSUPPORTED
- * (options whose truncation the GPU path does not implement), BBP_EHIP.
+ * use). Block sweeps whose boundary MPS can exceed chi (and every sweep of a plan with blocks wider than 6)
+ * run the boundary-MPS compression of Sec. III.D on the device: a Householder QR sweep and a truncated
+ * one-sided Jacobi SVD sweep after every column, in FP64, with each side message entering with its
+ * not-yet-absorbed part an isometry; the others contract exactly. Errors: BBP_EINVAL (bad sizes, NULL required
+ * pointer, workspace too small), BBP_EUNSUPPORTED (blocks wider than 8; chi below 2^(k/2), which would
+ * truncate the messages themselves; chi above 16 where a sweep needs the truncating kernel), BBP_EHIP.
  */
 int bbp_decode_device(int32_t d, double p, const uint8_t* syndromes_dev, int64_t batch,
                       const bbp_opts* opts, void* workspace, size_t workspace_bytes,
@@ -198,11 +208,11 @@ typedef struct bbp_group {
   int32_t* iters_dev;             /* [batch][4] */
   uint8_t* coset_dev;             /* [batch] */
   uint8_t* correction_dev;        /* [batch][d^2 + (d-1)^2] */
-  const float* init_messages_dev; /* optional [batch][4][M][64] start messages (dense, layout of messages_dev of
+  const float* init_messages_dev; /* optional [batch][4][M][S] start messages (dense, layout of messages_dev of
                                      bbp_decode_device), each scaled to unit norm by the decoder, entries beyond
                                      2^K ignored, an all-zero or non-finite one replaced by the uniform start;
                                      NULL = the uniform start of remark 2 */
-  float* messages_dev;            /* optional [batch][4][M][64] output: final messages, as in bbp_decode_device */
+  float* messages_dev;            /* optional [batch][4][M][S] output: final messages, as in bbp_decode_device */
   double noise[4];                /* optional biased Pauli noise: probabilities of I, X, Z, Y (index = code x + 2z),
                                      non-negative, summing to 1, noise[0] > 0; all zero = depolarizing with p.
                                      Exclusive with p_dev; opts->precision 0 only (else BBP_EUNSUPPORTED). */

@@ -97,8 +97,9 @@ def decode_device(d: int, p: float, syndromes, opts: bbp_opts, *, workspace=None
         out = {k: v for k, v in out.items() if k in ("loglik", "delta", "iters", "coset", "correction")}
     msg_ptr = None
     if messages:
-        M = plan_query(d, opts).num_messages
-        out["messages"] = torch.empty((batch, 4, max(M, 1), 64), dtype=torch.float32, device=dev)
+        info = plan_query(d, opts)
+        out["messages"] = torch.empty((batch, 4, max(info.num_messages, 1), info.message_stride),
+                                      dtype=torch.float32, device=dev)
         msg_ptr = out["messages"].data_ptr()
     st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
     tm = bbp_timing() if timing else None
@@ -192,10 +193,11 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
     uint8 CUDA tensor [batch, 2d(d-1)], p a float (depolarizing rate), a float64 CUDA tensor [batch] of
     per-syndrome depolarizing rates or a 4-sequence of Pauli probabilities (I, X, Z, Y) for biased noise,
     chi the group's bond dimension (0 or absent: opts.chi) and init optional start messages (float32
-    CUDA tensor [batch, 4, M, 64], e.g. from warm.predict; None: the uniform start). Returns (list of
+    CUDA tensor [batch, 4, M, S] with S the plan's message_stride, e.g. from warm.predict; None: the uniform
+    start). Returns (list of
     per-group output dicts as in decode_device, workspace, bbp_timing or None). `outs` (from an earlier
     call with the same groups) receives the results in place, keeping graph-mode arguments identical.
-    messages=True adds each group's final messages [batch, 4, M, 64] as 'messages'."""
+    messages=True adds each group's final messages [batch, 4, M, S] as 'messages'."""
     import torch
 
     gs = (bbp_group * len(groups))()
@@ -231,7 +233,8 @@ def decode_groups(groups, opts: bbp_opts, *, workspace=None, timing: bool = Fals
         msg_ptr = None
         if messages:
             if "messages" not in o:
-                o["messages"] = torch.empty((b, 4, max(plan_query(d, _with_chi(opts, chi)).num_messages, 1), 64),
+                info = plan_query(d, _with_chi(opts, chi))
+                o["messages"] = torch.empty((b, 4, max(info.num_messages, 1), info.message_stride),
                                             dtype=torch.float32, device=dev)
             msg_ptr = o["messages"].data_ptr()
         gs[k] = bbp_group(d, chi, p_val, p_ptr, syn.data_ptr(), b, o["loglik"].data_ptr(), o["delta"].data_ptr(),

@@ -48,6 +48,7 @@ class bbp_plan_info(C.Structure):
         ("num_messages", C.c_int32), ("updates_per_iter", C.c_int32), ("exact_sweeps", C.c_int32),
         ("max_cut_rank", C.c_int32), ("gpu_supported", C.c_int32),
         ("flops_per_iter", C.c_double), ("flops_bethe", C.c_double),
+        ("truncating_sweeps", C.c_int32), ("message_stride", C.c_int32),
     ]
 
 
@@ -59,9 +60,15 @@ class bbp_timing(C.Structure):
     ]
 
 
+TRUNC_CLASS = 1 << 12   # class code of the truncating block sweeps (trunc_sweep.hip)
+
+
 def sweep_kernel_name(cls: int, precision: int = 0) -> str:
     """Kernel instantiation of a sweep class code (see bbp_timing.top_class): sweep_kernel<...> for FP32,
-    sweep_kernel_bf16<...> for the BF16 matrix-core variant of precision mode 1."""
+    sweep_kernel_bf16<...> for the BF16 matrix-core variant of precision mode 1, trunc_sweep_kernel for the
+    truncating sweeps (FP64 at either precision)."""
+    if cls == TRUNC_CLASS:
+        return "trunc_sweep_kernel"
     q00, single, bot, top, kt = cls & 1, (cls >> 1) & 1, (cls >> 2) & 1, (cls >> 3) & 1, (cls >> 4) + 1
     b = lambda v: "true" if v else "false"
     return f"sweep_kernel{'_bf16' if precision else ''}<{kt}, {b(top)}, {b(bot)}, {b(single)}, {b(q00)}>"

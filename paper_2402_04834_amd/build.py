@@ -27,7 +27,7 @@ FLAGS = [
 
 # (source, extra flags, object name)
 UNITS = [("plan.cpp", [], "plan.o"), ("bbp.hip", [], "bbp.o"), ("warm.hip", [], "warm.o"),
-         ("small_sweep.hip", [], "small_sweep.o"), ("bmps.hip", [], "bmps.o")] + [
+         ("small_sweep.hip", [], "small_sweep.o"), ("bmps.hip", [], "bmps.o"), ("trunc_sweep.hip", [], "trunc_sweep.o")] + [
     ("sweep_kernel.hip", [f"-DBBP_KT={k}"], f"sweep_k{k}.o") for k in range(1, 7)
 ]
 

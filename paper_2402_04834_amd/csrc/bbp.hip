@@ -80,25 +80,29 @@ __global__ __launch_bounds__(256) void labels_kernel(const uint8_t* __restrict__
 // start messages: uniform unit vectors (remark 2), or the given ones (a learned warm start) scaled to unit
 // norm with the entries beyond 2^K cleared; one workgroup per job, one wavefront per message
 __global__ __launch_bounds__(256) void init_kernel(float* __restrict__ msgs, const float* __restrict__ given,
-                                                   const int32_t* __restrict__ edge_len, int M, int64_t jobs,
+                                                   const int32_t* __restrict__ edge_len, int M, int ms, int64_t jobs,
                                                    int32_t* __restrict__ conv, int32_t* __restrict__ iters,
                                                    double* __restrict__ terms) {
   const int64_t job = blockIdx.x;
   const int lane = threadIdx.x & 63;
   for (int id = threadIdx.x >> 6; id < M; id += blockDim.x >> 6) {
     const int K = edge_len[id];
-    const bool in = lane < (1 << K);
-    const int64_t at = (job * M + id) * MSTRIDE + lane;
-    float v;
+    const int64_t at = (job * M + id) * ms;
+    float ss = 0.0f;
     if (given) {
-      const float g = in ? given[at] : 0.0f;
-      float ss = g * g;
+      for (int e = lane; e < ms; e += 64) {
+        const float g = e < (1 << K) ? given[at + e] : 0.0f;
+        ss += g * g;
+      }
       for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-      v = (ss > 0.0f && ss < INFINITY) ? g * __builtin_amdgcn_rsqf(ss) : (in ? exp2f(-0.5f * K) : 0.0f);
-    } else {
-      v = in ? exp2f(-0.5f * K) : 0.0f;
     }
-    msgs[at] = v;
+    const bool ok = given && ss > 0.0f && ss < INFINITY;
+    for (int e = lane; e < ms; e += 64) {
+      const bool in = e < (1 << K);
+      float v = in ? exp2f(-0.5f * K) : 0.0f;
+      if (ok) v = in ? given[at + e] * __builtin_amdgcn_rsqf(ss) : 0.0f;
+      msgs[at + e] = v;
+    }
     if (lane == 0) terms[job * M + id] = INFINITY;   // never updated: counts as changed for a gated schedule
   }
   if (threadIdx.x == 0) {
@@ -126,7 +130,7 @@ __global__ void delta_kernel(const double* __restrict__ terms, int M, int64_t jo
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ lnW, int nblocks,
-                                                       const float* __restrict__ msgs, int M,
+                                                       const float* __restrict__ msgs, int M, int ms,
                                                        const int32_t* __restrict__ pairs, int npairs,
                                                        const uint8_t* __restrict__ labels, int d,
                                                        const double* __restrict__ delta_ws,
@@ -150,11 +154,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
       const double w = lnW[job * nblocks + blk];
       if (isnan(w)) bad = 1; else acc += w;
     }
-    const float* mb = msgs + job * M * MSTRIDE;
+    const float* mb = msgs + job * M * (int64_t)ms;
     for (int q = 0; q < npairs; ++q) {
-      const float* u = mb + pairs[2 * q] * MSTRIDE;
-      const float* v = mb + pairs[2 * q + 1] * MSTRIDE;
-      const double o = wave_sum_d((double)u[lane] * (double)v[lane]);
+      const float* u = mb + pairs[2 * q] * (int64_t)ms;
+      const float* v = mb + pairs[2 * q + 1] * (int64_t)ms;
+      double uv = 0.0;
+      for (int e = lane; e < ms; e += 64) uv += (double)u[e] * (double)v[e];
+      const double o = wave_sum_d(uv);
       if (o > 0.0) acc -= (lane == 0) ? log(o) : 0.0;
       else bad = 1;
     }
@@ -244,6 +250,7 @@ hipError_t bbp::launch_labels(hipStream_t st, const uint8_t* syn, int d, int64_t
 }
 
 hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
+  if (cls == bbp::TRUNC_CLASS) return launch_trunc_sweeps(st, a);
   if (a.small) return launch_small_sweeps(st, a);
   bool biased = false;
   for (int k = 0; k < a.ngroups; ++k) biased |= a.g[k].biased != 0;
@@ -325,8 +332,13 @@ int device_plan(int d, const bbp_opts* o, DevPlan** out) {
 }
 
 struct Layout {
-  size_t labels, msgs, terms, lnw, conv, iters, delta, total;
+  size_t labels, msgs, terms, lnw, conv, iters, delta, tws, total;
+  int64_t tws_slots;   // items per launch of the truncating kernel (0: the plan has no truncating sweeps)
 };
+
+// Workspace slots of the truncating kernel: one per item of its largest launch, at most this many (larger
+// launches run in chunks).
+constexpr int64_t TRUNC_SLOTS_MAX = 4096;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -335,12 +347,20 @@ Layout layout(const bbp::Plan& p, int64_t batch) {
   Layout l;
   size_t off = 0;
   l.labels = off; off = align256(off + jobs * p.L * p.L);
-  l.msgs = off; off = align256(off + jobs * std::max(p.M, 1) * MSTRIDE * sizeof(float));
+  l.msgs = off; off = align256(off + jobs * std::max(p.M, 1) * (size_t)p.mstride * sizeof(float));
   l.terms = off; off = align256(off + jobs * std::max(p.M, 1) * sizeof(double));
   l.lnw = off; off = align256(off + jobs * p.nblocks * sizeof(double));
   l.conv = off; off = align256(off + jobs * sizeof(int32_t));
   l.iters = off; off = align256(off + jobs * sizeof(int32_t));
   l.delta = off; off = align256(off + jobs * sizeof(double));
+  int per_job = 0;   // largest number of truncating sweeps in one launch list
+  for (int c = 0; c < 3; ++c) {
+    int n = 0;
+    for (const SweepDesc& s : (c < 2 ? p.round[c] : p.bethe)) n += s.trunc ? 1 : 0;
+    per_job = std::max(per_job, n);
+  }
+  l.tws_slots = std::min<int64_t>((int64_t)jobs * per_job, TRUNC_SLOTS_MAX);
+  l.tws = off; off = align256(off + (size_t)l.tws_slots * bbp::trunc_slot_bytes());
   l.total = off;
   return l;
 }
@@ -400,6 +420,7 @@ struct GroupRun {
   float* msgs = nullptr;
   double *terms = nullptr, *lnw = nullptr, *delta = nullptr;
   int32_t *conv = nullptr, *iters = nullptr;
+  double* tws = nullptr;   // truncating-kernel workspace (lay.tws_slots slots)
   int64_t jobs = 0;
   int biased = 0;
 };
@@ -512,7 +533,8 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
     if ((rc = begin_mark(st, 0, -1, -1))) return rc;
     labels_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(g.in.syndromes_dev, g.in.d, g.in.batch, g.labels);
     init_kernel<<<dim3((unsigned)g.jobs), dim3(256), 0, st>>>(g.msgs, g.in.init_messages_dev, g.dp->edge_len,
-                                                              g.dp->plan.M, g.jobs, g.conv, g.iters, g.terms);
+                                                              g.dp->plan.M, g.dp->plan.mstride, g.jobs, g.conv,
+                                                              g.iters, g.terms);
     HIP_TRY(hipGetLastError());
     if ((rc = end_mark(st))) return rc;
   }
@@ -571,6 +593,18 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
         G.pdev = g.in.p_dev;
         G.biased = g.biased;
         for (int k = 0; k < 4; ++k) G.pi[k] = (float)g.in.noise[k];
+        if (g.biased) {
+          for (int k = 0; k < 4; ++k) G.pq[k] = g.in.noise[k];
+        } else {
+          G.pq[0] = 1.0 - g.in.p;
+          G.pq[1] = G.pq[2] = G.pq[3] = g.in.p / 3.0;
+        }
+        G.mstride = g.dp->plan.mstride;
+        G.chi = g.opts.chi;
+        if (c == bbp::TRUNC_CLASS && !sa.tws) {
+          sa.tws = g.tws;
+          sa.tws_slots = g.lay.tws_slots;
+        }
         items += g.jobs * (int64_t)r.count;
       }
       sa.items = items;
@@ -608,7 +642,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
     const bbp::Plan& P = g.dp->plan;
     if ((rc = begin_mark(st, 0, -1, -1))) return rc;
     finalize_kernel<<<dim3((unsigned)g.in.batch), dim3(256), 0, st>>>(
-        g.lnw, P.nblocks, g.msgs, P.M, g.dp->pairs, (int)(P.pair_ids.size() / 2), g.labels, g.in.d, g.delta, g.iters,
+        g.lnw, P.nblocks, g.msgs, P.M, P.mstride, g.dp->pairs, (int)(P.pair_ids.size() / 2), g.labels, g.in.d, g.delta, g.iters,
         opts->delta1, opts->rule, g.in.loglik_dev, g.in.delta_dev, g.in.iters_dev, g.in.coset_dev,
         g.in.correction_dev);
     HIP_TRY(hipGetLastError());
@@ -616,7 +650,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
   }
   for (auto& g : gr)
     if (g.in.messages_dev && g.in.batch > 0 && g.dp->plan.M > 0)
-      HIP_TRY(hipMemcpyAsync(g.in.messages_dev, g.msgs, (size_t)g.jobs * g.dp->plan.M * MSTRIDE * sizeof(float),
+      HIP_TRY(hipMemcpyAsync(g.in.messages_dev, g.msgs, (size_t)g.jobs * g.dp->plan.M * g.dp->plan.mstride * sizeof(float),
                              hipMemcpyDeviceToDevice, st));
   return BBP_OK;
 }
@@ -701,6 +735,7 @@ int decode_groups(const bbp_group* groups, int ng, const bbp_opts* opts, void* w
     g.conv = (int32_t*)(ws + g.lay.conv);
     g.iters = (int32_t*)(ws + g.lay.iters);
     g.delta = (double*)(ws + g.lay.delta);
+    g.tws = g.lay.tws_slots > 0 ? (double*)(ws + g.lay.tws) : nullptr;
   }
   if (!any) return BBP_OK;
   int dev = 0;
@@ -923,6 +958,7 @@ int decode_noalloc(int32_t d, double p, const uint8_t* syndromes_dev, int64_t ba
   G.lnw = (double*)(ws + G.lay.lnw);
   G.conv = (int32_t*)(ws + G.lay.conv);
   G.iters = (int32_t*)(ws + G.lay.iters);
+  G.tws = G.lay.tws_slots > 0 ? (double*)(ws + G.lay.tws) : nullptr;
   G.delta = (double*)(ws + G.lay.delta);
   Tune tn;
   {
@@ -1028,6 +1064,8 @@ int bbp_plan_query(int32_t d, const bbp_opts* opts, bbp_plan_info* info) {
   info->gpu_supported = p.gpu_ok ? 1 : 0;
   info->flops_per_iter = p.flops_iter;
   info->flops_bethe = p.flops_bethe;
+  info->truncating_sweeps = p.trunc_sweeps;
+  info->message_stride = p.mstride;
   if (!p.gpu_ok) g_err = p.why;
   return BBP_OK;
 }

@@ -300,6 +300,22 @@ double sweep_flops(const Plan& p, const SweepDesc& s) {
   return f;
 }
 
+// Algorithmic flops of one sweep in the truncating kernel (bonds padded to 2 chi_max = 32 before the
+// compression, as the kernel executes them): per column, every crossing site and the top cap is factored by
+// Householder QR of a 64 x 32 matrix (2 m n^2 - 2 n^3 / 3), the reflections are applied to the 32 x 16 carry
+// (4 (64 - j) 16 per reflection j), and every site below the top cap takes one-sided Jacobi SVD of a 32 x 32
+// matrix, counted at six sweeps of 496 rotations (a 2 x 32 product and a 4 x 32 rotation each); the absorption
+// products (R times the column tensor) add 2 x 32 x 32 x 64 per site.
+double trunc_sweep_flops(const SweepDesc& s) {
+  const double qr = 2.0 * 64 * 32 * 32 - 2.0 * 32 * 32 * 32 / 3.0;
+  double apply = 0.0;
+  for (int j = 0; j < 32; ++j) apply += 4.0 * (64 - j) * 16;
+  const double svd = 6.0 * 496 * (2.0 * 32 + 6.0 * 32);
+  const double absorb = 2.0 * 32 * 32 * 64;
+  const double per_site = qr + apply + svd + absorb;
+  return (double)s.kt * (s.kp + 1) * per_site;
+}
+
 }  // namespace
 
 Plan make_plan(int d, int kr, int kc, int chi) {
@@ -393,28 +409,46 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       p.pair_ids.push_back(id[{p.edge_dst[e], p.edge_src[e]}]);
     }
 
-  // rank analysis, once per distinct sweep class
+  // rank analysis, once per distinct sweep class; a sweep whose boundary state can exceed chi is marked for
+  // the truncating kernel, and so is every sweep of a plan with blocks wider than 6 (the dense kernels hold
+  // at most 64 crossing configurations)
+  const int kmax = std::max(*std::max_element(p.rowsz.begin(), p.rowsz.end()),
+                            *std::max_element(p.colsz.begin(), p.colsz.end()));
+  p.mstride = 1 << std::max(6, kmax);
   std::map<std::tuple<int, int, int, int, int, int, int, int>, int> seen;
   Rng rng{0x5eed0fb10cb9ull};
   int worst = 0;
-  auto visit = [&](const SweepDesc& s) {
+  auto visit = [&](SweepDesc& s) {
     auto key = std::make_tuple(s.kr, s.kc, s.r0 & 1, s.c0 & 1, s.frame, s.msg_init >= 0, s.msg_top >= 0,
                                (s.msg_bot >= 0) * 2 + (s.r0 + s.kr == p.L) * 4 + (s.c0 + s.kc == p.L) * 8 +
                                    (s.r0 == 0) * 16 + (s.c0 == 0) * 32);
-    if (seen.count(key)) return;
-    int r = analyse_sweep(p, s, rng);
-    r = std::max(r, analyse_sweep(p, s, rng));   // two independent random points
-    seen[key] = r;
+    auto it = seen.find(key);
+    int r;
+    if (it != seen.end()) {
+      r = it->second;
+    } else {
+      r = analyse_sweep(p, s, rng);
+      r = std::max(r, analyse_sweep(p, s, rng));   // two independent random points
+      seen[key] = r;
+    }
     worst = std::max(worst, r);
+    s.trunc = (r > chi || kmax > 6) ? 1 : 0;
+    if (s.trunc) {
+      s.flops = (float)trunc_sweep_flops(s);
+      p.trunc_sweeps += 1;
+    }
+    p.max_kp = std::max(p.max_kp, s.kp);
   };
   for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) visit(s);
   for (auto& s : p.bethe) visit(s);
+  p.flops_iter = 0.0;
+  p.flops_bethe = 0.0;
+  for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) p.flops_iter += s.flops;
+  for (auto& s : p.bethe) p.flops_bethe += s.flops;
   p.max_rank = worst;
   p.exact = (worst <= chi);
   // dense messages are exact when no message MPS can exceed chi
   const bool msg_exact = (1 << (p.max_msg_len / 2)) <= chi;
-  const int kmax = std::max(*std::max_element(p.rowsz.begin(), p.rowsz.end()),
-                            *std::max_element(p.colsz.begin(), p.colsz.end()));
   // largest dense boundary state of any sweep (the device keeps it in 4096-entry LDS buffers)
   size_t max_state = 0, max_mid = 0;
   auto state_size = [&](const SweepDesc& s) {
@@ -428,17 +462,21 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       Ps = col.bot.Pnew;
     }
   };
-  for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) state_size(s);
-  for (auto& s : p.bethe) state_size(s);
-  if (kmax > 6 || max_state > 4096 || max_mid > 2048) {
+  for (int c = 0; c < 2; ++c) for (auto& s : p.round[c]) if (!s.trunc) state_size(s);
+  for (auto& s : p.bethe) if (!s.trunc) state_size(s);
+  if (kmax > TRUNC_KMAX) {
     p.gpu_ok = false;
-    p.why = "blocks larger than 6 tensors per side are not implemented on the GPU";
+    p.why = "blocks larger than 8 tensors per side are not implemented on the GPU";
+  } else if (max_state > 4096 || max_mid > 2048) {
+    p.gpu_ok = false;
+    p.why = "a dense block sweep exceeds the device's state buffers";
   } else if (!msg_exact) {
     p.gpu_ok = false;
     p.why = "chi below 2^(k/2): message MPSs would be truncated, not implemented on the GPU";
-  } else if (!p.exact) {
+  } else if (p.trunc_sweeps > 0 && chi > TRUNC_CHI_MAX) {
     p.gpu_ok = false;
-    p.why = "truncation can act inside block sweeps for this chi; the truncating GPU path is not enabled";
+    p.why = "the truncating block sweeps (blocks wider than 6, or chi below a block's boundary rank) hold chi "
+            "up to 16";
   } else {
     p.gpu_ok = true;
   }

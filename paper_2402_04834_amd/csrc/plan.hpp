@@ -8,6 +8,9 @@
 
 namespace bbp {
 
+constexpr int TRUNC_KMAX = 8;      // widest block and longest sweep of the truncating kernel
+constexpr int TRUNC_CHI_MAX = 16;  // largest chi of the truncating kernel
+
 // One block sweep as the device consumes it (plain 64-byte record).
 struct SweepDesc {
   int32_t r0, c0, kr, kc;       // block origin and size on the grid
@@ -19,7 +22,7 @@ struct SweepDesc {
   int32_t block;                // block index (row-major)
   float flops;                  // algorithmic flops of this sweep
   int32_t geo;                  // GEO_* flags (geom.hpp)
-  int32_t pad;
+  int32_t trunc;                // 1: the boundary state of this sweep can exceed chi (truncating kernel)
 };
 static_assert(sizeof(SweepDesc) == 64, "SweepDesc layout");
 
@@ -33,6 +36,9 @@ struct Plan {
   std::vector<int32_t> pair_ids;                              // undirected edges: (u->v, v->u) ids
   int max_msg_len = 0;
   bool exact = false;        // no boundary state can exceed chi: truncation is the identity
+  int mstride = 64;          // floats per stored dense message: 2^max(6, widest block)
+  int trunc_sweeps = 0;      // sweeps (rounds and closing) that run in the truncating kernel
+  int max_kp = 0;            // widest sweep (positions across)
   int max_rank = 0;          // largest generic Schmidt rank among cuts whose dimensions exceed chi on both sides
   bool gpu_ok = false;
   std::string why;           // reason when !gpu_ok

@@ -15,7 +15,7 @@ namespace bbp {
 // independent sweeps (wavefronts) per workgroup: one, so that the wavefront of a converged job, or one
 // that finishes early, frees its slot at once
 constexpr int SWEEP_WAVES = BBP_SWEEP_WAVES;
-constexpr int MSTRIDE = 64;      // floats per stored message (2^6)
+constexpr int MSTRIDE = 64;      // floats per stored message (2^6) for plans whose blocks are at most 6 wide
 
 constexpr int MAX_GROUPS = 8;   // (d, p) groups of one mixed batch
 
@@ -35,6 +35,9 @@ struct SweepGroup {
   const double* pdev;        // optional [job / 4] per-syndrome p (overrides p00, pe)
   int32_t biased;            // 1: the qubit entries are pi (Pauli probabilities by code x + 2z)
   float pi[4];
+  double pq[4];              // the four Pauli probabilities by code x + 2z in FP64 (truncating kernel)
+  int32_t mstride;           // floats per stored message (MSTRIDE unless a block is wider than 6)
+  int32_t chi;               // bond dimension (truncating kernel)
 };
 
 struct SweepArgs {
@@ -47,11 +50,23 @@ struct SweepArgs {
   float eta;                 // damping
   int32_t small;             // 1: every block is at most 2x2 tensors: one lane per item (small_sweep.hip)
   double gate;               // > 0: skip an update whose message and input messages all changed by less (terms)
+  double* tws;               // truncating kernel: workspace of tws_slots slots of trunc_slot_bytes()
+  int64_t tws_slots;         // items per launch of the truncating kernel (larger classes run in chunks)
+  int64_t item_base;         // first item of the current chunk
 };
+
+// Sweep class of the truncating kernel (any length; sweeps with SweepDesc::trunc set).
+constexpr int TRUNC_CLASS = 1 << 12;
+
+// workspace bytes of one truncating-kernel item
+size_t trunc_slot_bytes();
+// launch the a.items truncating sweeps (in chunks of a.tws_slots items)
+hipError_t launch_trunc_sweeps(hipStream_t st, const SweepArgs& a);
 
 // Class of a sweep: the kernel instantiation that runs it -- length, caps present, one position across,
 // first site a qubit: code (((kt - 1) * 4 + top * 2 + bottom) * 2 + single) * 2 + q00.
 inline int sweep_class(const SweepDesc& s) {
+  if (s.trunc) return TRUNC_CLASS;
   return (((s.kt - 1) * 4 + (s.msg_top >= 0 ? 2 : 0) + (s.msg_bot >= 0 ? 1 : 0)) * 2 + (s.kp == 1 ? 1 : 0)) * 2 +
          ((s.geo & GEO_Q00) ? 1 : 0);
 }

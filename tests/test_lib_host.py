@@ -44,10 +44,30 @@ def test_plan_matches_oracle_partition_and_is_exact(bbp, d, k, chi):
 
 
 def test_plan_detects_binding_truncation(bbp):
+    # chi below the boundary rank of a 6x6 block: those sweeps (and only those) take the truncating kernel
     info = bbp.plan_query(7, bbp.default_opts(block=6, chi=8))
-    assert info.exact_sweeps == 0 and info.max_cut_rank == 16 and info.gpu_supported == 0
+    assert info.exact_sweeps == 0 and info.max_cut_rank == 16 and info.gpu_supported == 1
+    assert 0 < info.truncating_sweeps and info.message_stride == 64
     info = bbp.plan_query(7, bbp.default_opts(block=6, chi=16))
-    assert info.exact_sweeps == 1
+    assert info.exact_sweeps == 1 and info.truncating_sweeps == 0
+
+
+@pytest.mark.parametrize("d,k,chi,stride", [(9, 7, 16, 128), (9, 8, 16, 256), (17, 8, 16, 256)])
+def test_wide_blocks_run_every_sweep_in_the_truncating_kernel(bbp, d, k, chi, stride):
+    info = bbp.plan_query(d, bbp.default_opts(block=k, chi=chi))
+    p = blockbp.Plan(d, k, k)
+    assert info.gpu_supported == 1 and info.message_stride == stride
+    assert info.truncating_sweeps == p.M + p.nI * p.nJ        # every update and every closing sweep
+    assert info.max_cut_rank > chi                              # the truncation really acts
+
+
+@pytest.mark.parametrize("d,k,chi,why", [(9, 9, 16, "larger than 8"), (9, 8, 32, "up to 16"),
+                                         (9, 6, 4, "message MPSs")])
+def test_unsupported_truncation_is_refused_with_a_reason(bbp, d, k, chi, why):
+    from paper_2402_04834_amd import _lib
+    info = bbp.plan_query(d, bbp.default_opts(block=k, chi=chi))
+    assert info.gpu_supported == 0
+    assert why in _lib.lib().bbp_last_error().decode()
 
 
 def test_invalid_arguments_are_rejected(bbp):
