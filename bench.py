@@ -46,13 +46,14 @@ def traffic(kernel, path=TRAFFIC):
 
 TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/geom.hpp", "paper_2402_04834_amd/csrc/sweep_launch.hpp",
                    "paper_2402_04834_amd/csrc/wave_sweep.hpp", "paper_2402_04834_amd/csrc/sweep_kernel.hip"]
-BMPS_TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/bmps_launch.hpp", "paper_2402_04834_amd/csrc/bmps.hip"]
+BMPS_TRAFFIC_SOURCES = ["paper_2402_04834_amd/csrc/bmps_launch.hpp", "paper_2402_04834_amd/csrc/bmps.hip",
+                        "paper_2402_04834_amd/csrc/wave_mps.hpp"]
 
 
 def _short_kernel_name(name):
     """'void bbp::(anonymous namespace)::sweep_kernel<false, 6, true, true, false, true, false>(...)' ->
     'sweep_kernel<6, true, true, false, true>' (FP32 depolarizing kernels; the first template argument true
-    gives 'sweep_kernel_bf16<...>', as _lib.sweep_kernel_name names them); 'bmps_kernel<double>'; other kernels
+    gives 'sweep_kernel_bf16<...>', as _lib.sweep_kernel_name names them); 'bmps_kernel'; other kernels
     keep their name."""
     import re
     m = re.search(r"sweep_kernel<(true|false), (\d+(?:, (?:true|false)){4}), false>", name)
@@ -60,7 +61,7 @@ def _short_kernel_name(name):
         return f"sweep_kernel{'_bf16' if m.group(1) == 'true' else ''}<{m.group(2)}>"
     if "trunc_sweep_kernel" in name:
         return "trunc_sweep_kernel"
-    return "bmps_kernel<double>" if "bmps_kernel<double>" in name else name
+    return "bmps_kernel" if re.search(r"bmps_kernel\b", name) and "decide" not in name else name
 
 
 def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024, target="sweep"):
@@ -69,7 +70,7 @@ def write_traffic_summary(fetch_csv, write_csv, copy_mib=1024, target="sweep"):
     MIB`, with the scale factors that make the calibration copy read and write exactly its size; stamped
     with the hash of the kernel sources."""
     sources, path, prefix = ((TRAFFIC_SOURCES, TRAFFIC, "sweep_kernel") if target == "sweep" else
-                             (BMPS_TRAFFIC_SOURCES, BMPS_TRAFFIC, "bmps_kernel<"))
+                             (BMPS_TRAFFIC_SOURCES, BMPS_TRAFFIC, "bmps_kernel"))
     import collections
     import csv
     import hashlib
@@ -541,18 +542,31 @@ def biased_main(a):
     print(json.dumps(line), flush=True)
 
 
-def bmps_flops(d):
-    """Algorithmic FP64 flops of one coset contraction by bmps_kernel at the padded sizes it works on (bonds
-    2 chi_max = 32, so at d=17 every interior bond is full): per grid row of every column but the last, the
-    carry product R B (2 * 64 * 32 * 32), Householder QR of the 64 x 32 result and its explicit Q
-    (2 (2 m n^2 - 2 n^3 / 3) with m = 64, n = 32), the carry product Q C (2 * 64 * 32 * 16), the SVD of the
-    32 x 32 matrix N with its right singular vectors (the Golub-Van Loan count 21 n^3) and C = N V^T
-    (2 * 32 * 32 * 16)."""
+def bmps_flops(d, chi=16):
+    """Algorithmic FP64 flops of one coset contraction by the boundary-MPS decoder at the actual bond sizes:
+    compressed bond j of the L-row chain b_j = min(chi, 2^j, 2^(L-j)), after a column is absorbed
+    w_j = min(2 b_j, 2^j, 2^(L-j)). Per row r of every column but the last, with the row's matrix M of
+    m = 2 w_r rows (left bond, leg) and n = w_{r+1} columns:
+      absorption  M = R (A (x) T): 2 m n (2 b_r) (the old left bond and the up leg summed per entry);
+      QR          Householder, 2 m n^2 - 2 n^3 / 3 (m >= n; mirrored otherwise), rows but the last;
+      Q C         the reflections applied to the carry from below (n x b_{r+1}): 4 m b_{r+1} min(m, n);
+      SVD         one-sided Jacobi of N (w_r x 2 b_{r+1}) with its right singular vectors, counted by the
+                  Golub-Van Loan figure 21 k^3, k = min(w_r, 2 b_{r+1}), plus C = N V: 2 w_r (2 b_{r+1}) b_r.
+    The kernel executes every matrix at the padded size 2 chi = 32; these are the method's own flops."""
     L = 2 * d - 1
-    m, n = 64, 32
-    qr = 2 * m * n * n - 2 * n ** 3 / 3
-    per_row = 2 * 64 * 32 * 32 + 2 * qr + 2 * 64 * 32 * 16 + 21 * n ** 3 + 2 * 32 * 32 * 16
-    return (L - 1) * L * per_row
+    b = [min(chi, 2 ** j, 2 ** (L - j)) for j in range(L + 1)]
+    w = [min(2 * b[j], 2 ** j, 2 ** (L - j)) for j in range(L + 1)]
+    per_col = 0.0
+    for r in range(L):
+        m, n = 2 * w[r], w[r + 1]
+        per_col += 2 * m * n * 2 * b[r]
+        if r < L - 1:
+            lo, hi = min(m, n), max(m, n)
+            per_col += 2 * hi * lo * lo - 2 * lo ** 3 / 3
+            per_col += 4 * m * b[r + 1] * lo
+        k = min(w[r], 2 * b[r + 1])
+        per_col += 21 * k ** 3 + 2 * w[r] * 2 * b[r + 1] * b[r]
+    return (L - 1) * per_col
 
 
 def bmps_main(a):
@@ -583,7 +597,7 @@ def bmps_main(a):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     avg_ms = kms / a.steps
-    flops = bmps_flops(d) * 4 * count
+    flops = bmps_flops(d, chi) * 4 * count
     achieved = flops / (avg_ms * 1e-3) / 1e12
     opts = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
     ref = bbp.decode_device(d, p, s, opts)
@@ -602,8 +616,8 @@ def bmps_main(a):
                     parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                       frac=achieved / PEAK_FP64_TFLOPS,
-                      traffic=traffic("bmps_kernel<double>", BMPS_TRAFFIC) if d == 17 and count == 4096 else None,
-                      kernel="bmps_kernel<double>",
+                      traffic=traffic("bmps_kernel", BMPS_TRAFFIC) if d == 17 and count == 4096 else None,
+                      kernel="bmps_kernel",
                       avg_launch_ms=avg_ms, flops_per_launch=flops),
         decisions_equal_to_blockbp=float((cb == cr).mean()),
         logical_failures=dict(bmps=[int(fb.sum()), count, list(wilson(int(fb.sum()), count))],

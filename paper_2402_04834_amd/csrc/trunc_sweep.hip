@@ -32,13 +32,15 @@
 
 #include "geom.hpp"
 #include "sweep_launch.hpp"
+#include "wave_mps.hpp"
 
 namespace bbp {
 namespace {
 
+using namespace wmps;
+
 constexpr int KM = TRUNC_KMAX;
 constexpr int TS = 16 * 2 * 16;   // one compressed site [a][h][b] (a, b < 16), or one cap operator [P][v][Q]
-constexpr int TQ = 32 * 64 + 32;  // one pass-1 factor: reflection vectors [j][row] (rows 2l + h, l < 32), betas
 // workspace slot of one item, in doubles
 constexpr int W_A = 0;                      // sites 0 .. kp+1
 constexpr int W_Q = W_A + (KM + 2) * TS;    // pass-1 factors of sites 0 .. kp; site kp+1 keeps its matrix M
@@ -46,28 +48,11 @@ constexpr int W_CT = W_Q + (KM + 2) * TQ;   // cap operators: top t = 0 .. kt-1,
 constexpr int W_SLOT = W_CT + 2 * KM * TS;
 
 // LDS pool in doubles (the phases never overlap)
-constexpr int XS = 17;                                        // Jacobi exchange row stride (LDS banks)
 constexpr int P1 = 32 * 32 + 2 * 64 + 32 + 3 * TS;            // R carry, vector buffers, betas, site, CT, Bb
 constexpr int P2 = 64 * XS + 32 * 16 + 32;                    // exchange (then V), carry C, singular values
 constexpr int PC = 256 + 32 * 32 + 32;                        // chain: matrix, vectors, betas
 constexpr int PE = 4 * 256;                                   // end: left / right chains (ping-pong)
 constexpr int POOL = std::max(std::max(P1, P2), std::max(PC, PE));
-
-// Jacobi: rotate while |<c_p, c_q>| > JAC |c_p| |c_q|; a row of norm at most RANKTOL |N|_F is rounding noise
-constexpr double JAC = 1e-13, RANKTOL = 1e-13;
-constexpr int SWEEPS = 16;
-
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-__device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
 
 __device__ __forceinline__ int bitrev(int w, int K) { return (int)(__brev((unsigned)w) >> (32 - K)); }
 
@@ -149,207 +134,6 @@ __device__ __forceinline__ void chain(double* W, double* Hv, double* Hb, int K, 
     else out[(K - 1) * TS + a * 32 + v * 16] = W[e];
   }
   __syncthreads();
-}
-
-// Householder QR of the 64 x 32 matrix held as x[k] = M[2k + par][hi] by lane (hi, par), reflections j < jmax.
-// On return x holds R above the diagonal and reflection vector j (pivot entry v_j) from the diagonal down in
-// lanes hi = j, rd the diagonal entry of R of the lane's column, Hb[j] the coefficients.
-__device__ __forceinline__ void qr64(double (&x)[32], double& rd, int jmax, double* vb, double* Hb) {
-  const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
-  rd = 0.0;
-  for (int j = 0; j < jmax; ++j) {
-    double* v = vb + (j & 1) * 64;
-    if (hi == j) {
-#pragma unroll
-      for (int k = 0; k < 32; ++k) v[2 * k + par] = (2 * k + par >= j) ? x[k] : 0.0;
-    }
-    __syncthreads();
-    double hv[32], pn = 0.0, pw = 0.0, xp = 0.0;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      hv[k] = v[2 * k + par];
-      pn += hv[k] * hv[k];
-      pw += hv[k] * x[k];
-      xp += (2 * k + par == j) ? x[k] : 0.0;
-    }
-    const double nrm = sqrt(pn + __shfl_xor(pn, 1));
-    const double alpha = v[j];
-    double beta = 0.0, vj = alpha, diag = alpha;
-    if (nrm > 0.0) {
-      const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
-      vj = alpha + sg * nrm;
-      beta = 1.0 / (nrm * (nrm + fabs(alpha)));
-      diag = -sg * nrm;
-    }
-    pw += (vj - alpha) * xp;   // the pivot entry of the vector is v_j, not alpha
-    const double w = (pw + __shfl_xor(pw, 1)) * beta;
-    if (hi > j) {
-#pragma unroll
-      for (int k = 0; k < 32; ++k) x[k] -= w * ((2 * k + par == j) ? vj : hv[k]);
-    } else if (hi == j) {
-      rd = diag;
-#pragma unroll
-      for (int k = 0; k < 32; ++k)
-        if (2 * k + par == j) x[k] = vj;
-    }
-    if (ln == 0) Hb[j] = beta;
-  }
-  __syncthreads();
-}
-
-// The reflection vectors left in x by qr64 (rows >= j of column j, zero above) and their coefficients into a
-// pass-1 factor slot: Vg[j * 64 + row], Vg[2048 + j].
-__device__ __forceinline__ void store_v(const double (&x)[32], int jmax, const double* Hb, double* Vg) {
-  const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
-  if (hi < jmax) {
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int row = 2 * k + par;
-      Vg[hi * 64 + row] = (row >= hi) ? x[k] : 0.0;
-    }
-  }
-  if (ln < jmax) Vg[2048 + ln] = Hb[ln];
-}
-
-// X = Q C for the carry C (Csh [m][k], m < 32, k < 16) and the factor stored by store_v, Q = H_0 ... H_{jmax-1}
-// on the first 32 unit columns: X = H_0 (H_1 (... [C; 0])). Lane (kc, qt) = (ln & 15, ln >> 4) holds rows
-// 16 qt + r of column kc in X[r]; a reflection is a 16-term partial product, two cross-quarter additions and
-// a 16-term update. The vectors are read once, from the slot pass 1 wrote.
-__device__ __forceinline__ void apply_q(double (&X)[16], int jmax, const double* Vg, const double* Csh) {
-  const int ln = threadIdx.x, kc = ln & 15, qt = ln >> 4;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = qt * 16 + r;
-    X[r] = (row < 32) ? Csh[row * 16 + kc] : 0.0;
-  }
-  for (int j = jmax - 1; j >= 0; --j) {
-    const double* v = Vg + j * 64 + qt * 16;
-    double p = 0.0;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) p += v[r] * X[r];
-    p += __shfl_xor(p, 16);
-    p += __shfl_xor(p, 32);
-    const double w = p * Vg[2048 + j];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) X[r] -= w * v[r];
-  }
-}
-
-// The carry R (rows 0..31 of the factored matrix) into Rsh [row][col], unit Frobenius norm; returns ln |R|_F.
-__device__ __forceinline__ double store_r(const double (&x)[32], double rd, double* Rsh) {
-  const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
-  double f = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int row = 2 * k + par;
-    const double r = row < hi ? x[k] : (row == hi ? rd : 0.0);
-    f += r * r;
-  }
-  const double fro = sqrt(wsum(f));
-  const double inv = (fro > 0.0) ? 1.0 / fro : 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int row = 2 * k + par;
-    Rsh[row * 32 + hi] = (row < hi ? x[k] : (row == hi ? rd : 0.0)) * inv;
-  }
-  __syncthreads();
-  return log(fro);
-}
-
-// One-sided Jacobi SVD of the 32 x 32 matrix N held as y[k] = N[l][(par, k)] by lane (l = hi, par), the chi
-// largest singular values kept. Writes the kept right singular vectors (rows j < 16 of V, zero beyond chi) as
-// site [j][par][k] (or, bottom cap, [j][k] from the par = 0 half) and the carry C = N V / |.|_F into Csh
-// [l][j]; returns the log of that norm.
-__device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh, double* Csh, double* sig,
-                                           double* site, bool bottom) {
-  const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
-  double y0[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) y0[k] = y[k];
-  double nf2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) nf2 += y[k] * y[k];
-  const double thr2 = wsum(nf2) * (RANKTOL * RANKTOL);
-  for (int sw = 0; sw < SWEEPS; ++sw) {
-    int rotated = 0;
-    double c2max = 0.0;
-    double own = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) own += y[k] * y[k];
-    own += __shfl_xor(own, 1);
-    for (int rd = 0; rd < 31; ++rd) {
-      const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : (2 * rd - hi + 62) % 31;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) Xsh[ln * XS + k] = y[k];
-      Xsh[ln * XS + 16] = own;
-      __syncthreads();
-      double z[16], gg = 0.0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        z[k] = Xsh[(2 * pl + par) * XS + k];
-        gg += y[k] * z[k];
-      }
-      const double other = Xsh[(2 * pl + par) * XS + 16];
-      __syncthreads();
-      gg += __shfl_xor(gg, 1);
-      const bool lower = hi < pl;
-      const double al = lower ? own : other, be = lower ? other : own;
-      const double c2 = (al > thr2 && be > thr2) ? gg * gg / (al * be) : 0.0;
-      c2max = c2 > c2max ? c2 : c2max;
-      if (c2 > JAC * JAC) {
-        // tan(theta) of the rotation that orthogonalises the pair (the smaller root), then cos and sin
-        const double zeta = (be - al) / (2.0 * gg), az = fabs(zeta);
-        const double tt = copysign(1.0 / (az + (az < 1e150 ? sqrt(zeta * zeta + 1.0) : az)), zeta);
-        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = cs * tt;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = lower ? (cs * y[k] - sn * z[k]) : (sn * z[k] + cs * y[k]);
-        const double cc = cs * cs;
-        own = lower ? cc * (al - 2.0 * tt * gg + tt * tt * be) : cc * (be + 2.0 * tt * gg + tt * tt * al);
-        rotated = 1;
-      }
-    }
-    if (!__any(rotated) || wmax(c2max) < 1e-16) break;
-  }
-  double s2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s2 += y[k] * y[k];
-  const double s2r = s2 + __shfl_xor(s2, 1);
-  const double sv = (s2r > thr2) ? sqrt(s2r) : 0.0;
-  const double key = (sv == sv) ? sv : -1.0;
-  if (par == 0) sig[hi] = key;
-  __syncthreads();
-  int rank = 0;
-  for (int i = 0; i < 32; ++i) {
-    const double o = sig[i];
-    rank += (o > key || (o == key && i < hi)) ? 1 : 0;
-  }
-  const bool kept = rank < chi && sv > 0.0;
-  const double inv = kept ? 1.0 / sv : 0.0;
-  double* Vsh = Xsh;   // the exchange buffer is free now
-  if (rank < 16) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (bottom) {
-        if (par == 0) site[rank * 16 + k] = y[k] * inv;
-      } else {
-        site[(rank * 2 + par) * 16 + k] = y[k] * inv;
-      }
-      Vsh[rank * 32 + par * 16 + k] = y[k] * inv;
-    }
-  }
-  const double fro = sqrt(wsum((par == 0 && kept) ? sv * sv : 0.0));
-  __syncthreads();
-  const double finv = (fro > 0.0) ? 1.0 / fro : 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
-    acc += __shfl_xor(acc, 1);
-    if ((j >> 3) == par) Csh[hi * 16 + j] = acc * finv;
-  }
-  __syncthreads();
-  return log(fro);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void trunc_sweep_kernel(SweepArgs a) {
@@ -532,13 +316,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         // N = Q_i C, then from the column layout to rows: lane (l, t) takes N[l][(t, k)] = X[2l + t][k]
         double X[16];
         apply_q(X, 32, Q + i * TQ, Csh);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) Xsh[((ln >> 4) * 16 + r) * XS + (ln & 15)] = X[r];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = Xsh[ln * XS + k];
+        cols_to_rows(X, Xsh, y);
       }
-      __syncthreads();   // the exchange buffer and Csh are rewritten by the step
       logs += svd_step(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
     }
     // top cap: S_0[q'][j] = sum_m Q_0[q'][m] C[m][j], unit Frobenius norm
