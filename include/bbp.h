@@ -262,8 +262,8 @@ int bbp_blockbp_decode(bbp_net* const* nets, int64_t batch, const bbp_opts* opts
  * matrix work in FP64 (an estimate is resolved down to about the unit roundoff times the state's norm, which
  * the likeliest configurations set, so FP32 would leave cosets some tens of nats below the best unresolved).
  *
- * Workspace: bbp_bmps_workspace_size bytes (coset labels plus 16*2*16 + 64*32 doubles per grid row and coset
- * network: 20 KiB * L * 4 * batch). Errors: BBP_EINVAL (d outside [2, 32], chi outside [1, 16], batch < 0
+ * Workspace: bbp_bmps_workspace_size bytes (coset labels plus 16*2*16 + 32*64 + 32 doubles per grid row and
+ * coset network -- the compressed row and its factor in compact form: about 20.3 KiB * L * 4 * batch). Errors: BBP_EINVAL (d outside [2, 32], chi outside [1, 16], batch < 0
  * or above 2^22).
  */
 int bbp_bmps_workspace_size(int32_t d, int64_t batch, int32_t chi, size_t* bytes);

@@ -213,7 +213,9 @@ def test_bmps_and_gate_host_side(bbp):
     L = 2 * d - 1
     assert h.bbp_bmps_workspace_size(d, batch, 16, C.byref(n)) == _lib.BBP_OK
     label_bytes = -(-batch * 4 * L * L // 256) * 256
-    assert n.value == label_bytes + 4 * batch * L * (16 * 2 * 16 + 64 * 32) * 8
+    # per row of each coset network: the compressed row [16][2][16] and the factor slot (32 reflection
+    # vectors of 64 entries and their 32 coefficients), in doubles
+    assert n.value == label_bytes + 4 * batch * L * (16 * 2 * 16 + 32 * 64 + 32) * 8
     assert h.bbp_bmps_workspace_size(d, batch, 17, C.byref(n)) == _lib.BBP_EINVAL     # chi above 16
     assert h.bbp_bmps_workspace_size(d, batch, 0, C.byref(n)) == _lib.BBP_EINVAL      # chi below 1
     assert h.bbp_bmps_workspace_size(1, batch, 16, C.byref(n)) == _lib.BBP_EINVAL     # d below 2
