@@ -319,10 +319,11 @@ __global__ __launch_bounds__(256) void conv_gemm(int L, int64_t rows, int cin, i
 // a 32-step, and holds D rows 4 (l/16) .. +3 of column l%16). Implicit GEMM with the gather of conv_gemm<G_FWD>:
 // Y[row][co] = act(sum_{t, ci} X[row + t][ci] Wt[co][t CIN + ci] + b[co]). One workgroup of four waves computes
 // 128 rows x all NT output channels (2 x 2 waves of 64 x NT/2, i.e. 4 x NT/32 MFMA blocks each), so every
-// gathered activation tile is read once; K advances in steps of 32 through double-buffered LDS tiles (one
-// barrier per step), the next step's global loads in flight during the current step's MFMAs. A 16-byte load
-// is 8 channels of one tap (CIN is a multiple of 16); the weights come transposed, Wt[co][k], k padded to a
-// multiple of the stage with zeros, so both LDS tiles are k-contiguous.
+// gathered activation tile is read once; K advances in steps of 32 through double-buffered, swizzled LDS tiles
+// (one barrier per step), the global loads two steps ahead in flight (two register sets). A 16-byte load is 8
+// channels of one tap (CIN is a multiple of 16) at an offset computed once per row and tap; the weights come
+// transposed, Wt[co][k], k padded to a multiple of the stage with zeros, so both LDS tiles are k-contiguous.
+// BF16 outputs leave through an LDS tile in 16-byte rows.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // Wt[co][kp] (kp < kpad) = W[t cin + ci][co] for kp = t cs + ci with ci < cin, else 0 (BF16)
@@ -335,72 +336,86 @@ __global__ void weights_t_kernel(const float* __restrict__ W, int cin, int cs, i
   }
 }
 
-#ifndef BBP_CONV_KS
-#define BBP_CONV_KS 32
-#endif
-constexpr int CONV_KS = BBP_CONV_KS;   // k per LDS stage of the BF16 convolutions (32 or 64)
+constexpr int CONV_KS = 32;   // k per LDS stage of the BF16 convolutions (one MFMA step)
 // k of a BF16 weight row: 9 cs padded to a multiple of the stage
 constexpr int kpad(int cs) { return (9 * cs + CONV_KS - 1) / CONV_KS * CONV_KS; }
 
-// WM: waves along M (2: wave tiles of 64 x NT/2, workgroup tiles of 128 x NT; 4: 64 x NT and 256 x NT, each
-// B fragment then serving four A fragments).
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+
+// LDS tiles hold rows of 32 BF16 (64 bytes, four 16-byte chunks); chunk g of row r sits at chunk g ^ ((r / 2) % 4).
+// A thread quad writes the four chunks of one row, so eight consecutive lanes write two whole rows; the 16
+// lanes of a fragment read one chunk of 16 consecutive rows, which the swizzle spreads over all banks.
+__device__ __forceinline__ int swz(int r, int g) { return r * 32 + 8 * (g ^ ((r >> 1) & 3)); }
+
+// WM: waves along M (wave tiles of 64 x NT/2, two waves along N: workgroups of 128 WM threads computing
+// 64 WM x NT). Compiled for three wavefronts per SIMD (at most 168 registers): the unconstrained build takes
+// 110 VGPRs and 96 accumulation registers, two wavefronts per SIMD, and ran the forward 13 % slower.
 template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
-__global__ __launch_bounds__(256) void conv_fwd_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
+__global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) void conv_fwd_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
                                                      const unsigned short* __restrict__ Wt,
                                                      const float* __restrict__ bias, void* __restrict__ Y) {
-  constexpr int KS = CONV_KS;                             // k per LDS stage (32 or 64: one or two MFMA steps)
-  constexpr int K = 9 * CIN, KP = kpad(CIN), S = KS + 8;   // LDS row stride: KS k + 8 (bank spread)
-  constexpr int MT = 64 * WM, WN = NT * WM / 4;           // workgroup rows, wave columns
-  constexpr int NJ = WN / 16;                             // 16-column blocks per wave
-  constexpr int G = KS / 8;                               // 8-k groups per row and stage
-  constexpr int UA = MT * G / 256, UB = (NT * G + 255) / 256;   // 16-byte chunks per thread and stage
-  static_assert(CIN % 16 == 0 && NT % 32 == 0 && NT <= 128 && (WM == 2 || WM == 4), "tile shape");
-  __shared__ __align__(16) unsigned short As[2][MT * S];
-  __shared__ __align__(16) unsigned short Bs[2][NT * S];
+  constexpr int KS = CONV_KS, KP = kpad(CIN), NS = KP / KS;   // stages
+  constexpr int TH = 128 * WM;                                 // threads
+  constexpr int MT = 64 * WM, WN = NT / 2, NJ = WN / 16;       // workgroup rows, wave columns, 16-blocks
+  constexpr int UA = MT * 4 / TH, UB = (NT * 4 + TH - 1) / TH;  // 16-byte chunks per thread and stage
+  constexpr int STAGE = (MT + NT) * KS;                        // one A and one B buffer
+  constexpr int TILE = OUT_BF ? MT * NT : 0;                   // BF16 output tile, written out through LDS
+  static_assert(CIN % 16 == 0 && NT % 32 == 0 && NT <= 128 && (WM == 2 || WM == 4) && KS == 32, "tile shape");
+  __shared__ __align__(16) unsigned short lds[(2 * STAGE > TILE) ? 2 * STAGE : TILE];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * MT;
-  const int wm = (w / (4 / WM)) * 64, wn = (w % (4 / WM)) * WN;
-  // global -> LDS assignment: A chunk q = tid + 256 u: row q / G, k group q % G (8 k each); B chunk q
-  // (< NT * G): column q / G, k group q % G
-  Site arow[UA];
-  bool aok[UA];
+  const int wm = (w >> 1) * 64, wn = (w & 1) * WN;
+  const int ag = tid & 3;   // the 8-k group of every chunk this thread stages
+  // element offsets (site x CIN) of the 9 taps of each staged row, -1 outside the grid or past the rows:
+  // computed once, so a stage's gather is one predicated 16-byte load
+  int off[UA][9];
 #pragma unroll
   for (int u = 0; u < UA; ++u) {
-    const int64_t row = m0 + (tid + 256 * u) / G;
-    aok[u] = row < rows;
-    arow[u] = aok[u] ? site_of(row, L) : Site{0, 0, 0};
+    const int64_t row = m0 + ((tid + TH * u) >> 2);
+    const Site st = site_of(row < rows ? row : 0, L);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int64_t src = shifted(st, t, 1, L);
+      off[u][t] = (row < rows && src >= 0) ? (int)(src * CIN) : -1;
+    }
   }
-  uint4 ra[UA], rb[UB];
-  auto load = [&](int k0) {
+  auto loadA = [&](const int s, uint4 (&ra)[UA]) {
 #pragma unroll
     for (int u = 0; u < UA; ++u) {
-      const int q = tid + 256 * u, k = k0 + 8 * (q % G);
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (aok[u] && k < K) {
-        const int tap = k / CIN, ch = k - tap * CIN;
-        const int64_t src = shifted(arow[u], tap, 1, L);
-        if (src >= 0) v = *(const uint4*)(X + src * CIN + ch);
+      int o, ch;
+      if constexpr (CIN >= KS) {   // a stage lies inside one tap
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int t = (KS * s) / CIN;
+        o = off[u][t];
+        ch = (KS * s) % CIN + 8 * ag;
+      } else {                     // CIN = 16: a stage spans taps t0 and t0 + 1 (t0 + 1 may be the padding)
+        const int t0 = (KS * s) / CIN;
+        const int a0 = off[u][t0 < 9 ? t0 : 8], a1 = off[u][t0 + 1 < 9 ? t0 + 1 : 8];
+        o = (ag >> 1) ? (t0 + 1 < 9 ? a1 : -1) : (t0 < 9 ? a0 : -1);
+        ch = 8 * (ag & 1);
       }
-      ra[u] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      const int q = tid + 256 * u;
-      uint4 b = {0u, 0u, 0u, 0u};
-      if (q < NT * G) b = *(const uint4*)(Wt + (int64_t)(q / G) * KP + k0 + 8 * (q % G));
-      rb[u] = b;
+      ra[u] = (o >= 0) ? *(const uint4*)(X + o + ch) : uint4{0u, 0u, 0u, 0u};
     }
   };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < UA; ++u) {
-      const int q = tid + 256 * u;
-      *(uint4*)&As[buf][(q / G) * S + 8 * (q % G)] = ra[u];
-    }
+  auto loadB = [&](const int s, uint4 (&rb)[UB]) {
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      const int q = tid + 256 * u;
-      if (q < NT * G) *(uint4*)&Bs[buf][(q / G) * S + 8 * (q % G)] = rb[u];
+      const int q = tid + TH * u;
+      rb[u] = (q < NT * 4) ? *(const uint4*)(Wt + (int64_t)(q >> 2) * KP + KS * s + 8 * (q & 3))
+                           : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store = [&](const int buf, const uint4 (&ra)[UA], const uint4 (&rb)[UB]) {
+    unsigned short* As = lds + buf * STAGE;
+    unsigned short* Bs = As + MT * KS;
+#pragma unroll
+    for (int u = 0; u < UA; ++u) *(uint4*)&As[swz((tid + TH * u) >> 2, ag)] = ra[u];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int q = tid + TH * u;
+      if (q < NT * 4) *(uint4*)&Bs[swz(q >> 2, q & 3)] = rb[u];
     }
   };
   f4 acc[4][NJ];
@@ -408,44 +423,89 @@ __global__ __launch_bounds__(256) void conv_fwd_bf16(int L, int64_t rows, const 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  load(0);
-  store(0);
+  // two register sets: the loads of stage s + 2 are issued while stage s is multiplied, and stored to LDS
+  // at the end of stage s + 1
+  uint4 ra[2][UA], rb[2][UB];
+  loadA(0, ra[0]);
+  loadB(0, rb[0]);
+  store(0, ra[0], rb[0]);
+  if (NS > 1) {
+    loadA(1, ra[1]);
+    loadB(1, rb[1]);
+  }
   __syncthreads();
-  const int fr = lane & 15, fk = 8 * (lane >> 4);
-  for (int k0 = 0, buf = 0; k0 < KP; k0 += KS, buf ^= 1) {
-    const bool more = k0 + KS < KP;
-    if (more) load(k0 + KS);
+  const int fr = lane & 15, fc = lane >> 4;
 #pragma unroll
-    for (int kk = 0; kk < KS; kk += 32) {
-      bf8 a[4], b[NJ];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = *(const bf8*)&As[buf][(wm + 16 * i + fr) * S + kk + fk];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = *(const bf8*)&Bs[buf][(wn + 16 * j + fr) * S + kk + fk];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  for (int s = 0; s < NS; ++s) {
+    if (s + 2 < NS) {
+      loadA(s + 2, ra[s & 1]);
+      loadB(s + 2, rb[s & 1]);
     }
-    if (more) store(buf ^ 1);
+    const unsigned short* As = lds + (s & 1) * STAGE;
+    const unsigned short* Bs = As + MT * KS;
+    bf8 a[4], b[NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const bf8*)&As[swz(wm + 16 * i + fr, fc)];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[j] = *(const bf8*)&Bs[swz(wn + 16 * j + fr, fc)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (s + 1 < NS) store((s + 1) & 1, ra[(s + 1) & 1], rb[(s + 1) & 1]);
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
+  // epilogue: bias, activation; lane l holds rows 4 (l / 16) .. +3 of column l % 16 of every block
+  const bool full = m0 + MT <= rows;
+  if constexpr (OUT_BF) {
+    // BF16 tile [MT][NT] in LDS (the stage buffers are free), then 16-byte rows out
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int col = wn + 16 * j + fr;
       const float bc = bias[col];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-        if (row >= rows) continue;
-        float v = acc[i][j][r] + bc;
-        if (RELU) v = fmaxf(v, 0.0f);
-        if (OUT_BF) ((unsigned short*)Y)[row * NT + col] = f2bf(v);
-        else ((float*)Y)[row * NT + col] = v;
+      for (int i = 0; i < 4; ++i) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = acc[i][j][r] + bc;
+          if (RELU) v[r] = fmaxf(v[r], 0.0f);
+        }
+        // two values per v_cvt_pk_bf16_f32 (round to nearest even), the pair taken as one 32-bit word: single
+        // elements of a BF16 vector are not extracted (the compiler mishandles that form)
+        const unsigned p01 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[0], v[1]}, bf2));
+        const unsigned p23 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[2], v[3]}, bf2));
+        const int row = wm + 16 * i + 4 * fc;
+        lds[(row + 0) * NT + col] = (unsigned short)(p01 & 0xFFFFu);
+        lds[(row + 1) * NT + col] = (unsigned short)(p01 >> 16);
+        lds[(row + 2) * NT + col] = (unsigned short)(p23 & 0xFFFFu);
+        lds[(row + 3) * NT + col] = (unsigned short)(p23 >> 16);
       }
     }
+    __syncthreads();
+    constexpr int CPR = NT / 8;   // 16-byte chunks per row
+#pragma unroll
+    for (int q = tid; q < MT * CPR; q += TH) {
+      const int row = q / CPR, c8 = q - row * CPR;
+      if (full || m0 + row < rows)
+        *(uint4*)((unsigned short*)Y + (m0 + row) * NT + 8 * c8) = *(const uint4*)&lds[row * NT + 8 * c8];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = wn + 16 * j + fr;
+      const float bc = bias[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm + 16 * i + 4 * fc + r;
+          float v = acc[i][j][r] + bc;
+          if (RELU) v = fmaxf(v, 0.0f);
+          if (full || row < rows) ((float*)Y)[row * NT + col] = v;
+        }
+    }
+  }
 }
 
 // db[c] = sum over rows of dY[row][c]; one workgroup per channel
@@ -908,7 +968,9 @@ struct Args {
 template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
 int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short* Wt, const float* bias, void* Y,
               hipStream_t st) {
-  conv_fwd_bf16<CIN, NT, WM, RELU, OUT_BF><<<dim3((unsigned)((rows + 64 * WM - 1) / (64 * WM))), dim3(256), 0, st>>>(
+  // the kernel addresses the activations with 32-bit element offsets
+  if (rows * CIN > (int64_t)INT32_MAX) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
+  conv_fwd_bf16<CIN, NT, WM, RELU, OUT_BF><<<dim3((unsigned)((rows + 64 * WM - 1) / (64 * WM))), dim3(128 * WM), 0, st>>>(
       L, rows, X, Wt, bias, Y);
   W_TRY(hipGetLastError());
   return BBP_OK;
