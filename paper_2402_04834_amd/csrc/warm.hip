@@ -325,6 +325,7 @@ __global__ __launch_bounds__(256) void conv_gemm(int L, int64_t rows, int cin, i
 // transposed, Wt[co][k], k padded to a multiple of the stage with zeros, so both LDS tiles are k-contiguous.
 // BF16 outputs leave through an LDS tile in 16-byte rows.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes staged through registers
 
 // Wt[co][kp] (kp < kpad) = W[t cin + ci][co] for kp = t cs + ci with ci < cin, else 0 (BF16)
 __global__ void weights_t_kernel(const float* __restrict__ W, int cin, int cs, int cout, int kpad,
@@ -367,55 +368,63 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
   const int64_t m0 = (int64_t)blockIdx.x * MT;
   const int wm = (w >> 1) * 64, wn = (w & 1) * WN;
   const int ag = tid & 3;   // the 8-k group of every chunk this thread stages
-  // element offsets (site x CIN) of the 9 taps of each staged row, -1 outside the grid or past the rows:
-  // computed once, so a stage's gather is one predicated 16-byte load
-  int off[UA][9];
+  // The gather is a raw buffer load: an offset at or past the buffer's size reads zeros without touching
+  // memory, so the padding taps need no branch and every stage issues the same loads (the wait before a
+  // stage's LDS store then covers only the older stage's loads, not the ones just issued).
+  const unsigned xbytes = (unsigned)(rows * CIN * 2);   // the host keeps this + 256 below 2^32
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)xbytes, 0x00020000);
+  // per staged row: its byte offset and where it sits on the grid (bit 0: first grid row, 1: last grid row,
+  // 2: first column, 3: last column, 4: past the rows); tap t is out of the grid where the row has a bit of
+  // tapmask(t), and reads at the sentinel xbytes
+  unsigned base[UA], edge[UA];
 #pragma unroll
   for (int u = 0; u < UA; ++u) {
     const int64_t row = m0 + ((tid + TH * u) >> 2);
     const Site st = site_of(row < rows ? row : 0, L);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int64_t src = shifted(st, t, 1, L);
-      off[u][t] = (row < rows && src >= 0) ? (int)(src * CIN) : -1;
-    }
+    base[u] = (unsigned)((row < rows ? row : 0) * CIN * 2);
+    edge[u] = (st.r == 0 ? 1u : 0u) | (st.r == L - 1 ? 2u : 0u) | (st.c == 0 ? 4u : 0u) | (st.c == L - 1 ? 8u : 0u) |
+              (row < rows ? 0u : 16u);
   }
-  auto loadA = [&](const int s, uint4 (&ra)[UA]) {
+  const int lrow = L * CIN * 2;   // bytes of one grid row
+  auto tap_at = [&](const int u, const int t) -> unsigned {
+    const unsigned mask = 16u | (t / 3 == 0 ? 1u : 0u) | (t / 3 == 2 ? 2u : 0u) | (t % 3 == 0 ? 4u : 0u) |
+                          (t % 3 == 2 ? 8u : 0u);
+    const int delta = (t / 3 - 1) * lrow + (t % 3 - 1) * CIN * 2;
+    return (edge[u] & mask) ? xbytes : base[u] + (unsigned)delta;
+  };
+  auto loadA = [&](const int s, u32x4 (&ra)[UA]) {
 #pragma unroll
     for (int u = 0; u < UA; ++u) {
-      int o, ch;
+      unsigned o;
+      int ch;
       if constexpr (CIN >= KS) {   // a stage lies inside one tap
-        constexpr int dummy = 0;
-        (void)dummy;
-        const int t = (KS * s) / CIN;
-        o = off[u][t];
+        o = tap_at(u, (KS * s) / CIN);
         ch = (KS * s) % CIN + 8 * ag;
       } else {                     // CIN = 16: a stage spans taps t0 and t0 + 1 (t0 + 1 may be the padding)
         const int t0 = (KS * s) / CIN;
-        const int a0 = off[u][t0 < 9 ? t0 : 8], a1 = off[u][t0 + 1 < 9 ? t0 + 1 : 8];
-        o = (ag >> 1) ? (t0 + 1 < 9 ? a1 : -1) : (t0 < 9 ? a0 : -1);
+        o = (ag >> 1) ? (t0 + 1 < 9 ? tap_at(u, t0 + 1) : xbytes) : (t0 < 9 ? tap_at(u, t0) : xbytes);
         ch = 8 * (ag & 1);
       }
-      ra[u] = (o >= 0) ? *(const uint4*)(X + o + ch) : uint4{0u, 0u, 0u, 0u};
+      ra[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)(o + 2 * ch), 0, 0));
     }
   };
-  auto loadB = [&](const int s, uint4 (&rb)[UB]) {
+  auto loadB = [&](const int s, u32x4 (&rb)[UB]) {
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      const int q = tid + TH * u;
-      rb[u] = (q < NT * 4) ? *(const uint4*)(Wt + (int64_t)(q >> 2) * KP + KS * s + 8 * (q & 3))
-                           : uint4{0u, 0u, 0u, 0u};
+      // past the NT x 4 chunks the load repeats the last one (not stored): no branch around the load
+      const int q = min(tid + TH * u, NT * 4 - 1);
+      rb[u] = *(const u32x4*)(Wt + (int64_t)(q >> 2) * KP + KS * s + 8 * (q & 3));
     }
   };
-  auto store = [&](const int buf, const uint4 (&ra)[UA], const uint4 (&rb)[UB]) {
+  auto store = [&](const int buf, const u32x4 (&ra)[UA], const u32x4 (&rb)[UB]) {
     unsigned short* As = lds + buf * STAGE;
     unsigned short* Bs = As + MT * KS;
 #pragma unroll
-    for (int u = 0; u < UA; ++u) *(uint4*)&As[swz((tid + TH * u) >> 2, ag)] = ra[u];
+    for (int u = 0; u < UA; ++u) *(u32x4*)&As[swz((tid + TH * u) >> 2, ag)] = ra[u];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int q = tid + TH * u;
-      if (q < NT * 4) *(uint4*)&Bs[swz(q >> 2, q & 3)] = rb[u];
+      if ((NT * 4) % TH == 0 || q < NT * 4) *(u32x4*)&Bs[swz(q >> 2, q & 3)] = rb[u];
     }
   };
   f4 acc[4][NJ];
@@ -425,21 +434,23 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
     for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   // two register sets: the loads of stage s + 2 are issued while stage s is multiplied, and stored to LDS
   // at the end of stage s + 1
-  uint4 ra[2][UA], rb[2][UB];
-  loadA(0, ra[0]);
-  loadB(0, rb[0]);
-  store(0, ra[0], rb[0]);
+  u32x4 ra0[UA], rb0[UB], ra1[UA], rb1[UB];
+  loadA(0, ra0);
+  loadB(0, rb0);
+  store(0, ra0, rb0);
   if (NS > 1) {
-    loadA(1, ra[1]);
-    loadB(1, rb[1]);
+    loadA(1, ra1);
+    loadB(1, rb1);
   }
   __syncthreads();
   const int fr = lane & 15, fc = lane >> 4;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
+  // one stage: multiply the LDS buffer s % 2 while the loads of stage s + 2 go into the register set that
+  // stage s + 1 no longer needs; the register sets are named, not indexed, so they stay in registers
+  auto stage = [&](const int s, u32x4 (&ra_next)[UA], u32x4 (&rb_next)[UB], const u32x4 (&ra_due)[UA],
+                   const u32x4 (&rb_due)[UB]) {
     if (s + 2 < NS) {
-      loadA(s + 2, ra[s & 1]);
-      loadB(s + 2, rb[s & 1]);
+      loadA(s + 2, ra_next);
+      loadB(s + 2, rb_next);
     }
     const unsigned short* As = lds + (s & 1) * STAGE;
     const unsigned short* Bs = As + MT * KS;
@@ -452,8 +463,14 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (s + 1 < NS) store((s + 1) & 1, ra[(s + 1) & 1], rb[(s + 1) & 1]);
+    if (s + 1 < NS) store((s + 1) & 1, ra_due, rb_due);
     __syncthreads();
+  };
+  // stage s (even) refills set 0 and stores set 1; stage s + 1 the reverse
+#pragma unroll
+  for (int s = 0; s < NS; s += 2) {
+    stage(s, ra0, rb0, ra1, rb1);
+    if (s + 1 < NS) stage(s + 1, ra1, rb1, ra0, rb0);
   }
   // epilogue: bias, activation; lane l holds rows 4 (l / 16) .. +3 of column l % 16 of every block
   const bool full = m0 + MT <= rows;
@@ -484,6 +501,185 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
     }
     __syncthreads();
     constexpr int CPR = NT / 8;   // 16-byte chunks per row
+#pragma unroll
+    for (int q = tid; q < MT * CPR; q += TH) {
+      const int row = q / CPR, c8 = q - row * CPR;
+      if (full || m0 + row < rows)
+        *(uint4*)((unsigned short*)Y + (m0 + row) * NT + 8 * c8) = *(const uint4*)&lds[row * NT + 8 * c8];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = wn + 16 * j + fr;
+      const float bc = bias[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm + 16 * i + 4 * fc + r;
+          float v = acc[i][j][r] + bc;
+          if (RELU) v = fmaxf(v, 0.0f);
+          if (full || row < rows) ((float*)Y)[row * NT + col] = v;
+        }
+    }
+  }
+}
+
+// The same convolution for CIN >= 64 from a haloed input tile: the 128 output rows of a workgroup read
+// their 3 x 3 neighbourhoods from the contiguous input rows m0 - L - 1 .. m0 + 128 + L, which are staged in
+// LDS once per 32-channel chunk (HALO_ROWS rows of 80 bytes: 64 of data and 16 of padding, so that 16
+// consecutive rows fall on distinct banks) instead of being gathered nine times. K runs chunk by chunk and,
+// inside a chunk, tap by tap; a tap's A fragments are the halo rows shifted by dr L + dc, and a row whose tap
+// leaves the grid reads a zero row instead. Weight stages, register sets and the epilogue are those of the
+// gather kernel. Needs 128 + 2 L + 2 <= HALO_ROWS (L <= 49, d <= 25); larger grids take the gather kernel.
+constexpr int HALO_MT = 128, HALO_ROWS = 228, HALO_RE = 40;   // rows per tile, halo rows, elements per halo row
+
+template <int CIN, int NT, int RELU, bool OUT_BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void conv_halo_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
+                                                       const unsigned short* __restrict__ Wt,
+                                                       const float* __restrict__ bias, void* __restrict__ Y) {
+  constexpr int KS = CONV_KS, KP = 9 * CIN, NC = CIN / KS, NS = 9 * NC;   // k per step, weight row, chunks, steps
+  constexpr int TH = 256, MT = HALO_MT, WN = NT / 2, NJ = WN / 16;
+  constexpr int UB = (NT * 4 + TH - 1) / TH;                 // 16-byte weight chunks per thread and step
+  constexpr int UH = (HALO_ROWS * 4 + TH - 1) / TH;          // 16-byte halo pieces per thread and chunk
+  constexpr int HALO = HALO_ROWS * HALO_RE;                  // elements of one halo buffer
+  constexpr int BST = NT * KS;                               // elements of one weight stage
+  constexpr int TILE = OUT_BF ? MT * NT : 0;
+  constexpr int MAIN = 2 * HALO + 2 * BST + 32;              // two halo buffers, two weight stages, a zero row
+  static_assert(CIN % 64 == 0 && NT % 32 == 0 && NT <= 128 && TILE <= 2 * HALO, "tile shape");
+  __shared__ __align__(16) unsigned short lds[MAIN];
+  unsigned short* const Bsm = lds + 2 * HALO;
+  unsigned short* const zrow = Bsm + 2 * BST;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * WN;
+  const int fr = lane & 15, fc = lane >> 4;
+  const unsigned xbytes = (unsigned)(rows * CIN * 2);   // the host keeps this + 512 below 2^32
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)xbytes, 0x00020000);
+  const int hr = MT + 2 * L + 2;                         // halo rows in use
+  // halo pieces of this thread: row h = p / 4, 16-byte group p % 4; byte offset of channel 0 of the group
+  // (chunk c adds 64 c), xbytes for rows outside the input or the halo
+  unsigned hoff[UH];
+#pragma unroll
+  for (int u = 0; u < UH; ++u) {
+    const int p = tid + TH * u, h = p >> 2;
+    const int64_t g = m0 - L - 1 + h;
+    hoff[u] = (h < hr && g >= 0 && g < rows) ? (unsigned)(g * CIN * 2 + 16 * (p & 3)) : xbytes;
+  }
+  // A fragment rows of this lane (i = 0..3): halo element offset of the unshifted row and group fc, and where
+  // the row sits on the grid (bit 0: first grid row, 1: last grid row, 2: first column, 3: last column)
+  int abase[4];
+  unsigned edge[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = wm + 16 * i + fr;
+    abase[i] = (r + L + 1) * HALO_RE + 8 * fc;
+    const int64_t row = m0 + r;
+    const Site st = site_of(row < rows ? row : 0, L);
+    edge[i] = (st.r == 0 ? 1u : 0u) | (st.r == L - 1 ? 2u : 0u) | (st.c == 0 ? 4u : 0u) | (st.c == L - 1 ? 8u : 0u);
+  }
+  auto loadH = [&](const int c, u32x4 (&rh)[UH]) {
+#pragma unroll
+    for (int u = 0; u < UH; ++u)
+      rh[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)(hoff[u] + 64 * c), 0, 0));
+  };
+  auto storeH = [&](const int buf, const u32x4 (&rh)[UH]) {
+#pragma unroll
+    for (int u = 0; u < UH; ++u) {
+      const int p = tid + TH * u, h = p >> 2;
+      if ((UH * TH <= HALO_ROWS * 4) || h < HALO_ROWS) *(u32x4*)&lds[buf * HALO + h * HALO_RE + 8 * (p & 3)] = rh[u];
+    }
+  };
+  auto loadB = [&](const int s, u32x4 (&rb)[UB]) {
+    const int k0 = (s % 9) * CIN + KS * (s / 9);   // step s: tap s % 9, channels 32 (s / 9) ..
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int q = min(tid + TH * u, NT * 4 - 1);   // past the NT x 4 chunks: the last one again, not stored
+      rb[u] = *(const u32x4*)(Wt + (int64_t)(q >> 2) * KP + k0 + 8 * (q & 3));
+    }
+  };
+  auto storeB = [&](const int buf, const u32x4 (&rb)[UB]) {
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int q = tid + TH * u;
+      if ((NT * 4) % TH == 0 || q < NT * 4) *(u32x4*)&Bsm[buf * BST + swz(q >> 2, q & 3)] = rb[u];
+    }
+  };
+  f4 acc[4][NJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  u32x4 rh[UH], rb0[UB], rb1[UB];
+  loadH(0, rh);
+  loadB(0, rb0);
+  storeH(0, rh);
+  storeB(0, rb0);
+  loadB(1, rb1);
+  if (tid < 4) *(u32x4*)&zrow[8 * tid] = (u32x4){0u, 0u, 0u, 0u};
+  __syncthreads();
+  // step s: chunk c = s / 9, tap t = s % 9; the weights of step s + 2 load into the set step s + 1 does not
+  // need; the next chunk's halo loads at its first tap and goes to LDS after its third
+  auto step = [&](const int s, u32x4 (&rb_next)[UB], const u32x4 (&rb_due)[UB]) {
+    const int c = s / 9, t = s % 9;
+    if (s + 2 < NS) loadB(s + 2, rb_next);
+    if (t == 0 && c + 1 < NC) loadH(c + 1, rh);
+    const unsigned short* Hs = lds + (c & 1) * HALO;
+    // the fragment addresses are formed anew each step: kept from the step two chunks back (same buffer, same
+    // tap) they would hold 72 registers for the whole kernel
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(abase[i]), "+v"(edge[i]));
+    const int sh = ((t / 3 - 1) * L + (t % 3 - 1)) * HALO_RE;
+    const unsigned off_grid = (t / 3 == 0 ? 1u : 0u) | (t / 3 == 2 ? 2u : 0u) | (t % 3 == 0 ? 4u : 0u) |
+                              (t % 3 == 2 ? 8u : 0u);   // edges across which tap t leaves the grid
+    const unsigned short* Bs = Bsm + (s & 1) * BST;
+    bf8 a[4], b[NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned short* pa = (edge[i] & off_grid) ? zrow + 8 * fc : Hs + abase[i] + sh;
+      a[i] = *(const bf8*)pa;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[j] = *(const bf8*)&Bs[swz(wn + 16 * j + fr, fc)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (t == 2 && c + 1 < NC) storeH((c + 1) & 1, rh);
+    if (s + 1 < NS) storeB((s + 1) & 1, rb_due);
+    __syncthreads();
+  };
+#pragma unroll
+  for (int s = 0; s < NS; s += 2) {
+    step(s, rb0, rb1);
+    if (s + 1 < NS) step(s + 1, rb1, rb0);
+  }
+  // epilogue: bias, activation; lane l holds rows 4 (l / 16) .. +3 of column l % 16 of every block
+  const bool full = m0 + MT <= rows;
+  if constexpr (OUT_BF) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = wn + 16 * j + fr;
+      const float bc = bias[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = acc[i][j][r] + bc;
+          if (RELU) v[r] = fmaxf(v[r], 0.0f);
+        }
+        const unsigned p01 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[0], v[1]}, bf2));
+        const unsigned p23 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[2], v[3]}, bf2));
+        const int row = wm + 16 * i + 4 * fc;
+        lds[(row + 0) * NT + col] = (unsigned short)(p01 & 0xFFFFu);
+        lds[(row + 1) * NT + col] = (unsigned short)(p01 >> 16);
+        lds[(row + 2) * NT + col] = (unsigned short)(p23 & 0xFFFFu);
+        lds[(row + 3) * NT + col] = (unsigned short)(p23 >> 16);
+      }
+    }
+    __syncthreads();
+    constexpr int CPR = NT / 8;
 #pragma unroll
     for (int q = tid; q < MT * CPR; q += TH) {
       const int row = q / CPR, c8 = q - row * CPR;
@@ -968,8 +1164,17 @@ struct Args {
 template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
 int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short* Wt, const float* bias, void* Y,
               hipStream_t st) {
-  // the kernel addresses the activations with 32-bit element offsets
-  if (rows * CIN > (int64_t)INT32_MAX) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
+  // the kernel addresses the activations through one buffer descriptor with 32-bit byte offsets, the
+  // out-of-grid sentinel (the buffer's size) plus a channel offset included
+  if (rows * CIN > (int64_t)INT32_MAX - 512) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
+  if constexpr (CIN >= 64) {
+    if (HALO_MT + 2 * L + 2 <= HALO_ROWS) {
+      conv_halo_bf16<CIN, NT, RELU, OUT_BF><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
+          L, rows, X, Wt, bias, Y);
+      W_TRY(hipGetLastError());
+      return BBP_OK;
+    }
+  }
   conv_fwd_bf16<CIN, NT, WM, RELU, OUT_BF><<<dim3((unsigned)((rows + 64 * WM - 1) / (64 * WM))), dim3(128 * WM), 0, st>>>(
       L, rows, X, Wt, bias, Y);
   W_TRY(hipGetLastError());
