@@ -525,73 +525,103 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
   }
 }
 
-// The same convolution for CIN >= 64 from a haloed input tile: the 128 output rows of a workgroup read
-// their 3 x 3 neighbourhoods from the contiguous input rows m0 - L - 1 .. m0 + 128 + L, which are staged in
-// LDS once per 32-channel chunk (HALO_ROWS rows of 80 bytes: 64 of data and 16 of padding, so that 16
-// consecutive rows fall on distinct banks) instead of being gathered nine times. K runs chunk by chunk and,
-// inside a chunk, tap by tap; a tap's A fragments are the halo rows shifted by dr L + dc, and a row whose tap
-// leaves the grid reads a zero row instead. Weight stages, register sets and the epilogue are those of the
-// gather kernel. Needs 128 + 2 L + 2 <= HALO_ROWS (L <= 49, d <= 25); larger grids take the gather kernel.
-constexpr int HALO_MT = 128, HALO_ROWS = 228, HALO_RE = 40;   // rows per tile, halo rows, elements per halo row
+// The same convolution from a haloed input tile: the 128 output rows of a workgroup read their 3 x 3
+// neighbourhoods from the contiguous input rows m0 - L - 1 .. m0 + 128 + L, which are staged in LDS once per
+// chunk of up to 32 channels (HALO_ROWS rows, each padded by 16 bytes so that 16 consecutive rows fall on
+// distinct banks) instead of being gathered nine times. With CIN >= 32, K runs chunk by chunk and, inside a
+// chunk, tap by tap (one 32-deep step each); with CIN = 16 a step holds two taps (lanes 0-31 the first, 32-63
+// the second; the tenth tap is the weights' zero padding). A tap's A fragments are the halo rows shifted by
+// dr L + dc, and a row whose tap leaves the grid reads a zero row instead. Weight stages, register sets and the
+// BF16 epilogue are those of the gather kernel. Needs 128 + 2 L + 2 <= HALO_ROWS (L <= 49, d <= 25); larger
+// grids take the gather kernel.
+constexpr int HALO_MT = 128, HALO_ROWS = 228;   // rows per tile, halo rows
 
 template <int CIN, int NT, int RELU, bool OUT_BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void conv_halo_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
                                                        const unsigned short* __restrict__ Wt,
                                                        const float* __restrict__ bias, void* __restrict__ Y) {
-  constexpr int KS = CONV_KS, KP = 9 * CIN, NC = CIN / KS, NS = 9 * NC;   // k per step, weight row, chunks, steps
+  constexpr int KS = CONV_KS, KP = kpad(CIN);                // k per step, weight row
+  constexpr int CH = CIN < KS ? CIN : KS, NC = CIN / CH;     // channels per chunk, chunks
+  constexpr int NS = CIN < KS ? KP / KS : 9 * NC;            // steps
+  constexpr int RE = CH + 8, RP = CH / 8;                    // elements and 16-byte pieces per halo row
   constexpr int TH = 256, MT = HALO_MT, WN = NT / 2, NJ = WN / 16;
   constexpr int UB = (NT * 4 + TH - 1) / TH;                 // 16-byte weight chunks per thread and step
-  constexpr int UH = (HALO_ROWS * 4 + TH - 1) / TH;          // 16-byte halo pieces per thread and chunk
-  constexpr int HALO = HALO_ROWS * HALO_RE;                  // elements of one halo buffer
+  constexpr int UH = (HALO_ROWS * RP + TH - 1) / TH;         // 16-byte halo pieces per thread and chunk
+  constexpr int NH = NC > 1 ? 2 : 1, HALO = HALO_ROWS * RE;  // halo buffers, elements of one
   constexpr int BST = NT * KS;                               // elements of one weight stage
-  constexpr int TILE = OUT_BF ? MT * NT : 0;
-  constexpr int MAIN = 2 * HALO + 2 * BST + 32;              // two halo buffers, two weight stages, a zero row
-  static_assert(CIN % 64 == 0 && NT % 32 == 0 && NT <= 128 && TILE <= 2 * HALO, "tile shape");
-  __shared__ __align__(16) unsigned short lds[MAIN];
-  unsigned short* const Bsm = lds + 2 * HALO;
+  constexpr int TILE = OUT_BF ? MT * (NT + 16) : 0;          // BF16 output tile (padded rows)
+  constexpr int MAIN = NH * HALO + 2 * BST + 32;             // halo buffers, two weight stages, a zero row
+  static_assert((CIN == 16 || CIN % 32 == 0) && NT % 32 == 0 && NT <= 128, "tile shape");
+  __shared__ __align__(16) unsigned short lds[MAIN > TILE ? MAIN : TILE];
+  unsigned short* const Bsm = lds + NH * HALO;
   unsigned short* const zrow = Bsm + 2 * BST;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  // workgroups are dealt to the eight XCDs in turn; tile b / 8 of XCD b % 8 is made consecutive with the
+  // XCD's previous tile, so the halo rows that neighbouring tiles share are found in that XCD's L2
+  const unsigned nb = gridDim.x, per = nb / 8, bid = blockIdx.x;
+  const unsigned tile = bid < 8 * per ? (bid % 8) * per + bid / 8 : bid;
+  const int64_t m0 = (int64_t)tile * MT;
   const int wm = (w >> 1) * 64, wn = (w & 1) * WN;
   const int fr = lane & 15, fc = lane >> 4;
   const unsigned xbytes = (unsigned)(rows * CIN * 2);   // the host keeps this + 512 below 2^32
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)xbytes, 0x00020000);
   const int hr = MT + 2 * L + 2;                         // halo rows in use
-  // halo pieces of this thread: row h = p / 4, 16-byte group p % 4; byte offset of channel 0 of the group
-  // (chunk c adds 64 c), xbytes for rows outside the input or the halo
+  // (rows < 2^31: 32-bit row arithmetic)
+  const int g0 = (int)m0 - L - 1;                        // input row of halo row 0
+  // halo pieces of this thread: row h = p / RP, 16-byte group p % RP; byte offset of channel 0 of the group
+  // (chunk c adds 2 CH c), xbytes for rows outside the input or the halo
   unsigned hoff[UH];
 #pragma unroll
   for (int u = 0; u < UH; ++u) {
-    const int p = tid + TH * u, h = p >> 2;
-    const int64_t g = m0 - L - 1 + h;
-    hoff[u] = (h < hr && g >= 0 && g < rows) ? (unsigned)(g * CIN * 2 + 16 * (p & 3)) : xbytes;
+    const int p = tid + TH * u, h = p / RP, g = g0 + h;
+    hoff[u] = (h < hr && g >= 0 && (int64_t)g < rows) ? (unsigned)g * (2u * CIN) + 16u * (p % RP) : xbytes;
   }
-  // A fragment rows of this lane (i = 0..3): halo element offset of the unshifted row and group fc, and where
-  // the row sits on the grid (bit 0: first grid row, 1: last grid row, 2: first column, 3: last column)
+  // A fragment rows of this lane (i = 0..3): halo element offset of the unshifted row and its 8 channels, and
+  // where the row sits on the grid (bit 0: first grid row, 1: last grid row, 2: first column, 3: last column;
+  // bit 4 always set: the padding tap reads the zero row for every row). The row's place in its job's grid
+  // comes from the tile's (uniform) and small quotients by L^2 and by L per lane: x < L^2 + 128, so the FP32
+  // quotient is off by at most one, which the remainder tests correct.
+  const int LL = L * L;
+  const int rem0 = (int)((unsigned)m0 % (unsigned)LL);
+  const float rl = 1.0f / (float)L, rll = 1.0f / (float)LL;
+  auto quot = [](const int x, const int n, const float rn, int& rem) {
+    int q = (int)((float)x * rn);
+    rem = x - q * n;
+    if (rem >= n) {
+      ++q;
+      rem -= n;
+    } else if (rem < 0) {
+      --q;
+      rem += n;
+    }
+    return q;
+  };
   int abase[4];
   unsigned edge[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = wm + 16 * i + fr;
-    abase[i] = (r + L + 1) * HALO_RE + 8 * fc;
-    const int64_t row = m0 + r;
-    const Site st = site_of(row < rows ? row : 0, L);
-    edge[i] = (st.r == 0 ? 1u : 0u) | (st.r == L - 1 ? 2u : 0u) | (st.c == 0 ? 4u : 0u) | (st.c == L - 1 ? 8u : 0u);
+    abase[i] = (r + L + 1) * RE + 8 * (CIN < KS ? (fc & 1) : fc);
+    int site, col;
+    quot(rem0 + r, LL, rll, site);
+    const int gr = quot(site, L, rl, col);
+    edge[i] = 16u | (gr == 0 ? 1u : 0u) | (gr == L - 1 ? 2u : 0u) | (col == 0 ? 4u : 0u) | (col == L - 1 ? 8u : 0u);
   }
   auto loadH = [&](const int c, u32x4 (&rh)[UH]) {
 #pragma unroll
     for (int u = 0; u < UH; ++u)
-      rh[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)(hoff[u] + 64 * c), 0, 0));
+      rh[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)(hoff[u] + 2 * CH * c), 0, 0));
   };
   auto storeH = [&](const int buf, const u32x4 (&rh)[UH]) {
 #pragma unroll
     for (int u = 0; u < UH; ++u) {
-      const int p = tid + TH * u, h = p >> 2;
-      if ((UH * TH <= HALO_ROWS * 4) || h < HALO_ROWS) *(u32x4*)&lds[buf * HALO + h * HALO_RE + 8 * (p & 3)] = rh[u];
+      const int p = tid + TH * u, h = p / RP;
+      if ((UH * TH <= HALO_ROWS * RP) || h < HALO_ROWS) *(u32x4*)&lds[buf * HALO + h * RE + 8 * (p % RP)] = rh[u];
     }
   };
   auto loadB = [&](const int s, u32x4 (&rb)[UB]) {
-    const int k0 = (s % 9) * CIN + KS * (s / 9);   // step s: tap s % 9, channels 32 (s / 9) ..
+    // step s: tap s % 9, channels 32 (s / 9) .. (CIN >= 32), or taps 2 s, 2 s + 1 (CIN = 16)
+    const int k0 = CIN < KS ? KS * s : (s % 9) * CIN + KS * (s / 9);
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int q = min(tid + TH * u, NT * 4 - 1);   // past the NT x 4 chunks: the last one again, not stored
@@ -620,8 +650,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   __syncthreads();
   // step s: chunk c = s / 9, tap t = s % 9; the weights of step s + 2 load into the set step s + 1 does not
   // need; the next chunk's halo loads at its first tap and goes to LDS after its third
+  // edge bits across which tap t leaves the grid (bit 4 for the padding tap 9), and the tap's row shift
+  auto off_grid = [](const int t) -> unsigned {
+    return t > 8 ? 16u
+                 : (t / 3 == 0 ? 1u : 0u) | (t / 3 == 2 ? 2u : 0u) | (t % 3 == 0 ? 4u : 0u) | (t % 3 == 2 ? 8u : 0u);
+  };
+  auto shift = [&](const int t) { return t > 8 ? 0 : ((t / 3 - 1) * L + (t % 3 - 1)) * RE; };
   auto step = [&](const int s, u32x4 (&rb_next)[UB], const u32x4 (&rb_due)[UB]) {
-    const int c = s / 9, t = s % 9;
+    const int c = CIN < KS ? 0 : s / 9, t = CIN < KS ? 2 * s : s % 9;
     if (s + 2 < NS) loadB(s + 2, rb_next);
     if (t == 0 && c + 1 < NC) loadH(c + 1, rh);
     const unsigned short* Hs = lds + (c & 1) * HALO;
@@ -629,14 +665,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
     // tap) they would hold 72 registers for the whole kernel
 #pragma unroll
     for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(abase[i]), "+v"(edge[i]));
-    const int sh = ((t / 3 - 1) * L + (t % 3 - 1)) * HALO_RE;
-    const unsigned off_grid = (t / 3 == 0 ? 1u : 0u) | (t / 3 == 2 ? 2u : 0u) | (t % 3 == 0 ? 4u : 0u) |
-                              (t % 3 == 2 ? 8u : 0u);   // edges across which tap t leaves the grid
+    // this lane's tap: t, or with CIN = 16 t + 1 for lanes 32-63
+    const bool second = CIN < KS && fc >= 2;
+    const int sh = second ? shift(t + 1) : shift(t);
+    const unsigned og = second ? off_grid(t + 1) : off_grid(t);
     const unsigned short* Bs = Bsm + (s & 1) * BST;
     bf8 a[4], b[NJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const unsigned short* pa = (edge[i] & off_grid) ? zrow + 8 * fc : Hs + abase[i] + sh;
+      const unsigned short* pa = (edge[i] & og) ? zrow + 8 * fc : Hs + abase[i] + sh;
       a[i] = *(const bf8*)pa;
     }
 #pragma unroll
@@ -644,7 +681,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
     if (t == 2 && c + 1 < NC) storeH((c + 1) & 1, rh);
     if (s + 1 < NS) storeB((s + 1) & 1, rb_due);
     __syncthreads();
@@ -654,52 +691,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
     step(s, rb0, rb1);
     if (s + 1 < NS) step(s + 1, rb1, rb0);
   }
-  // epilogue: bias, activation; lane l holds rows 4 (l / 16) .. +3 of column l % 16 of every block
+  // epilogue: bias, activation. The weights are the MFMA's first operand, so lane l holds output channels
+  // 4 (l / 16) .. +3 of site l % 16 of every 16 x 16 block: four consecutive values of one output row.
   const bool full = m0 + MT <= rows;
   if constexpr (OUT_BF) {
+    // BF16 tile [MT][NT + 16] in LDS (rows padded by 32 bytes against bank conflicts of the 8-byte writes),
+    // then 16-byte rows out
+    constexpr int TS = NT + 16, CPR = NT / 8;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int col = wn + 16 * j + fr;
-      const float bc = bias[col];
+      const int ch = wn + 16 * j + 4 * fc;
+      const float b0 = bias[ch], b1 = bias[ch + 1], b2 = bias[ch + 2], b3 = bias[ch + 3];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          v[r] = acc[i][j][r] + bc;
-          if (RELU) v[r] = fmaxf(v[r], 0.0f);
+        float v0 = acc[i][j][0] + b0, v1 = acc[i][j][1] + b1, v2 = acc[i][j][2] + b2, v3 = acc[i][j][3] + b3;
+        if (RELU) {
+          v0 = fmaxf(v0, 0.0f);
+          v1 = fmaxf(v1, 0.0f);
+          v2 = fmaxf(v2, 0.0f);
+          v3 = fmaxf(v3, 0.0f);
         }
-        const unsigned p01 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[0], v[1]}, bf2));
-        const unsigned p23 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v[2], v[3]}, bf2));
-        const int row = wm + 16 * i + 4 * fc;
-        lds[(row + 0) * NT + col] = (unsigned short)(p01 & 0xFFFFu);
-        lds[(row + 1) * NT + col] = (unsigned short)(p01 >> 16);
-        lds[(row + 2) * NT + col] = (unsigned short)(p23 & 0xFFFFu);
-        lds[(row + 3) * NT + col] = (unsigned short)(p23 >> 16);
+        // two values per v_cvt_pk_bf16_f32 (round to nearest even), each pair taken as one 32-bit word
+        const unsigned p01 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v0, v1}, bf2));
+        const unsigned p23 = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){v2, v3}, bf2));
+        *(uint2*)&lds[(wm + 16 * i + fr) * TS + ch] = uint2{p01, p23};
       }
     }
     __syncthreads();
-    constexpr int CPR = NT / 8;
 #pragma unroll
     for (int q = tid; q < MT * CPR; q += TH) {
       const int row = q / CPR, c8 = q - row * CPR;
       if (full || m0 + row < rows)
-        *(uint4*)((unsigned short*)Y + (m0 + row) * NT + 8 * c8) = *(const uint4*)&lds[row * NT + 8 * c8];
+        *(uint4*)((unsigned short*)Y + (m0 + row) * NT + 8 * c8) = *(const uint4*)&lds[row * TS + 8 * c8];
     }
   } else {
+    // FP32: four consecutive channels are one 16-byte store
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int col = wn + 16 * j + fr;
-      const float bc = bias[col];
+      const int ch = wn + 16 * j + 4 * fc;
+      const float b0 = bias[ch], b1 = bias[ch + 1], b2 = bias[ch + 2], b3 = bias[ch + 3];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + wm + 16 * i + 4 * fc + r;
-          float v = acc[i][j][r] + bc;
-          if (RELU) v = fmaxf(v, 0.0f);
-          if (full || row < rows) ((float*)Y)[row * NT + col] = v;
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = m0 + wm + 16 * i + fr;
+        float4 v{acc[i][j][0] + b0, acc[i][j][1] + b1, acc[i][j][2] + b2, acc[i][j][3] + b3};
+        if (RELU) {
+          v.x = fmaxf(v.x, 0.0f);
+          v.y = fmaxf(v.y, 0.0f);
+          v.z = fmaxf(v.z, 0.0f);
+          v.w = fmaxf(v.w, 0.0f);
         }
+        if (full || row < rows) *(float4*)((float*)Y + row * NT + ch) = v;
+      }
     }
   }
 }
@@ -1167,7 +1209,7 @@ int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short
   // the kernel addresses the activations through one buffer descriptor with 32-bit byte offsets, the
   // out-of-grid sentinel (the buffer's size) plus a channel offset included
   if (rows * CIN > (int64_t)INT32_MAX - 512) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
-  if constexpr (CIN >= 64) {
+  {
     if (HALO_MT + 2 * L + 2 <= HALO_ROWS) {
       conv_halo_bf16<CIN, NT, RELU, OUT_BF><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
           L, rows, X, Wt, bias, Y);
