@@ -9,7 +9,7 @@
 //          unchanged to distances it was not trained on;
 //   trunk  three 3x3 convolutions with zero padding (11 -> 64 -> 128 -> 96 channels), ReLU after the first
 //          two; each is an implicit GEMM on the matrix cores: FP32 (v_mfma_f32_16x16x4f32) for training and
-//          for parity, or BF16 weights and activations with FP32 sums (v_mfma_f32_16x16x16bf16) for inference;
+//          for parity, or BF16 weights and activations with FP32 sums (v_mfma_f32_16x16x32_bf16) for inference;
 //          activations are row-major [site][channel];
 //   head   per directed message with K legs (leg i joins site a_i of the sender to site b_i across the
 //          boundary), with f_i = [F(a_i), F(b_i)] and the weights of the message's direction:
@@ -323,7 +323,8 @@ __global__ __launch_bounds__(256) void conv_gemm(int L, int64_t rows, int cin, i
 // (one barrier per step), the global loads two steps ahead in flight (two register sets). A 16-byte load is 8
 // channels of one tap (CIN is a multiple of 16) at an offset computed once per row and tap; the weights come
 // transposed, Wt[co][k], k padded to a multiple of the stage with zeros, so both LDS tiles are k-contiguous.
-// BF16 outputs leave through an LDS tile in 16-byte rows.
+// BF16 outputs leave through an LDS tile in 16-byte rows. This gather kernel serves grids too large for the
+// haloed tile of conv_halo_bf16 below (L > 49).
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes staged through registers
 
