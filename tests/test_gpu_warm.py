@@ -84,7 +84,9 @@ def test_forward_messages_against_oracle(dev, d, k):
     assert np.abs(got[..., :8] - got[..., :1]).max() > 0.05
 
 
-@pytest.mark.parametrize("d,k", [(5, 3), (9, 6)])
+# d=25: the largest grid (L=49) of the haloed-tile convolutions, whose halo then fills its LDS rows exactly;
+# d=27 (L=53): the gather kernels that serve larger grids
+@pytest.mark.parametrize("d,k", [(5, 3), (9, 6), (25, 6), (27, 6)])
 def test_bf16_forward_against_oracle(dev, d, k):
     """Inference precision: BF16 convolution weights, input channels and hidden activations, FP32 sums, the last
     convolution composed with the head (its per-site projections). The oracle runs the same arithmetic in FP64

@@ -43,6 +43,28 @@ def test_noalloc_equals_workspace_decode_two_calls():
         np.testing.assert_array_equal(workload.syndrome_of(d, got["correction"]), syn)
 
 
+def test_noalloc_truncating_plan_equals_workspace_decode():
+    # a plan with truncating sweeps (6x6 blocks at chi 8): their per-sweep workspace slots also sit in the
+    # static array
+    import torch
+    import paper_2402_04834_amd as bbp
+    dev = torch.device("cuda:0")
+    d, p, batch = 7, 0.10, 3
+    opts = bbp.default_opts(block=6, chi=8, max_iter=4, fixed_iters=1)
+    assert bbp.plan_query(d, opts).truncating_sweeps > 0
+    assert batch <= bbp.noalloc_max_batch(d, opts)
+    _, syn = workload.make_batch(d, p, batch, workload="test", p_index=91)
+    s = torch.from_numpy(syn).to(dev)
+    _say(f"[noalloc] d={d} batch={batch} blocks 6 chi 8 (truncating sweeps)")
+    got = _np(bbp.decode_device_noalloc(d, p, s, opts))
+    torch.cuda.synchronize()
+    ref = _np(bbp.decode_device(d, p, s, opts))
+    torch.cuda.synchronize()
+    for key in ref:
+        np.testing.assert_array_equal(got[key], ref[key], err_msg=key)
+    np.testing.assert_array_equal(workload.syndrome_of(d, got["correction"]), syn)
+
+
 def test_noalloc_limit_is_refused():
     import torch
     import paper_2402_04834_amd as bbp
