@@ -179,8 +179,10 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
 #pragma unroll
     for (int k = 0; k < 16; ++k) own += y[k] * y[k];
     own += __shfl_xor(own, 1);
-    for (int rd = 0; rd < 31; ++rd) {
-      const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : (2 * rd - hi + 62) % 31;
+    // round rd pairs rows hi and pl: 31 and rd, the others (2 rd - hi) mod 31, stepped by 2 each round
+    int cyc = (62 - hi) % 31;
+    for (int rd = 0; rd < 31; ++rd, cyc = (cyc + 2 >= 31) ? cyc + 2 - 31 : cyc + 2) {
+      const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : cyc;
 #pragma unroll
       for (int k = 0; k < 16; ++k) Xsh[ln * XS + k] = y[k];
       Xsh[ln * XS + 16] = own;
@@ -201,11 +203,12 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
       c2max = c2 > c2max ? c2 : c2max;
       if (c2 > JAC * JAC) {
         // The angle only has to bring the pair closer to orthogonal, so t = tan(theta) (the smaller root) is
-        // formed in FP32 (fast reciprocal and square root; above the noise threshold zeta stays within 1e30);
+        // formed in FP32 (the hardware's approximate reciprocal and square root, one instruction each; above the
+        // noise threshold zeta stays within 1e30);
         // cos and sin are then formed in FP64 from that t, so that the rotation is orthogonal to FP64
         // rounding.
         const float zf = (float)(be - al) * __builtin_amdgcn_rcpf(2.0f * (float)gg), azf = fabsf(zf);
-        const float denf = azf + (azf < 1e18f ? __builtin_sqrtf(fmaf(zf, zf, 1.0f)) : azf);
+        const float denf = azf + (azf < 1e18f ? __builtin_amdgcn_sqrtf(fmaf(zf, zf, 1.0f)) : azf);
         const double tt = (double)copysignf(__builtin_amdgcn_rcpf(denf), zf);
         const double xx = tt * tt + 1.0;
         double cs = __builtin_amdgcn_rsq(xx);
