@@ -228,10 +228,15 @@ struct ClassRun {
   double flops;   // algorithmic flops of these sweeps for one job
 };
 
-// Sort a sweep list by class (the sweeps of one list are independent) and cut it into launches.
+// Sort a sweep list by class (the sweeps of one list are independent) and cut it into launches. Truncating
+// sweeps, whose costs differ several-fold with their length and width, go longest first, so that the short
+// ones fill the end of a launch.
 std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
-  std::stable_sort(v.begin(), v.end(),
-                   [](const SweepDesc& a, const SweepDesc& b) { return bbp::sweep_class(a) < bbp::sweep_class(b); });
+  std::stable_sort(v.begin(), v.end(), [](const SweepDesc& a, const SweepDesc& b) {
+    const int ca = bbp::sweep_class(a), cb = bbp::sweep_class(b);
+    if (ca != cb) return ca < cb;
+    return ca == bbp::TRUNC_CLASS && a.flops > b.flops;
+  });
   std::vector<ClassRun> runs;
   for (int i = 0; i < (int)v.size(); ++i) {
     const int c = bbp::sweep_class(v[i]);
@@ -338,7 +343,7 @@ struct Layout {
 
 // Workspace slots of the truncating kernel: one per item of its largest launch, at most this many (larger
 // launches run in chunks).
-constexpr int64_t TRUNC_SLOTS_MAX = 4096;
+constexpr int64_t TRUNC_SLOTS_MAX = 32768;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

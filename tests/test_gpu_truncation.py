@@ -159,3 +159,25 @@ def test_truncating_start_messages_and_ragged_batches(dev):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(part["messages"].cpu().numpy(), m4[lo:hi])
         np.testing.assert_array_equal(part["loglik"].cpu().numpy(), four["loglik"].cpu().numpy()[lo:hi])
+
+
+def test_truncating_launch_in_several_chunks(dev):
+    # a round with more truncating items than one launch has workspace slots for (32768) runs in chunks:
+    # every syndrome decodes bit for bit as it does alone. 19 truncating sweeps over three lists put at least
+    # 7 in one, so 1200 syndromes (4800 jobs) make at least 33600 items.
+    import torch
+    import paper_2402_04834_amd as bbp
+    d, k, chi, n = 9, 6, 8, 1200
+    opts = bbp.default_opts(block=k, chi=chi, max_iter=2, fixed_iters=1)
+    assert bbp.plan_query(d, opts).truncating_sweeps == 19
+    _, syn = workload.make_batch(d, 0.1, n, workload="test", p_index=17)
+    st = torch.from_numpy(syn).to(dev)
+    _say(f"[trunc-chunks] d={d} k={k} chi={chi} batch={n}")
+    big = bbp.decode_device(d, 0.1, st, opts, messages=True)
+    torch.cuda.synchronize()
+    bm, bl = big["messages"].cpu().numpy(), big["loglik"].cpu().numpy()
+    for i in (0, 611, n - 1):
+        one = bbp.decode_device(d, 0.1, st[i:i + 1].contiguous(), opts, messages=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(one["messages"].cpu().numpy()[0], bm[i], err_msg=f"syndrome {i}")
+        np.testing.assert_array_equal(one["loglik"].cpu().numpy()[0], bl[i], err_msg=f"syndrome {i}")
