@@ -48,7 +48,7 @@ constexpr int W_CT = W_Q + (KM + 2) * TQ;   // cap operators: top t = 0 .. kt-1,
 constexpr int W_SLOT = W_CT + 2 * KM * TS;
 
 // LDS pool in doubles (the phases never overlap)
-constexpr int P1 = 32 * 32 + 2 * 64 + 32 + 3 * TS;            // R carry, vector buffers, betas, site, CT, Bb
+constexpr int P1 = 32 * 32 + 2 * 64 + 32 + 2 * TS;            // R carry, vector buffers, betas, site, CT (or Bb)
 constexpr int P2 = 64 * XS + 32 * 16 + 32;                    // exchange (then V), carry C, singular values
 constexpr int PC = 256 + 32 * 32 + 32;                        // chain: matrix, vectors, betas
 constexpr int PE = 4 * 256;                                   // end: left / right chains (ping-pong)
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
     double* Hb = vb + 2 * 64;
     double* Ash = Hb + 32;
     double* CTs = Ash + TS;
-    double* Bb = CTs + TS;
+    double* Bb = CTs;   // the bottom cap's product replaces the cap operator it is formed from
     double x[32], rd;
     // top cap: M_0[q'][(d, v)] = sum_P S_0[P][d] CT[P][v][q'], rows q' < 16
     for (int e = ln; e < 256; e += 64) Ash[e] = A[e];
@@ -278,15 +278,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
     if (bot)
       for (int e = ln; e < TS; e += 64) CTs[e] = CT[(KM + t) * TS + e];
     __syncthreads();
-    for (int e = ln; e < 512; e += 64) {
-      const int dv = e >> 4, q = e & 15, d = dv >> 1, v = dv & 1;
-      double acc = 0.0;
-      if (bot) {
-        for (int P = 0; P < 16; ++P) acc += Ash[d * 16 + P] * CTs[P * 32 + v * 16 + q];
-      } else if (v == 0 && q == 0) {
-        acc = Ash[d * 16];
+    {
+      double bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = ln + 64 * u, dv = e >> 4, q = e & 15, d = dv >> 1, v = dv & 1;
+        double acc = 0.0;
+        if (bot) {
+          for (int P = 0; P < 16; ++P) acc += Ash[d * 16 + P] * CTs[P * 32 + v * 16 + q];
+        } else if (v == 0 && q == 0) {
+          acc = Ash[d * 16];
+        }
+        bv[u] = acc;
       }
-      Bb[e] = acc;
+      __syncthreads();   // every lane has read the operator before Bb overwrites it
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bb[ln + 64 * u] = bv[u];
     }
     __syncthreads();
     {
