@@ -224,7 +224,9 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
         rotated = 1;
       }
     }
-    if (!__any(rotated) || wmax(c2max) < 1e-16) break;
+    // a sweep whose pairs all started within cos 1e-6 of orthogonal leaves them within about 1e-12
+    // (quadratic convergence): far below the FP32 messages the singular vectors end up in
+    if (!__any(rotated) || wmax(c2max) < 1e-12) break;
   }
   double s2 = 0.0;
 #pragma unroll
