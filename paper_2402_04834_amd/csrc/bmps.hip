@@ -178,7 +178,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         continue;
       }
       T rd;
-      qr64(x, rd, 32, vb, Hb);
+      qr64u<32>(x, rd, vb, Hb);
       logs += store_r(x, rd, Rsh);
       store_v(x, 32, Hb, Qr);
     }

@@ -269,7 +269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         }
       }
       __syncthreads();   // every lane has read R
-      qr64(x, rd, 32, vb, Hb);
+      qr64u<32>(x, rd, vb, Hb);
       logs += store_r(x, rd, Rsh);
       store_v(x, 32, Hb, Q + i * TQ);
     }

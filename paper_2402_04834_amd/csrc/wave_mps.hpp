@@ -88,6 +88,58 @@ __device__ __forceinline__ void qr64(double (&x)[32], double& rd, int jmax, doub
   __syncthreads();
 }
 
+// qr64 with the reflections unrolled (JMAX = jmax): reflection j touches rows >= j only, i.e. registers
+// k >= j / 2, and its pivot row is a compile-time register, so the vector's rows above the pivot are neither
+// stored, read nor multiplied, and the pivot takes one select instead of one per register. (Used for the
+// 32-reflection factorisations; an unrolled 16-reflection instance beside it in the truncating kernel took
+// the compiler beyond 40 minutes.)
+template <int JMAX>
+__device__ __forceinline__ void qr64u(double (&x)[32], double& rd, double* vb, double* Hb) {
+  const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
+  rd = 0.0;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) {
+    const int k0 = j >> 1, jp = j & 1;   // pivot row j = 2 k0 + jp
+    double* v = vb + (j & 1) * 64;
+    if (hi == j) {
+#pragma unroll
+      for (int k = k0; k < 32; ++k) v[2 * k + par] = x[k];
+    }
+    __syncthreads();
+    double hv[32], pn = 0.0;
+#pragma unroll
+    for (int k = k0; k < 32; ++k) {
+      hv[k] = v[2 * k + par];
+      if (k == k0 && jp == 1) hv[k] = par ? hv[k] : 0.0;   // row 2 k0 < j is not part of the vector
+      pn += hv[k] * hv[k];
+    }
+    const double nrm = sqrt(pn + __shfl_xor(pn, 1));
+    const double alpha = v[j];
+    double beta = 0.0, vj = alpha, diag = alpha;
+    if (nrm > 0.0) {
+      const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
+      vj = alpha + sg * nrm;
+      beta = 1.0 / (nrm * (nrm + fabs(alpha)));
+      diag = -sg * nrm;
+    }
+    // the pivot entry of the vector is v_j, not alpha
+    hv[k0] = (par == jp) ? vj : hv[k0];
+    double pw = 0.0;
+#pragma unroll
+    for (int k = k0; k < 32; ++k) pw += hv[k] * x[k];
+    const double w = (pw + __shfl_xor(pw, 1)) * beta;
+    if (hi > j) {
+#pragma unroll
+      for (int k = k0; k < 32; ++k) x[k] -= w * hv[k];
+    } else if (hi == j) {
+      rd = diag;
+      if (par == jp) x[k0] = vj;
+    }
+    if (ln == 0) Hb[j] = beta;
+  }
+  __syncthreads();
+}
+
 // The reflection vectors left in x by qr64 (rows >= j of column j, zero above) and their coefficients into a
 // pass-1 factor slot: Vg[j * 64 + row], Vg[2048 + j].
 __device__ __forceinline__ void store_v(const double (&x)[32], int jmax, const double* Hb, double* Vg) {
