@@ -160,8 +160,11 @@ __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict
     for (int k = 0; k < C0; ++k) v[k] = 0.0f;
     const int bx = (coset == 1 || coset == 2) ? 1 : 0, bz = (coset == 2 || coset == 3) ? 1 : 0;
     if (((r + c) & 1) == 0) {
-      int x, z;
-      fs(r, c, x, z);
+      int x = 0, z = 0;
+      if ((r & 1) == 0) {   // horizontal-edge qubit: f_s from the table above (vertical ones carry none)
+        x = Q[r][c] & 1;
+        z = Q[r][c] >> 1;
+      }
       const int lx = (r == 0) ? 1 : 0, lz = (c == 0) ? 1 : 0;   // logical X on row 0, Z on column 0
       v[0] = (float)(x ^ (bx & lx));
       v[1] = (float)(z ^ (bz & lz));
@@ -180,7 +183,19 @@ __global__ __launch_bounds__(256) void features_kernel(const uint8_t* __restrict
     v[8] = (float)bx;
     v[9] = (float)bz;
     T* o = X + ((b * 4 + coset) * (int64_t)L * L + site) * CS;
-    for (int k = 0; k < CS; ++k) store_el(o + k, k < C0 ? v[k] : 0.0f);
+    if constexpr (sizeof(T) == 2 && CS == 16) {
+      // the site's 16 BF16 channels as two 16-byte stores
+      unsigned w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float lo = 2 * k < C0 ? v[2 * k] : 0.0f, hi = 2 * k + 1 < C0 ? v[2 * k + 1] : 0.0f;
+        w[k] = (unsigned)f2bf(lo) | ((unsigned)f2bf(hi) << 16);
+      }
+      ((uint4*)o)[0] = uint4{w[0], w[1], w[2], w[3]};
+      ((uint4*)o)[1] = uint4{w[4], w[5], w[6], w[7]};
+    } else {
+      for (int k = 0; k < CS; ++k) store_el(o + k, k < C0 ? v[k] : 0.0f);
+    }
   }
 }
 
