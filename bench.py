@@ -435,8 +435,10 @@ def d17_leg(a, d, p, block, chi, max_iter, syn_dev, precision):
 def mixed_main(a):
     """Mixed-distance workload: 8192 syndromes, per syndrome d uniform over {9, 13, 17, 21} and p uniform
     over [0.05, 0.15], chi 16 for d <= 13 and 32 above, 6x6 blocks, <= 20 iterations with early exit. The
-    timed steps replay one HIP graph that holds the whole decode of all four distances; an eager pass
-    with per-launch HIP events then gives the kernel rates."""
+    timed steps replay one HIP graph that holds the whole decode of all four distances, in --precision (1,
+    the BF16 matrix-core contractions, by default) and, for precision 1, once more in plain FP32 (the batched
+    BF16 decode against plain FP32 on the same GPU); an eager pass with per-launch HIP events then gives the
+    kernel rates."""
     import numpy as np
     import torch
 
@@ -452,43 +454,60 @@ def mixed_main(a):
         sel = [(p, s) for dd, p, _, s in items if dd == d]
         groups.append((d, torch.tensor([p for p, _ in sel], dtype=torch.float64, device=dev),
                        torch.from_numpy(np.stack([s for _, s in sel])).to(dev), chi_of[d]))
-    opts = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1, graph=1)
     # launch variant: tuned on the group with the most work (d=21), which the decode of the mix then uses
     big = groups[-1]
-    tune_opts = bbp.default_opts(block=6, chi=big[3], max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
+    tune_opts = bbp.default_opts(block=6, chi=big[3], max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1,
+                                 precision=a.precision)
     tune = bbp.autotune(big[0], 0.10, big[2], tune_opts)
-    st = torch.cuda.Stream(dev)
-    with torch.cuda.stream(st):
-        outs, ws, _ = bbp.decode_groups(groups, opts, stream=st)          # capture
-        for _ in range(a.warmup):
-            outs, ws, _ = bbp.decode_groups(groups, opts, stream=st, workspace=ws, outs=outs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(st):
-        for _ in range(a.steps):
-            outs, ws, _ = bbp.decode_groups(groups, opts, stream=st, workspace=ws, outs=outs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    def timed(precision):
+        opts = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1, graph=1,
+                                precision=precision)
+        st = torch.cuda.Stream(dev)
+        with torch.cuda.stream(st):
+            outs, ws, _ = bbp.decode_groups(groups, opts, stream=st)          # capture
+            for _ in range(a.warmup):
+                outs, ws, _ = bbp.decode_groups(groups, opts, stream=st, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(st):
+            for _ in range(a.steps):
+                outs, ws, _ = bbp.decode_groups(groups, opts, stream=st, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        return outs, ws, time.perf_counter() - t0
+
+    outs, ws, elapsed = timed(a.precision)
     value = count * a.steps / elapsed
-    eager = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1)
+    fp32 = None
+    if a.precision == 1 and not a.no_fp32_comparison:
+        # the same mix, graph and launch set-up in plain FP32: the batched BF16 decode against plain FP32
+        o32, _, e32 = timed(0)
+        same = [float((o["coset"] == q["coset"]).double().mean()) for o, q in zip(outs, o32)]
+        fp32 = dict(value=count * a.steps / e32, ms_per_step=1e3 * e32 / a.steps,
+                    decisions_equal_to_bf16={g[0]: f for g, f in zip(groups, same)},
+                    speedup_of_bf16=e32 / elapsed)
+    eager = bbp.default_opts(block=6, chi=32, max_iter=20, delta0=1e-4, delta1=1e-2, damping=0.1,
+                             precision=a.precision)
     bbp.set_tuning(big[0], tune_opts, tune.order, 1)   # kernel rates: every launch timed alone
     _, _, tm = bbp.decode_groups(groups, eager, workspace=ws, timing=True)
     achieved = tm.top_flops / (tm.top_ms * 1e-3) / 1e12 if tm.top_ms > 0 else 0.0
     line = dict(
         metric="syndromes decoded/s, mixed d in {9, 13, 17, 21} (1 GPU)", value=value, unit="syndromes/s",
         n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=1e3 * elapsed / a.steps, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        scaling="weak", vs_baseline=None, dtype=("f32", "bf16/f32")[a.precision], data="synthetic",
         config=dict(workload="8192 syndromes, d uniform in {9, 13, 17, 21}, p uniform in [0.05, 0.15], chi 16 "
                              "(d <= 13) / 32, 6x6 blocks, <= 20 BP iterations, early exit, one HIP graph per step",
                     batch=count, per_distance={g[0]: int(g[2].shape[0]) for g in groups}, parallelism="single GPU"),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=_lib.sweep_kernel_name(tm.top_class),
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=_lib.sweep_kernel_name(tm.top_class, a.precision),
                       avg_launch_ms=tm.top_ms / max(tm.top_launches, 1),
                       measured_on="one eager decode on one stream"),
         mean_iterations_per_coset={g[0]: float(o["iters"].double().mean()) for g, o in zip(groups, outs)},
         launch_tuning=dict(order=("sweep-major", "job-major")[tune.order], streams=tune.streams,
                            tuned_on=f"d={big[0]}, {int(big[2].shape[0])} syndromes"),
     )
+    if fp32 is not None:
+        line["fp32_comparison"] = fp32
     print(json.dumps(line), flush=True)
 
 

@@ -51,12 +51,14 @@ def _mix_inputs():
     return [(d, p, workload.make_batch(d, p, b, workload="mixed", p_index=d)[1]) for d, p, b in MIX]
 
 
-def test_mixed_groups_equal_separate_decodes(dev):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_groups_equal_separate_decodes(dev, precision):
+    # FP32, and precision mode 1 (BF16 matrix-core contractions): batching never changes a result
     import torch
     import paper_2402_04834_amd as bbp
-    opts = bbp.default_opts(block=6, chi=32, max_iter=12)
+    opts = bbp.default_opts(block=6, chi=32, max_iter=12, precision=precision)
     inputs = _mix_inputs()
-    _say("[mixed] groups", [(d, p, s.shape[0]) for d, p, s in inputs])
+    _say("[mixed] groups", [(d, p, s.shape[0]) for d, p, s in inputs], "precision", precision)
     outs, _, _ = bbp.decode_groups([(d, p, torch.from_numpy(s).to(dev)) for d, p, s in inputs], opts)
     torch.cuda.synchronize()
     for (d, p, s), o in zip(inputs, outs):
