@@ -117,7 +117,9 @@ int bbp_plan_query(int32_t d, const bbp_opts* opts, bbp_plan_info* info);
 
 /* ---------------------------------------------------------------------------------------------------
  * Device workspace needed by bbp_decode_device for `batch` syndromes of distance d (bytes, 256-byte
- * aligned sub-buffers). Errors: BBP_EINVAL.
+ * aligned sub-buffers). A plan with truncating sweeps adds one 273 KB FP64 slot per truncating sweep of a
+ * colour round and coset job, at most 32768 slots (8.9 GB; larger rounds run in chunks of that many).
+ * Errors: BBP_EINVAL.
  */
 int bbp_workspace_size(int32_t d, int64_t batch, const bbp_opts* opts, size_t* bytes);
 
