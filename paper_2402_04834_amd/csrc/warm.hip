@@ -546,10 +546,11 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
 // chunk of up to 32 channels (HALO_ROWS rows, each padded by 16 bytes so that 16 consecutive rows fall on
 // distinct banks) instead of being gathered nine times. With CIN >= 32, K runs chunk by chunk and, inside a
 // chunk, tap by tap (one 32-deep step each); with CIN = 16 a step holds two taps (lanes 0-31 the first, 32-63
-// the second; the tenth tap is the weights' zero padding). A tap's A fragments are the halo rows shifted by
-// dr L + dc, and a row whose tap leaves the grid reads a zero row instead. Weight stages, register sets and the
-// BF16 epilogue are those of the gather kernel. Needs 128 + 2 L + 2 <= HALO_ROWS (L <= 49, d <= 25); larger
-// grids take the gather kernel.
+// the second; the tenth tap is the weights' zero padding). A tap's activation fragments are the halo rows
+// shifted by dr L + dc, and a row whose tap leaves the grid reads a zero row instead. The weight stages and
+// their register sets are those of the gather kernel; here the weights are the MFMA's first operand, so each
+// lane ends with four consecutive output channels of one site. Needs 128 + 2 L + 2 <= HALO_ROWS (L <= 49,
+// d <= 25); larger grids take the gather kernel.
 constexpr int HALO_MT = 128, HALO_ROWS = 228;   // rows per tile, halo rows
 
 template <int CIN, int NT, int RELU, bool OUT_BF>
