@@ -165,14 +165,30 @@ __device__ __forceinline__ void apply_q(double (&X)[16], int jmax, const double*
     const int row = qt * 16 + r;
     X[r] = (row < 32) ? Csh[row * 16 + kc] : 0.0;
   }
+  // the next reflection's vector quarter and coefficient are loaded while this one is applied (the loads
+  // come from the workspace, through L2: one reflection's latency each, otherwise)
+  double vn[16], bn = 0.0;
+  if (jmax > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) vn[r] = Vg[(jmax - 1) * 64 + qt * 16 + r];
+    bn = Vg[2048 + jmax - 1];
+  }
   for (int j = jmax - 1; j >= 0; --j) {
-    const double* v = Vg + j * 64 + qt * 16;
+    double v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = vn[r];
+    const double beta = bn;
+    if (j > 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) vn[r] = Vg[(j - 1) * 64 + qt * 16 + r];
+      bn = Vg[2048 + j - 1];
+    }
     double p = 0.0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) p += v[r] * X[r];
     p += __shfl_xor(p, 16);
     p += __shfl_xor(p, 32);
-    const double w = p * Vg[2048 + j];
+    const double w = p * beta;
 #pragma unroll
     for (int r = 0; r < 16; ++r) X[r] -= w * v[r];
   }
