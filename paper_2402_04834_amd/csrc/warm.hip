@@ -553,7 +553,7 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(3))) v
 // d <= 25); larger grids take the gather kernel.
 constexpr int HALO_MT = 128, HALO_ROWS = 228;   // rows per tile, halo rows
 
-template <int CIN, int NT, int RELU, bool OUT_BF>
+template <int CIN, int NT, int RELU, bool OUT_BF, int PN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void conv_halo_bf16(int L, int64_t rows, const unsigned short* __restrict__ X,
                                                        const unsigned short* __restrict__ Wt,
                                                        const float* __restrict__ bias, void* __restrict__ Y) {
@@ -742,11 +742,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
         *(uint4*)((unsigned short*)Y + (m0 + row) * NT + 8 * c8) = *(const uint4*)&lds[row * TS + 8 * c8];
     }
   } else {
-    // FP32: four consecutive channels are one 16-byte store
+    // FP32: four consecutive channels are one 16-byte store. PN > 0: the channels are the head's per-site
+    // projections, PN per direction (4 PN <= NT, PN a multiple of 4); they are stored direction by direction,
+    // [4][rows][PN], so that a message reads the PN values of a site from one short run, and the padding
+    // channels beyond 4 PN are not stored.
+    static_assert(PN == 0 || (PN % 4 == 0 && 4 * PN <= NT), "projection layout");
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int ch = wn + 16 * j + 4 * fc;
+      if (PN > 0 && ch >= 4 * PN) continue;
       const float b0 = bias[ch], b1 = bias[ch + 1], b2 = bias[ch + 2], b3 = bias[ch + 3];
+      const int dir = PN > 0 ? ch / (PN > 0 ? PN : 1) : 0, cd = ch - dir * PN;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t row = m0 + wm + 16 * i + fr;
@@ -757,7 +763,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
           v.z = fmaxf(v.z, 0.0f);
           v.w = fmaxf(v.w, 0.0f);
         }
-        if (full || row < rows) *(float4*)((float*)Y + row * NT + ch) = v;
+        float* dst = PN > 0 ? (float*)Y + (dir * rows + row) * PN + cd : (float*)Y + row * NT + ch;
+        if (full || row < rows) *(float4*)dst = v;
       }
     }
   }
@@ -927,9 +934,10 @@ __global__ void compose_head_kernel(const float* __restrict__ prm, int kpad, uns
 
 // one wavefront per (job, message): lanes 0 .. 2K+4(K-1)-1 form the head outputs from the projections of the
 // legs' sites, every lane then scores its configuration b as head_kernel does
-__global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__ Pj, const int32_t* __restrict__ legs,
-                                                       int M, int L, int64_t jobs, const float* __restrict__ prm,
-                                                       float* __restrict__ msgs) {
+// Pj: projection j < NPROJ of direction dir at grid row g (= job L^2 + site) at Pj[dir dstride + g sstride + j]
+__global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__ Pj, int64_t dstride, int sstride,
+                                                       const int32_t* __restrict__ legs, int M, int L, int64_t jobs,
+                                                       const float* __restrict__ prm, float* __restrict__ msgs) {
   const int64_t job = blockIdx.x / M;
   const int e = (int)(blockIdx.x - job * M), lane = threadIdx.x;
   if (job >= jobs) return;
@@ -937,8 +945,8 @@ __global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__
   const int K = lg[0], dir = lg[1];
   const float* H = prm + OFF.head + (size_t)dir * HEAD;
   const float *bu = H + 2 * C3 * 2, *bp = bu + 2 + 4 * C3 * 4;
-  const float* P = Pj + job * (int64_t)L * L * PROJ_CH + dir * NPROJ;
-  auto proj = [&](int site, int j) { return P[(int64_t)site * PROJ_CH + j]; };
+  const float* P = Pj + dir * dstride + job * (int64_t)L * L * sstride;
+  auto proj = [&](int site, int j) { return P[(int64_t)site * sstride + j]; };
   // output o = lane: unary 2 i + c, pairwise 2 MAXK + 4 i + q (as head_kernel)
   float outv = 0.0f;
   if (lane < 2 * MAXK) {
@@ -1220,15 +1228,20 @@ struct Args {
 };
 
 // forward trunk of `jobs` coset jobs starting at syndrome syn / noise rates pdev: features F [rows][C3]
-template <int CIN, int NT, int WM, int RELU, bool OUT_BF>
+// the haloed-tile kernel serves grids whose halo fits its LDS rows
+bool halo_fits(int L) { return HALO_MT + 2 * L + 2 <= HALO_ROWS; }
+
+// PN > 0 (the composed last layer): with the haloed-tile kernel the projections are stored direction-major,
+// [4][rows][PN]; the gather kernel of larger grids stores them [rows][NT]
+template <int CIN, int NT, int WM, int RELU, bool OUT_BF, int PN = 0>
 int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short* Wt, const float* bias, void* Y,
               hipStream_t st) {
   // the kernel addresses the activations through one buffer descriptor with 32-bit byte offsets, the
   // out-of-grid sentinel (the buffer's size) plus a channel offset included
   if (rows * CIN > (int64_t)INT32_MAX - 512) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
   {
-    if (HALO_MT + 2 * L + 2 <= HALO_ROWS) {
-      conv_halo_bf16<CIN, NT, RELU, OUT_BF><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
+    if (halo_fits(L)) {
+      conv_halo_bf16<CIN, NT, RELU, OUT_BF, PN><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
           L, rows, X, Wt, bias, Y);
       W_TRY(hipGetLastError());
       return BBP_OK;
@@ -1265,8 +1278,8 @@ int trunk_bf16(int d, const uint8_t* syn, const double* pdev, double p, int64_t 
   int rc;
   if ((rc = conv_bf16<CS0, C1, CONV_WM, 1, true>(L, rows, X0, Wb, prm + OFF.b1, A1, st))) return rc;
   if ((rc = conv_bf16<C1, C2, CONV_WM, 1, true>(L, rows, A1, Wb + WB1, prm + OFF.b2, A2, st))) return rc;
-  if ((rc = conv_bf16<C2, PROJ_CH, CONV_WM, 0, false>(L, rows, A2, Wb + WB1 + WB2, (const float*)(Wb + WB_TOTAL), F,
-                                                       st)))
+  if ((rc = conv_bf16<C2, PROJ_CH, CONV_WM, 0, false, NPROJ>(L, rows, A2, Wb + WB1 + WB2,
+                                                              (const float*)(Wb + WB_TOTAL), F, st)))
     return rc;
   return BBP_OK;
 }
@@ -1342,13 +1355,17 @@ int bbp_warm_predict(int32_t d, double p, const double* p_dev, const uint8_t* sy
                           : trunk(d, sb, pb, p, jobs, params_dev, (char*)workspace, w, a.st);
     if (rc) return rc;
     if (lg.M > 0) {
-      if (precision == 1)
+      if (precision == 1) {
+        const bool dm = halo_fits(L);   // the layout conv_bf16 stored the projections in
+        const int64_t rows = jobs * (int64_t)L * L;
         head_proj_kernel<<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
-            (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, messages_dev + b0 * 4 * lg.M * 64);
-      else
+            (const float*)((char*)workspace + w.F), dm ? rows * NPROJ : (int64_t)NPROJ, dm ? NPROJ : PROJ_CH, lg.dev,
+            lg.M, L, jobs, params_dev, messages_dev + b0 * 4 * lg.M * 64);
+      } else {
         head_kernel<false><<<dim3((unsigned)(jobs * lg.M)), dim3(64), 0, a.st>>>(
             (const float*)((char*)workspace + w.F), lg.dev, lg.M, L, jobs, params_dev, nullptr, nullptr, 0.0f,
             messages_dev + b0 * 4 * lg.M * 64, nullptr, nullptr, nullptr);
+      }
       W_TRY(hipGetLastError());
     }
   }
