@@ -144,8 +144,8 @@ def test_stabilizer_multiplication_leaves_coset_unchanged():
     np.testing.assert_allclose(network.exact_log_contraction(d, x2, z2, pi), base, rtol=1e-12)
 
 
-# Coset probabilities at d = 3, eps = 0.1 (order I, X, Y, Z) for four syndromes, from an independent
-# enumeration of all 4^13 errors made when the method was surveyed (key = sum_i s_i 2^i, Z-checks first).
+# Coset probabilities at d = 3, eps = 0.1 (order I, X, Y, Z) for four syndromes, from an enumeration of all
+# 4^13 errors written independently of oracle/ (key = sum_i s_i 2^i, Z-checks first).
 # They fix the conventions of the syndrome order, the chains of f_s and the logical representatives
 # together: a transposed check order or a logical on the wrong boundary moves these values between columns.
 T1_D3_EPS010 = {
