@@ -9,6 +9,13 @@ An existing file with the same parameters is extended (records already present a
 be resumed. The committed d=17 file holds all 4096 syndromes of the benchmark batch (about 21 hours of oracle
 time summed over the worker processes); the d=11 files hold all 1024 syndromes of each p.
 
+Truncating block sweeps on the benchmark's d=17 batch (its first syndromes; chi binds inside the blocks):
+
+    python tests/golden/make_oracle_fixtures.py --workload d17 --d 17 --p 0.10 --block 6 --chi 8 --count 64 \
+        --chunk 2 --procs 7 --out tests/golden/d17_p010_k6_chi8_first64.json
+    python tests/golden/make_oracle_fixtures.py --workload d17 --d 17 --p 0.10 --block 8 --chi 16 --count 32 \
+        --chunk 1 --procs 7 --out tests/golden/d17_p010_k8_chi16_first32.json
+
 Mixed-distance workload (8192 syndromes, each with its own d in {9, 13, 17, 21} and p in [0.05, 0.15]; chi 16
 for d <= 13 and 32 above, 6x6 blocks): the first --per-d syndromes of every distance, each decoded at its own p:
 

@@ -181,3 +181,38 @@ def test_truncating_launch_in_several_chunks(dev):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(one["messages"].cpu().numpy()[0], bm[i], err_msg=f"syndrome {i}")
         np.testing.assert_array_equal(one["loglik"].cpu().numpy()[0], bl[i], err_msg=f"syndrome {i}")
+
+
+@pytest.mark.parametrize("fixture,k,chi,batch", [("d17_p010_k6_chi8_first64.json", 6, 8, 256),
+                                                 ("d17_p010_k8_chi16_first32.json", 8, 16, 256)])
+def test_full_size_d17_truncating_against_oracle_fixture(dev, fixture, k, chi, batch):
+    # the truncating workload of the benchmark (the first 256 syndromes of the d=17, p=0.10 batch, <= 20
+    # iterations with early exit) in one decode, checked on the syndromes of a committed oracle fixture
+    # (tests/golden, written by make_oracle_fixtures.py from oracle/ only): iteration counts equal away from
+    # delta0, ln Z of the cosets with equal counts within the early-exit tolerance, decisions equal beyond
+    # a 1e-3-nat margin (measured at 6x6, chi 8: all 256 iteration counts equal, |dlnZ| <= 2.6e-6)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fixture)
+    g = json.load(open(path))
+    meta = g["meta"]
+    assert (meta["d"], meta["block"], meta["chi"], meta["max_iter"]) == (17, k, chi, 20)
+    _say(f"[trunc full size] d=17 {k}x{k} chi {chi} batch={batch}, {len(g['records'])} oracle records")
+    _, syn = workload.make_batch(17, meta["p"], batch, workload=meta["workload"], p_index=meta["p_index"])
+    got = _decode(dev, 17, meta["p"], syn, messages=False, block=k, chi=chi, max_iter=20, damping=meta["eta"],
+                  delta0=meta["delta0"], delta1=meta["delta1"])
+    idx = np.array([r["index"] for r in g["records"]])
+    ref_ll = np.array([r["loglik"] for r in g["records"]])
+    ref_dl = np.array([r["delta"] for r in g["records"]])
+    ref_it = np.array([r["iters"] for r in g["records"]])
+    ref_cs = np.array([r["coset"] for r in g["records"]])
+    it, ll = got["iters"][idx], got["loglik"][idx]
+    same = it == ref_it
+    near = np.abs(np.log(np.maximum(ref_dl, 1e-30) / meta["delta0"])) < 0.1
+    assert np.all(same | near), (it[~(same | near)], ref_it[~(same | near)])
+    ok = same & np.isfinite(ref_ll)
+    err = np.abs(ll[ok] - ref_ll[ok])
+    _say(f"   same iteration counts {same.mean():.3f}; |dlnZ| max {err.max():.2e} median {np.median(err):.2e}")
+    np.testing.assert_array_less(err, 2e-5 + 2e-7 * np.abs(ref_ll[ok]))
+    _decisions_agree(got["coset"][idx], ref_ll, ref_cs, ref_dl, meta["delta1"], margin=1e-3)
+    assert np.all(got["coset"] < 4)
