@@ -647,6 +647,32 @@ def bmps_main(a):
     print(json.dumps(line), flush=True)
 
 
+def _trunc_oracle_agreement(block, chi, out, count):
+    """Decisions, iteration counts and ln Z of a truncating decode of the d=17 batch against the committed
+    oracle fixture of its first syndromes (tests/golden/d17_p010_k{block}_chi{chi}_first*.json), or None."""
+    import glob
+
+    import numpy as np
+    paths = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"d17_p010_k{block}_chi{chi}_first*.json")))
+    if not paths:
+        return None
+    g = json.load(open(paths[0]))
+    rec = [r for r in g["records"] if r["index"] < count]
+    if not rec:
+        return None
+    idx = np.array([r["index"] for r in rec])
+    ref_ll = np.array([r["loglik"] for r in rec])
+    ref_it = np.array([r["iters"] for r in rec])
+    ref_cs = np.array([r["coset"] for r in rec])
+    it, ll, cs = (out[k].cpu().numpy()[idx] for k in ("iters", "loglik", "coset"))
+    same = (it == ref_it) & np.isfinite(ref_ll)
+    err = np.abs(ll[same] - ref_ll[same])
+    return dict(syndromes=len(rec), decisions_equal=int((cs == ref_cs).sum()),
+                cosets_same_iterations=int((it == ref_it).sum()), cosets=int(it.size),
+                max_abs_dlnz_same_iterations=float(err.max()) if err.size else None,
+                oracle=os.path.relpath(paths[0], ROOT))
+
+
 def trunc_main(a):
     """Block sweeps with a binding chi (Sec. III.D): the first --trunc-batch syndromes of the d=17, p=0.10
     workload decoded with (i) 6x6 blocks at chi 8 -- the sweeps whose boundary rank (16) exceeds chi run the
@@ -703,7 +729,8 @@ def trunc_main(a):
                         frac=ach / PEAK_FP64_TFLOPS, avg_launch_ms=tms / max(tl, 1), launches=tl,
                         flops_per_launch=tfl / max(tl, 1)),
             decisions_equal_to_exact_chi32=float((c == cref).mean()),
-            logical_failures=[int(f.sum()), count, list(wilson(int(f.sum()), count))]))
+            logical_failures=[int(f.sum()), count, list(wilson(int(f.sum()), count))],
+            oracle_agreement=_trunc_oracle_agreement(block, chi, out, count)))
         del ws
     line = dict(
         metric=f"syndromes decoded/s at d={d} with truncating block sweeps (1 GPU)",
