@@ -247,8 +247,8 @@ def main():
                          "at d=17, p=0.05 and 0.10, against the bMPS reference; trunc: block sweeps with a "
                          "binding chi (6x6 blocks at chi 8, 8x8 blocks at chi 16) on the first --trunc-batch "
                          "d17 syndromes")
-    ap.add_argument("--trunc-batch", type=int, default=1024,
-                    help="syndromes of the trunc workload (default 1024, the first of the d17 batch)")
+    ap.add_argument("--trunc-batch", type=int, default=256,
+                    help="syndromes of the trunc workload (default 256, the first of the d17 batch)")
     ap.add_argument("--block", type=int, default=6, choices=range(1, 7),
                     help="block size k of the d17 workload (default 6; 1 = plain BP between single tensors)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -698,6 +698,9 @@ def trunc_main(a):
     fref = logical_failures(d, errors, ref["correction"].cpu().numpy())
     legs = []
     for block, chi in [(6, 8), (8, 16)]:
+        # progress on stderr: each configuration takes tens of seconds
+        print(f"[trunc] {block}x{block} blocks, chi {chi}: {count} syndromes, 1 + {a.warmup} + {a.steps} decodes",
+              file=sys.stderr, flush=True)
         opts = bbp.default_opts(block=block, chi=chi, **base)
         info = bbp.plan_query(d, opts)
         ws = torch.empty(bbp.workspace_size(d, count, opts), dtype=torch.uint8, device=dev)
