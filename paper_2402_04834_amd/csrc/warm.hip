@@ -752,7 +752,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       const int ch = wn + 16 * j + 4 * fc;
       if (PN > 0 && ch >= 4 * PN) continue;
       const float b0 = bias[ch], b1 = bias[ch + 1], b2 = bias[ch + 2], b3 = bias[ch + 3];
-      const int dir = PN > 0 ? ch / (PN > 0 ? PN : 1) : 0, cd = ch - dir * PN;
+      constexpr int PD = PN > 0 ? PN : 1;   // projections per direction (PN = 0: the plain layout, unused)
+      const int dir = ch / PD, cd = ch - dir * PD;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t row = m0 + wm + 16 * i + fr;
