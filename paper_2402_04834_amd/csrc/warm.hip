@@ -561,14 +561,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   constexpr int CH = CIN < KS ? CIN : KS, NC = CIN / CH;     // channels per chunk, chunks
   constexpr int NS = CIN < KS ? KP / KS : 9 * NC;            // steps
   constexpr int RE = CH + 8, RP = CH / 8;                    // elements and 16-byte pieces per halo row
-  constexpr int TH = 256, MT = HALO_MT, WN = NT / 2, NJ = WN / 16;
+  // waves: 2 x 2 (64 rows x NT / 2 each, NT a multiple of 32), or 4 x 1 (32 rows x NT each) when NT is an
+  // odd multiple of 16
+  constexpr int WNW = NT % 32 == 0 ? 2 : 1, MI = WNW == 2 ? 4 : 2;
+  constexpr int TH = 256, MT = HALO_MT, WN = NT / WNW, NJ = WN / 16;
   constexpr int UB = (NT * 4 + TH - 1) / TH;                 // 16-byte weight chunks per thread and step
   constexpr int UH = (HALO_ROWS * RP + TH - 1) / TH;         // 16-byte halo pieces per thread and chunk
   constexpr int NH = NC > 1 ? 2 : 1, HALO = HALO_ROWS * RE;  // halo buffers, elements of one
   constexpr int BST = NT * KS;                               // elements of one weight stage
   constexpr int TILE = OUT_BF ? MT * (NT + 16) : 0;          // BF16 output tile (padded rows)
   constexpr int MAIN = NH * HALO + 2 * BST + 32;             // halo buffers, two weight stages, a zero row
-  static_assert((CIN == 16 || CIN % 32 == 0) && NT % 32 == 0 && NT <= 128, "tile shape");
+  static_assert((CIN == 16 || CIN % 32 == 0) && NT % 16 == 0 && NT <= 128 && MI * 16 * (4 / WNW) == MT,
+                "tile shape");
   __shared__ __align__(16) unsigned short lds[MAIN > TILE ? MAIN : TILE];
   unsigned short* const Bsm = lds + NH * HALO;
   unsigned short* const zrow = Bsm + 2 * BST;
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   const unsigned nb = gridDim.x, per = nb / 8, bid = blockIdx.x;
   const unsigned tile = bid < 8 * per ? (bid % 8) * per + bid / 8 : bid;
   const int64_t m0 = (int64_t)tile * MT;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * WN;
+  const int wm = WNW == 2 ? (w >> 1) * 64 : w * 32, wn = WNW == 2 ? (w & 1) * WN : 0;
   const int fr = lane & 15, fc = lane >> 4;
   const unsigned xbytes = (unsigned)(rows * CIN * 2);   // the host keeps this + 512 below 2^32
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)xbytes, 0x00020000);
@@ -613,10 +617,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
     }
     return q;
   };
-  int abase[4];
-  unsigned edge[4];
+  int abase[MI];
+  unsigned edge[MI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < MI; ++i) {
     const int r = wm + 16 * i + fr;
     abase[i] = (r + L + 1) * RE + 8 * (CIN < KS ? (fc & 1) : fc);
     int site, col;
@@ -652,9 +656,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       if ((NT * 4) % TH == 0 || q < NT * 4) *(u32x4*)&Bsm[buf * BST + swz(q >> 2, q & 3)] = rb[u];
     }
   };
-  f4 acc[4][NJ];
+  f4 acc[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   u32x4 rh[UH], rb0[UB], rb1[UB];
@@ -681,22 +685,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
     // the fragment addresses are formed anew each step: kept from the step two chunks back (same buffer, same
     // tap) they would hold 72 registers for the whole kernel
 #pragma unroll
-    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(abase[i]), "+v"(edge[i]));
+    for (int i = 0; i < MI; ++i) asm volatile("" : "+v"(abase[i]), "+v"(edge[i]));
     // this lane's tap: t, or with CIN = 16 t + 1 for lanes 32-63
     const bool second = CIN < KS && fc >= 2;
     const int sh = second ? shift(t + 1) : shift(t);
     const unsigned og = second ? off_grid(t + 1) : off_grid(t);
     const unsigned short* Bs = Bsm + (s & 1) * BST;
-    bf8 a[4], b[NJ];
+    bf8 a[MI], b[NJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < MI; ++i) {
       const unsigned short* pa = (edge[i] & og) ? zrow + 8 * fc : Hs + abase[i] + sh;
       a[i] = *(const bf8*)pa;
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) b[j] = *(const bf8*)&Bs[swz(wn + 16 * j + fr, fc)];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
     if (t == 2 && c + 1 < NC) storeH((c + 1) & 1, rh);
@@ -720,7 +724,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       const int ch = wn + 16 * j + 4 * fc;
       const float b0 = bias[ch], b1 = bias[ch + 1], b2 = bias[ch + 2], b3 = bias[ch + 3];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < MI; ++i) {
         float v0 = acc[i][j][0] + b0, v1 = acc[i][j][1] + b1, v2 = acc[i][j][2] + b2, v3 = acc[i][j][3] + b3;
         if (RELU) {
           v0 = fmaxf(v0, 0.0f);
@@ -755,7 +759,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       constexpr int PD = PN > 0 ? PN : 1;   // projections per direction (PN = 0: the plain layout, unused)
       const int dir = ch / PD, cd = ch - dir * PD;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < MI; ++i) {
         const int64_t row = m0 + wm + 16 * i + fr;
         float4 v{acc[i][j][0] + b0, acc[i][j][1] + b1, acc[i][j][2] + b2, acc[i][j][3] + b3};
         if (RELU) {
@@ -1242,7 +1246,10 @@ int conv_bf16(int L, int64_t rows, const unsigned short* X, const unsigned short
   if (rows * CIN > (int64_t)INT32_MAX - 512) return wfail(BBP_EINVAL, "too many sites for one BF16 convolution");
   {
     if (halo_fits(L)) {
-      conv_halo_bf16<CIN, NT, RELU, OUT_BF, PN><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
+      // the haloed-tile kernel computes only the 4 PN projection channels of the composed layer (the weight
+      // rows beyond them are the padding of the gather kernel's tile)
+      constexpr int NTH = PN > 0 ? 4 * PN : NT;
+      conv_halo_bf16<CIN, NTH, RELU, OUT_BF, PN><<<dim3((unsigned)((rows + HALO_MT - 1) / HALO_MT)), dim3(256), 0, st>>>(
           L, rows, X, Wt, bias, Y);
       W_TRY(hipGetLastError());
       return BBP_OK;
