@@ -246,7 +246,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         x[0] = Ash[d];
       }
     }
-    qr64(x, rd, 16, vb, Hb);
+    qr64u<16, 8>(x, rd, vb, Hb);   // rows q' < 16: registers k < 8
     logs += store_r(x, rd, Rsh);
     store_v(x, 16, Hb, Q);
     // crossing sites

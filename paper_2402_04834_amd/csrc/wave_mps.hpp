@@ -90,11 +90,13 @@ __device__ __forceinline__ void qr64(double (&x)[32], double& rd, int jmax, doub
 
 // qr64 with the reflections unrolled (JMAX = jmax): reflection j touches rows >= j only, i.e. registers
 // k >= j / 2, and its pivot row is a compile-time register, so the vector's rows above the pivot are neither
-// stored, read nor multiplied, and the pivot takes one select instead of one per register. (Used for the
-// 32-reflection factorisations; an unrolled 16-reflection instance beside it in the truncating kernel took
-// the compiler beyond 40 minutes.)
-template <int JMAX>
+// stored, read nor multiplied, and the pivot takes one select instead of one per register. KR: only rows
+// below 2 KR can be nonzero (x[k] = 0 for k >= KR, left untouched), as in a cap's 16-row matrix; the
+// rolled form with 64 rows kept x in scratch memory there. (An unrolled instance with 16 reflections over
+// all 32 registers beside the 32-reflection one took the compiler beyond 40 minutes.)
+template <int JMAX, int KR = 32>
 __device__ __forceinline__ void qr64u(double (&x)[32], double& rd, double* vb, double* Hb) {
+  static_assert(KR <= 32 && JMAX <= 2 * KR, "reflections within the nonzero rows");
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   rd = 0.0;
 #pragma unroll
@@ -103,12 +105,12 @@ __device__ __forceinline__ void qr64u(double (&x)[32], double& rd, double* vb, d
     double* v = vb + (j & 1) * 64;
     if (hi == j) {
 #pragma unroll
-      for (int k = k0; k < 32; ++k) v[2 * k + par] = x[k];
+      for (int k = k0; k < KR; ++k) v[2 * k + par] = x[k];
     }
     __syncthreads();
     double hv[32], pn = 0.0;
 #pragma unroll
-    for (int k = k0; k < 32; ++k) {
+    for (int k = k0; k < KR; ++k) {
       hv[k] = v[2 * k + par];
       if (k == k0 && jp == 1) hv[k] = par ? hv[k] : 0.0;   // row 2 k0 < j is not part of the vector
       pn += hv[k] * hv[k];
@@ -126,11 +128,11 @@ __device__ __forceinline__ void qr64u(double (&x)[32], double& rd, double* vb, d
     hv[k0] = (par == jp) ? vj : hv[k0];
     double pw = 0.0;
 #pragma unroll
-    for (int k = k0; k < 32; ++k) pw += hv[k] * x[k];
+    for (int k = k0; k < KR; ++k) pw += hv[k] * x[k];
     const double w = (pw + __shfl_xor(pw, 1)) * beta;
     if (hi > j) {
 #pragma unroll
-      for (int k = k0; k < 32; ++k) x[k] -= w * hv[k];
+      for (int k = k0; k < KR; ++k) x[k] -= w * hv[k];
     } else if (hi == j) {
       rd = diag;
       if (par == jp) x[k0] = vj;
