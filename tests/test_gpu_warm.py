@@ -125,6 +125,38 @@ def test_bf16_forward_against_oracle(dev, d, k):
     assert span > 1.0      # the comparison is not trivial
 
 
+def test_bf16_forward_several_chunks(dev):
+    """The inference forward runs in chunks of 512 syndromes (2048 coset jobs, one workspace slot set): a batch
+    of 600 at d=9 takes two, the second ragged. Its messages equal those of the same syndromes forwarded in
+    separate calls (512, then 88) bitwise -- a site's sums do not depend on where its tile starts -- and the
+    first and last syndromes of both chunks match the oracle as in test_bf16_forward_against_oracle."""
+    import torch
+    import paper_2402_04834_amd as bbp
+    from paper_2402_04834_amd import warm
+    d, k, b = 9, 6, 600
+    _, syn = workload.make_batch(d, 0.1, b, workload="warm", p_index=290)
+    ps = np.random.default_rng(290).uniform(0.05, 0.15, size=b)
+    th = _theta(29)
+    opts = bbp.default_opts(block=k, chi=32)
+    tp, ts, tt = torch.from_numpy(ps).to(dev), torch.from_numpy(syn).to(dev), torch.from_numpy(th).to(dev)
+    _say(f"[warm bf16 chunks] d={d} batch {b}")
+    whole = warm.predict(d, tp, ts, opts, tt, precision=1).cpu().numpy()
+    parts = [warm.predict(d, tp[a:z], ts[a:z], opts, tt, precision=1).cpu().numpy() for a, z in ((0, 512), (512, b))]
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(whole, np.concatenate(parts))
+    plan = blockbp.Plan(d, k, k)
+    for i in (0, 511, 512, b - 1):
+        for c in range(4):
+            ref = warmnet.predict_stored(th.astype(np.float64), warmnet.features(d, syn[i], ps[i], c), d, plan,
+                                         warmnet.round_bf16)
+            for e in range(plan.M):
+                K = len(warmnet.legs(d, plan, e))
+                r, q = ref[e, :2 ** K], whole[i, c, e, :2 ** K]
+                sel = r > 1e-4
+                diff = np.log(np.maximum(q[sel], 1e-30)) - np.log(r[sel])
+                assert diff.max() - diff.min() <= 0.02, (i, c, e, diff)
+
+
 @pytest.mark.parametrize("d,k", [(5, 3), (7, 4)])
 def test_loss_gradient_against_oracle(dev, d, k):
     import torch
