@@ -59,8 +59,9 @@ def _short_kernel_name(name):
     m = re.search(r"sweep_kernel<(true|false), (\d+(?:, (?:true|false)){4}), false>", name)
     if m:
         return f"sweep_kernel{'_bf16' if m.group(1) == 'true' else ''}<{m.group(2)}>"
-    if "trunc_sweep_kernel" in name:
-        return "trunc_sweep_kernel"
+    m = re.search(r"trunc_sweep_kernel<(true|false)>", name)
+    if m:
+        return f"trunc_sweep_kernel<{m.group(1)}>"
     return "bmps_kernel" if re.search(r"bmps_kernel\b", name) and "decide" not in name else name
 
 
@@ -710,11 +711,13 @@ def trunc_main(a):
         torch.cuda.synchronize()
         tms = tfl = 0.0
         tl = 0
+        kname = "trunc_sweep_kernel"
         t0 = time.perf_counter()
         for _ in range(a.steps):
             out = bbp.decode_device(d, p, s, opts, workspace=ws, timing=True)
             tm = out["timing"]
-            if tm.top_class == _lib.TRUNC_CLASS:
+            if _lib.is_trunc_class(tm.top_class):
+                kname = _lib.sweep_kernel_name(tm.top_class)
                 tms += tm.top_ms
                 tl += tm.top_launches
                 tfl += tm.top_flops
@@ -728,7 +731,7 @@ def trunc_main(a):
             ms_per_step=1e3 * elapsed / a.steps, truncating_sweeps=info.truncating_sweeps,
             message_stride=info.message_stride, max_cut_rank=info.max_cut_rank,
             mean_iterations_per_coset=out["iters"].double().mean().item(),
-            kernel=dict(name="trunc_sweep_kernel", bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+            kernel=dict(name=kname, bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                         frac=ach / PEAK_FP64_TFLOPS, avg_launch_ms=tms / max(tl, 1), launches=tl,
                         flops_per_launch=tfl / max(tl, 1)),
             decisions_equal_to_exact_chi32=float((c == cref).mean()),

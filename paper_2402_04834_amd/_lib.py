@@ -60,15 +60,19 @@ class bbp_timing(C.Structure):
     ]
 
 
-TRUNC_CLASS = 1 << 12   # class code of the truncating block sweeps (trunc_sweep.hip)
+TRUNC_CLASS = 1 << 12   # class code of the truncating block sweeps (trunc_sweep.hip); | 1: their narrow form
+
+
+def is_trunc_class(cls: int) -> bool:
+    return (cls & ~1) == TRUNC_CLASS
 
 
 def sweep_kernel_name(cls: int, precision: int = 0) -> str:
     """Kernel instantiation of a sweep class code (see bbp_timing.top_class): sweep_kernel<...> for FP32,
     sweep_kernel_bf16<...> for the BF16 matrix-core variant of precision mode 1, trunc_sweep_kernel for the
-    truncating sweeps (FP64 at either precision)."""
-    if cls == TRUNC_CLASS:
-        return "trunc_sweep_kernel"
+    truncating sweeps (FP64 at either precision; <true> the narrow form, chi <= 8 and at most 7 positions)."""
+    if is_trunc_class(cls):
+        return f"trunc_sweep_kernel<{'true' if cls & 1 else 'false'}>"
     q00, single, bot, top, kt = cls & 1, (cls >> 1) & 1, (cls >> 2) & 1, (cls >> 3) & 1, (cls >> 4) + 1
     b = lambda v: "true" if v else "false"
     return f"sweep_kernel{'_bf16' if precision else ''}<{kt}, {b(top)}, {b(bot)}, {b(single)}, {b(q00)}>"

@@ -235,7 +235,7 @@ std::vector<ClassRun> by_class(std::vector<SweepDesc>& v) {
   std::stable_sort(v.begin(), v.end(), [](const SweepDesc& a, const SweepDesc& b) {
     const int ca = bbp::sweep_class(a), cb = bbp::sweep_class(b);
     if (ca != cb) return ca < cb;
-    return ca == bbp::TRUNC_CLASS && a.flops > b.flops;
+    return bbp::trunc_class(ca) && a.flops > b.flops;
   });
   std::vector<ClassRun> runs;
   for (int i = 0; i < (int)v.size(); ++i) {
@@ -255,7 +255,7 @@ hipError_t bbp::launch_labels(hipStream_t st, const uint8_t* syn, int d, int64_t
 }
 
 hipError_t bbp::launch_sweeps(int cls, hipStream_t st, const SweepArgs& a) {
-  if (cls == bbp::TRUNC_CLASS) return launch_trunc_sweeps(st, a);
+  if (bbp::trunc_class(cls)) return launch_trunc_sweeps(st, a, (cls & 1) != 0);
   if (a.small) return launch_small_sweeps(st, a);
   bool biased = false;
   for (int k = 0; k < a.ngroups; ++k) biased |= a.g[k].biased != 0;
@@ -606,7 +606,7 @@ int enqueue(std::vector<GroupRun>& gr, const bbp_opts* opts, const Tune& tn, hip
         }
         G.mstride = g.dp->plan.mstride;
         G.chi = g.opts.chi;
-        if (c == bbp::TRUNC_CLASS && !sa.tws) {
+        if (bbp::trunc_class(c) && !sa.tws) {
           sa.tws = g.tws;
           sa.tws_slots = g.lay.tws_slots;
         }

@@ -25,6 +25,7 @@
 
 #include "geom.hpp"
 #include "sweep.hpp"
+#include "trunc_shape.hpp"
 
 namespace bbp {
 
@@ -305,15 +306,25 @@ double sweep_flops(const Plan& p, const SweepDesc& s) {
 // Householder QR of a 64 x 32 matrix (2 m n^2 - 2 n^3 / 3), the reflections are applied to the 32 x 16 carry
 // (4 (64 - j) 16 per reflection j), and every site below the top cap takes one-sided Jacobi SVD of a 32 x 32
 // matrix, counted at six sweeps of 496 rotations (a 2 x 32 product and a 4 x 32 rotation each); the absorption
-// products (R times the column tensor) add 2 x 32 x 32 x 64 per site.
-double trunc_sweep_flops(const SweepDesc& s) {
-  const double qr = 2.0 * 64 * 32 * 32 - 2.0 * 32 * 32 * 32 / 3.0;
-  double apply = 0.0;
-  for (int j = 0; j < 32; ++j) apply += 4.0 * (64 - j) * 16;
-  const double svd = 6.0 * 496 * (2.0 * 32 + 6.0 * 32);
-  const double absorb = 2.0 * 32 * 32 * 64;
-  const double per_site = qr + apply + svd + absorb;
-  return (double)s.kt * (s.kp + 1) * per_site;
+// products (R times the column tensor) add 2 x 32 x 32 x 64 per site. Narrow sweeps (trunc_shape.hpp) execute
+// half-size work: 16 reflections over rows < 32, reflections on rows < 32 of the carry, 120 rotations per
+// Jacobi sweep (16 rows), absorption into rows < 32 from 16 terms.
+double trunc_sweep_flops(const SweepDesc& s, int chi) {
+  double qr, apply = 0.0, svd, absorb;
+  if (trunc_narrow(chi, s.kp)) {
+    // rows < 32 of the padded site matrix, 16 reflections each updating all 32 columns; 16 Jacobi rows
+    qr = 0.0;
+    for (int j = 0; j < 16; ++j) qr += 4.0 * (32 - j) * (32 - j);
+    for (int j = 0; j < 16; ++j) apply += 4.0 * (32 - j) * 16;
+    svd = 6.0 * 120 * (2.0 * 32 + 6.0 * 32);
+    absorb = 2.0 * 16 * 16 * 64;
+  } else {
+    qr = 2.0 * 64 * 32 * 32 - 2.0 * 32 * 32 * 32 / 3.0;
+    for (int j = 0; j < 32; ++j) apply += 4.0 * (64 - j) * 16;
+    svd = 6.0 * 496 * (2.0 * 32 + 6.0 * 32);
+    absorb = 2.0 * 32 * 32 * 64;
+  }
+  return (double)s.kt * (s.kp + 1) * (qr + apply + svd + absorb);
 }
 
 }  // namespace
@@ -432,9 +443,9 @@ Plan make_plan(int d, int kr, int kc, int chi) {
       seen[key] = r;
     }
     worst = std::max(worst, r);
-    s.trunc = (r > chi || kmax > 6) ? 1 : 0;
+    s.trunc = (r > chi || kmax > 6) ? (trunc_narrow(chi, s.kp) ? 2 : 1) : 0;
     if (s.trunc) {
-      s.flops = (float)trunc_sweep_flops(s);
+      s.flops = (float)trunc_sweep_flops(s, chi);
       p.trunc_sweeps += 1;
     }
     p.max_kp = std::max(p.max_kp, s.kp);

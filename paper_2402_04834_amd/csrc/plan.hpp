@@ -22,7 +22,8 @@ struct SweepDesc {
   int32_t block;                // block index (row-major)
   float flops;                  // algorithmic flops of this sweep
   int32_t geo;                  // GEO_* flags (geom.hpp)
-  int32_t trunc;                // 1: the boundary state of this sweep can exceed chi (truncating kernel)
+  int32_t trunc;                // 1: the boundary state of this sweep can exceed chi (truncating kernel); 2: the
+                                // same in the narrow form (every bond within 8, trunc_shape.hpp)
 };
 static_assert(sizeof(SweepDesc) == 64, "SweepDesc layout");
 

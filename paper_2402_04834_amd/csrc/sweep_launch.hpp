@@ -55,18 +55,20 @@ struct SweepArgs {
   int64_t item_base;         // first item of the current chunk
 };
 
-// Sweep class of the truncating kernel (any length; sweeps with SweepDesc::trunc set).
+// Sweep classes of the truncating kernel (any length; sweeps with SweepDesc::trunc set): TRUNC_CLASS, and
+// TRUNC_CLASS | 1 for the narrow form (trunc_shape.hpp).
 constexpr int TRUNC_CLASS = 1 << 12;
+inline bool trunc_class(int cls) { return (cls & ~1) == TRUNC_CLASS; }
 
 // workspace bytes of one truncating-kernel item
 size_t trunc_slot_bytes();
-// launch the a.items truncating sweeps (in chunks of a.tws_slots items)
-hipError_t launch_trunc_sweeps(hipStream_t st, const SweepArgs& a);
+// launch the a.items truncating sweeps (in chunks of a.tws_slots items), all of the narrow form or none
+hipError_t launch_trunc_sweeps(hipStream_t st, const SweepArgs& a, bool narrow);
 
 // Class of a sweep: the kernel instantiation that runs it -- length, caps present, one position across,
 // first site a qubit: code (((kt - 1) * 4 + top * 2 + bottom) * 2 + single) * 2 + q00.
 inline int sweep_class(const SweepDesc& s) {
-  if (s.trunc) return TRUNC_CLASS;
+  if (s.trunc) return TRUNC_CLASS | (s.trunc == 2 ? 1 : 0);
   return (((s.kt - 1) * 4 + (s.msg_top >= 0 ? 2 : 0) + (s.msg_bot >= 0 ? 1 : 0)) * 2 + (s.kp == 1 ? 1 : 0)) * 2 +
          ((s.geo & GEO_Q00) ? 1 : 0);
 }

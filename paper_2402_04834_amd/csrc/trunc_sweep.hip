@@ -32,6 +32,7 @@
 
 #include "geom.hpp"
 #include "sweep_launch.hpp"
+#include "trunc_shape.hpp"
 #include "wave_mps.hpp"
 
 namespace bbp {
@@ -136,6 +137,9 @@ __device__ __forceinline__ void chain(double* W, double* Hv, double* Hb, int K, 
   __syncthreads();
 }
 
+// NARROW: the sweeps of the narrow form (trunc_shape.hpp), factored and decomposed at half size; each form has
+// its own instantiation so that neither pays the other's registers.
+template <bool NARROW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void trunc_sweep_kernel(SweepArgs a) {
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   const int64_t item = a.item_base + (int64_t)blockIdx.x;
@@ -249,7 +253,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
     qr64u<16, 8>(x, rd, vb, Hb);   // rows q' < 16: registers k < 8
     logs += store_r(x, rd, Rsh);
     store_v(x, 16, Hb, Q);
-    // crossing sites
+    // crossing sites: M [(k, h)][(b, dn)] = sum_(a, u) R[k][(a, u)] (A_i T)[(a, u)][(h, b, dn)], factored. KR
+    // registers hold the rows that can be nonzero (rows < 2 KR); narrow: R has at most 16 rows and the site's
+    // bonds at most 8, so M is 32 x 16 (16 reflections) inside the padded 64 x 32
+    constexpr int KR = NARROW ? 16 : 32;
     for (int i = 1; i <= kp; ++i) {
       for (int e = ln; e < TS; e += 64) Ash[e] = A[i * TS + e];
       __syncthreads();
@@ -261,17 +268,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         const double t11 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 1 * 4 + dn * 2 + par);
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = 0.0;
-        for (int aa = 0; aa < 16; ++aa) {
+        for (int aa = 0; aa < KR / 2; ++aa) {
           const double a0 = Ash[(aa * 2 + 0) * 16 + b], a1 = Ash[(aa * 2 + 1) * 16 + b];
           const double b0 = a0 * t00 + a1 * t01, b1 = a0 * t10 + a1 * t11;
 #pragma unroll
-          for (int k = 0; k < 32; ++k) x[k] += Rsh[k * 32 + aa * 2] * b0 + Rsh[k * 32 + aa * 2 + 1] * b1;
+          for (int k = 0; k < KR; ++k) x[k] += Rsh[k * 32 + aa * 2] * b0 + Rsh[k * 32 + aa * 2 + 1] * b1;
         }
       }
       __syncthreads();   // every lane has read R
-      qr64u<32>(x, rd, vb, Hb);
+      qr64u<KR, KR>(x, rd, vb, Hb);
       logs += store_r(x, rd, Rsh);
-      store_v(x, 32, Hb, Q + i * TQ);
+      store_v(x, KR, Hb, Q + i * TQ);
     }
     // bottom cap: Bb[(d, v)][q'] = sum_P S[d][P] CT[P][v][q'], then M[l][q'] = sum R[l][(d, v)] Bb[(d, v)][q']
     for (int e = ln; e < 256; e += 64) Ash[e] = A[(kp + 1) * TS + e];
@@ -322,10 +329,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
       } else {
         // N = Q_i C, then from the column layout to rows: lane (l, t) takes N[l][(t, k)] = X[2l + t][k]
         double X[16];
-        apply_q(X, 32, Q + i * TQ, Csh);
+        apply_q(X, NARROW ? 16 : 32, Q + i * TQ, Csh);
         cols_to_rows(X, Xsh, y);
       }
-      logs += svd_step(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
+      logs += svd_step<NARROW ? 16 : 32>(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
     }
     // top cap: S_0[q'][j] = sum_m Q_0[q'][m] C[m][j], unit Frobenius norm
     {
@@ -442,14 +449,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
 
 size_t trunc_slot_bytes() { return (size_t)W_SLOT * sizeof(double); }
 
-hipError_t launch_trunc_sweeps(hipStream_t st, const SweepArgs& a) {
+hipError_t launch_trunc_sweeps(hipStream_t st, const SweepArgs& a, bool narrow) {
   if (a.items <= 0) return hipSuccess;
   if (!a.tws || a.tws_slots <= 0) return hipErrorInvalidValue;
   SweepArgs b = a;
   for (int64_t base = 0; base < a.items; base += a.tws_slots) {
     b.item_base = base;
     const int64_t n = std::min<int64_t>(a.tws_slots, a.items - base);
-    trunc_sweep_kernel<<<dim3((unsigned)n), dim3(64), 0, st>>>(b);
+    if (narrow)
+      trunc_sweep_kernel<true><<<dim3((unsigned)n), dim3(64), 0, st>>>(b);
+    else
+      trunc_sweep_kernel<false><<<dim3((unsigned)n), dim3(64), 0, st>>>(b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -231,9 +231,12 @@ __device__ __forceinline__ double store_r(const double (&x)[32], double rd, doub
 // One-sided Jacobi SVD of the 32 x 32 matrix N held as y[k] = N[l][(par, k)] by lane (l = hi, par), the chi
 // largest singular values kept. Writes the kept right singular vectors (rows j < 16 of V, zero beyond chi) as
 // site [j][par][k] (or, bottom cap, [j][k] from the par = 0 half) and the carry C = N V / |.|_F into Csh
-// [l][j]; returns the log of that norm.
+// [l][j]; returns the log of that norm. NR (16 or 32): rows l >= NR are zero and take no part in the rounds
+// (NR - 1 rounds of the round-robin pairing per Jacobi sweep instead of 31).
+template <int NR>
 __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh, double* Csh, double* sig,
                                            double* site, bool bottom) {
+  static_assert(NR == 16 || NR == 32, "Jacobi rows");
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   double y0[16];
 #pragma unroll
@@ -249,10 +252,13 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
 #pragma unroll
     for (int k = 0; k < 16; ++k) own += y[k] * y[k];
     own += __shfl_xor(own, 1);
-    // round rd pairs rows hi and pl: 31 and rd, the others (2 rd - hi) mod 31, stepped by 2 each round
-    int cyc = (62 - hi) % 31;
-    for (int rd = 0; rd < 31; ++rd, cyc = (cyc + 2 >= 31) ? cyc + 2 - 31 : cyc + 2) {
-      const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : cyc;
+    // round rd pairs rows hi and pl among the NR rows: NR - 1 and rd, the others (2 rd - hi) mod (NR - 1),
+    // stepped by 2 each round; a zero row beyond NR meets itself and does not rotate
+    constexpr int nm = NR - 1;
+    const bool live = NR == 32 || hi < NR;   // (hi < 32 always)
+    int cyc = live ? (2 * nm - hi) % nm : 0;
+    for (int rd = 0; rd < nm; ++rd, cyc = (cyc + 2 >= nm) ? cyc + 2 - nm : cyc + 2) {
+      const int pl = !live ? hi : (hi == nm) ? rd : (hi == rd) ? nm : cyc;
 #pragma unroll
       for (int k = 0; k < 16; ++k) Xsh[ln * XS + k] = y[k];
       Xsh[ln * XS + 16] = own;
@@ -269,7 +275,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
       const bool lower = hi < pl;
       const double al = lower ? own : other, be = lower ? other : own;
       // squared cosine of the pair (approximate reciprocal: it only decides whether to rotate)
-      const double c2 = (al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : 0.0;
+      const double c2 = (live && al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : 0.0;
       c2max = c2 > c2max ? c2 : c2max;
       if (c2 > JAC * JAC) {
         // The angle only has to bring the pair closer to orthogonal, so t = tan(theta) (the smaller root) is
