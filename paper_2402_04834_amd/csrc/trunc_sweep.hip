@@ -332,7 +332,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         apply_q(X, NARROW ? 16 : 32, Q + i * TQ, Csh);
         cols_to_rows(X, Xsh, y);
       }
-      logs += svd_step<NARROW ? 16 : 32>(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
+      logs += svd_step<NARROW ? 16 : 32, NARROW ? 8 : 16>(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
     }
     // top cap: S_0[q'][j] = sum_m Q_0[q'][m] C[m][j], unit Frobenius norm
     {

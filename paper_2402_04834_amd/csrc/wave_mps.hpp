@@ -232,25 +232,26 @@ __device__ __forceinline__ double store_r(const double (&x)[32], double rd, doub
 // largest singular values kept. Writes the kept right singular vectors (rows j < 16 of V, zero beyond chi) as
 // site [j][par][k] (or, bottom cap, [j][k] from the par = 0 half) and the carry C = N V / |.|_F into Csh
 // [l][j]; returns the log of that norm. NR (16 or 32): rows l >= NR are zero and take no part in the rounds
-// (NR - 1 rounds of the round-robin pairing per Jacobi sweep instead of 31).
-template <int NR>
+// (NR - 1 rounds of the round-robin pairing per Jacobi sweep instead of 31). KC (8 or 16): y[k] = 0 for
+// k >= KC on entry (right bond within 8), so the rounds exchange, multiply and rotate KC entries per lane.
+template <int NR, int KC = 16>
 __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh, double* Csh, double* sig,
                                            double* site, bool bottom) {
-  static_assert(NR == 16 || NR == 32, "Jacobi rows");
+  static_assert((NR == 16 || NR == 32) && (KC == 8 || KC == 16), "Jacobi rows and entries");
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   double y0[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) y0[k] = y[k];
+  for (int k = 0; k < KC; ++k) y0[k] = y[k];
   double nf2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) nf2 += y[k] * y[k];
+  for (int k = 0; k < KC; ++k) nf2 += y[k] * y[k];
   const double thr2 = wsum(nf2) * (RANKTOL * RANKTOL);
   for (int sw = 0; sw < SWEEPS; ++sw) {
     int rotated = 0;
     double c2max = 0.0;
     double own = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) own += y[k] * y[k];
+    for (int k = 0; k < KC; ++k) own += y[k] * y[k];
     own += __shfl_xor(own, 1);
     // round rd pairs rows hi and pl among the NR rows: NR - 1 and rd, the others (2 rd - hi) mod (NR - 1),
     // stepped by 2 each round; a zero row beyond NR meets itself and does not rotate
@@ -260,12 +261,12 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
     for (int rd = 0; rd < nm; ++rd, cyc = (cyc + 2 >= nm) ? cyc + 2 - nm : cyc + 2) {
       const int pl = !live ? hi : (hi == nm) ? rd : (hi == rd) ? nm : cyc;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) Xsh[ln * XS + k] = y[k];
+      for (int k = 0; k < KC; ++k) Xsh[ln * XS + k] = y[k];
       Xsh[ln * XS + 16] = own;
       __syncthreads();
       double z[16], gg = 0.0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
+      for (int k = 0; k < KC; ++k) {
         z[k] = Xsh[(2 * pl + par) * XS + k];
         gg += y[k] * z[k];
       }
@@ -294,7 +295,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
         // lower row p: c p - s q; higher row q: c q + s p -- one multiply and one fused multiply-add each
         const double sz = lower ? -sn : sn;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = fma(sz, z[k], cs * y[k]);
+        for (int k = 0; k < KC; ++k) y[k] = fma(sz, z[k], cs * y[k]);
         const double cc = cs * cs;
         own = lower ? cc * (al - 2.0 * tt * gg + tt * tt * be) : cc * (be + 2.0 * tt * gg + tt * tt * al);
         rotated = 1;
@@ -306,7 +307,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
   }
   double s2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) s2 += y[k] * y[k];
+  for (int k = 0; k < KC; ++k) s2 += y[k] * y[k];
   const double s2r = s2 + __shfl_xor(s2, 1);
   const double sv = (s2r > thr2) ? sqrt(s2r) : 0.0;
   const double key = (sv == sv) ? sv : -1.0;
@@ -338,7 +339,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
   for (int j = 0; j < 16; ++j) {
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
+    for (int k = 0; k < KC; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
     acc += __shfl_xor(acc, 1);
     if ((j >> 3) == par) Csh[hi * 16 + j] = acc * finv;
   }
