@@ -137,6 +137,48 @@ __device__ __forceinline__ void chain(double* W, double* Hv, double* Hb, int K, 
   __syncthreads();
 }
 
+// apply_q and cols_to_rows (wave_mps.hpp) in the narrow form: X = Q C with 16 reflections for the rows < 32
+// and the columns k < 8 that can be nonzero. Lane (kc, g) = (ln & 7, ln >> 3) holds rows 4 g + r (r < 4) of
+// column kc; a reflection is a 4-term partial product, a sum over the eight row groups (three exchanges) and
+// a 4-term update, with the next reflection's entries loaded meanwhile. Then lane (l, t) takes
+// y[k] = X[2 l + t][k] (k < 8; zero beyond, and in the lanes of rows >= 32).
+__device__ __forceinline__ void apply_q_narrow(const double* Vg, const double* Csh, double* Xsh, double (&y)[16]) {
+  const int ln = threadIdx.x, kc = ln & 7, g = ln >> 3;
+  double X[4], vn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    X[r] = Csh[(4 * g + r) * 16 + kc];
+    vn[r] = Vg[15 * 64 + 4 * g + r];
+  }
+  double bn = Vg[2048 + 15];
+  for (int j = 15; j >= 0; --j) {
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = vn[r];
+    const double beta = bn;
+    if (j > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) vn[r] = Vg[(j - 1) * 64 + 4 * g + r];
+      bn = Vg[2048 + j - 1];
+    }
+    double p = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p += v[r] * X[r];
+    p += __shfl_xor(p, 8);
+    p += __shfl_xor(p, 16);
+    p += __shfl_xor(p, 32);
+    const double w = p * beta;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X[r] -= w * v[r];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Xsh[(4 * g + r) * XS + kc] = X[r];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) y[k] = (k < 8 && ln < 32) ? Xsh[ln * XS + k] : 0.0;
+  __syncthreads();
+}
+
 // NARROW: the sweeps of the narrow form (trunc_shape.hpp), factored and decomposed at half size; each form has
 // its own instantiation so that neither pays the other's registers.
 template <bool NARROW>
@@ -328,9 +370,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         for (int k = 0; k < 16; ++k) y[k] = par == 0 ? Mg[hi * 16 + k] : 0.0;
       } else {
         // N = Q_i C, then from the column layout to rows: lane (l, t) takes N[l][(t, k)] = X[2l + t][k]
-        double X[16];
-        apply_q(X, NARROW ? 16 : 32, Q + i * TQ, Csh);
-        cols_to_rows(X, Xsh, y);
+        if constexpr (NARROW) {
+          apply_q_narrow(Q + i * TQ, Csh, Xsh, y);
+        } else {
+          double X[16];
+          apply_q(X, 32, Q + i * TQ, Csh);
+          cols_to_rows(X, Xsh, y);
+        }
       }
       logs += svd_step<NARROW ? 16 : 32, NARROW ? 8 : 16>(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
     }
