@@ -77,6 +77,7 @@ def _decisions_agree(gpu_coset, ref_ll, ref_coset, ref_delta, delta1, margin=1e-
     (9, 0.10, 6, 8, 3, 0.1, 4),     # 6x6 blocks with a 5-wide remainder: truncating and exact sweeps mixed
     (9, 0.10, 7, 16, 3, 0.1, 4),    # 7x7 blocks (message stride 128), every sweep truncating
     (9, 0.08, 8, 16, 3, 0.1, 4),    # 8x8 blocks (message stride 256), caps of bond 16
+    (9, 0.10, 7, 8, 3, 0.1, 3),     # 7x7 blocks at chi 8: the narrow form at its limit (chain bonds 8)
     (11, 0.10, 4, 4, 3, 0.1, 3),    # 4x4 blocks at chi 4, ragged [4, 4, 4, 4, 4, 1]
 ])
 def test_truncating_fixed_iterations_parity(dev, d, p, k, chi, iters, eta, count):
