@@ -307,18 +307,18 @@ double sweep_flops(const Plan& p, const SweepDesc& s) {
 // (4 (64 - j) 16 per reflection j), and every site below the top cap takes one-sided Jacobi SVD of a 32 x 32
 // matrix, counted at six sweeps of 496 rotations (a 2 x 32 product and a 4 x 32 rotation each); the absorption
 // products (R times the column tensor) add 2 x 32 x 32 x 64 per site. Narrow sweeps (trunc_shape.hpp) execute
-// half-size work: 16 reflections over rows < 32, reflections on rows < 32 of the carry, 120 rotations of
-// 16-entry rows per Jacobi sweep, absorption into rows < 32 from 16 terms.
+// the nonzero blocks only: QR of 32 x 16, reflections on the carry's 32 x 8 block, 120 rotations of 16-entry
+// rows per Jacobi sweep, absorption into 32 x 16 from 16 terms.
 double trunc_sweep_flops(const SweepDesc& s, int chi) {
   double qr, apply = 0.0, svd, absorb;
   if (trunc_narrow(chi, s.kt, s.kp)) {
-    // rows < 32 of the padded site matrix, 16 reflections each updating all 32 columns; 16 Jacobi rows of
-    // 2 x 8 nonzero entries
+    // the 32 x 16 site matrix with 16 reflections, the reflections on the carry's 32 x 8 block, 16 Jacobi rows
+    // of 2 x 8 nonzero entries, absorption into the 32 x 16 matrix from 16 terms
     qr = 0.0;
-    for (int j = 0; j < 16; ++j) qr += 4.0 * (32 - j) * (32 - j);
-    for (int j = 0; j < 16; ++j) apply += 4.0 * (32 - j) * 16;
+    for (int j = 0; j < 16; ++j) qr += 4.0 * (32 - j) * (16 - j);
+    for (int j = 0; j < 16; ++j) apply += 4.0 * (32 - j) * 8;
     svd = 6.0 * 120 * (2.0 * 16 + 6.0 * 16);
-    absorb = 2.0 * 16 * 16 * 64;
+    absorb = 2.0 * 16 * 32 * 16;
   } else {
     qr = 2.0 * 64 * 32 * 32 - 2.0 * 32 * 32 * 32 / 3.0;
     for (int j = 0; j < 32; ++j) apply += 4.0 * (64 - j) * 16;

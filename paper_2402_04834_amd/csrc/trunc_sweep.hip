@@ -137,6 +137,80 @@ __device__ __forceinline__ void chain(double* W, double* Hv, double* Hb, int K, 
   __syncthreads();
 }
 
+// A crossing site's factorisation in the narrow form: M (rows (k, h) < 32 with R row k < 16, columns (b, dn)
+// < 16) held as x[k] = M[4 k + q][c] by lane (c, q) = (ln >> 2, ln & 3), k < 8 -- the matrix of qr64u<16, 16>
+// without its 16 zero columns, so a lane holds 8 rows instead of 16. Householder QR with 16 reflections
+// (vectors broadcast through LDS as in qr64u, sums over a column's four lanes by two exchanges), then R (unit
+// Frobenius norm, zero in the columns >= 16) into Rsh [row][col] and the vectors and coefficients into the
+// factor slot in store_v's format (rows < 32). Returns ln |R|_F.
+__device__ __forceinline__ double factor_narrow(double (&x)[8], double* vb, double* Hb, double* Rsh, double* Vg) {
+  const int ln = threadIdx.x, c = ln >> 2, q = ln & 3;
+  double rd = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int kj = j >> 2, qj = j & 3;   // pivot row j = 4 kj + qj
+    double* v = vb + (j & 1) * 64;
+    if (c == j) {
+#pragma unroll
+      for (int k = kj; k < 8; ++k) v[4 * k + q] = x[k];
+    }
+    __syncthreads();
+    double hv[8], pn = 0.0;
+#pragma unroll
+    for (int k = kj; k < 8; ++k) {
+      hv[k] = v[4 * k + q];
+      if (k == kj) hv[k] = q < qj ? 0.0 : hv[k];   // rows above the pivot are not part of the vector
+      pn += hv[k] * hv[k];
+    }
+    pn += __shfl_xor(pn, 1);
+    pn += __shfl_xor(pn, 2);
+    const double nrm = sqrt(pn);
+    const double alpha = v[j];
+    double beta = 0.0, vj = alpha, diag = alpha;
+    if (nrm > 0.0) {
+      const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
+      vj = alpha + sg * nrm;
+      beta = 1.0 / (nrm * (nrm + fabs(alpha)));
+      diag = -sg * nrm;
+    }
+    hv[kj] = (q == qj) ? vj : hv[kj];   // the pivot entry of the vector is v_j, not alpha
+    double pw = 0.0;
+#pragma unroll
+    for (int k = kj; k < 8; ++k) pw += hv[k] * x[k];
+    pw += __shfl_xor(pw, 1);
+    pw += __shfl_xor(pw, 2);
+    const double w = pw * beta;
+    if (c > j) {
+#pragma unroll
+      for (int k = kj; k < 8; ++k) x[k] -= w * hv[k];
+    } else if (c == j) {
+      rd = diag;
+      if (q == qj) x[kj] = vj;
+    }
+    if (ln == 0) Hb[j] = beta;
+  }
+  __syncthreads();
+  double f = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int row = 4 * k + q;
+    const double r = row < c ? x[k] : (row == c ? rd : 0.0);
+    f += r * r;
+  }
+  const double fro = sqrt(wsum(f));
+  const double inv = (fro > 0.0) ? 1.0 / fro : 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int row = 4 * k + q;
+    Rsh[row * 32 + c] = (row < c ? x[k] : (row == c ? rd : 0.0)) * inv;
+    Rsh[row * 32 + 16 + c] = 0.0;
+    Vg[c * 64 + row] = (row >= c) ? x[k] : 0.0;
+  }
+  if (ln < 16) Vg[2048 + ln] = Hb[ln];
+  __syncthreads();
+  return log(fro);
+}
+
 // apply_q and cols_to_rows (wave_mps.hpp) in the narrow form: X = Q C with 16 reflections for the rows < 32
 // and the columns k < 8 that can be nonzero. Lane (kc, g) = (ln & 7, ln >> 3) holds rows 4 g + r (r < 4) of
 // column kc; a reflection is a 4-term partial product, a sum over the eight row groups (three exchanges) and
@@ -295,32 +369,51 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
     qr64u<16, 8>(x, rd, vb, Hb);   // rows q' < 16: registers k < 8
     logs += store_r(x, rd, Rsh);
     store_v(x, 16, Hb, Q);
-    // crossing sites: M [(k, h)][(b, dn)] = sum_(a, u) R[k][(a, u)] (A_i T)[(a, u)][(h, b, dn)], factored. KR
-    // registers hold the rows that can be nonzero (rows < 2 KR); narrow: R has at most 16 rows and the site's
-    // bonds at most 8, so M is 32 x 16 (16 reflections) inside the padded 64 x 32
-    constexpr int KR = NARROW ? 16 : 32;
+    // crossing sites: M [(k, h)][(b, dn)] = sum_(a, u) R[k][(a, u)] (A_i T)[(a, u)][(h, b, dn)], factored; in the
+    // narrow form R has at most 16 rows and the site's bonds at most 8, so M is 32 x 16 (factor_narrow)
     for (int i = 1; i <= kp; ++i) {
       for (int e = ln; e < TS; e += 64) Ash[e] = A[i * TS + e];
       __syncthreads();
-      {
-        const int b = hi >> 1, dn = hi & 1;
-        const double t00 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 0 * 4 + dn * 2 + par);
-        const double t01 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 1 * 4 + dn * 2 + par);
-        const double t10 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 0 * 4 + dn * 2 + par);
-        const double t11 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 1 * 4 + dn * 2 + par);
+      if constexpr (NARROW) {
+        // lane (c, q): column c = (b, dn), rows 4 k + q = (R row 2 k + q / 2, leg q % 2)
+        const int c = ln >> 2, q = ln & 3, b = c >> 1, dn = c & 1, h = q & 1, k0 = q >> 1;
+        const double t00 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 0 * 4 + dn * 2 + h);
+        const double t01 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 1 * 4 + dn * 2 + h);
+        const double t10 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 0 * 4 + dn * 2 + h);
+        const double t11 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 1 * 4 + dn * 2 + h);
+        double xn[8];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) x[k] = 0.0;
-        for (int aa = 0; aa < KR / 2; ++aa) {
+        for (int k = 0; k < 8; ++k) xn[k] = 0.0;
+        for (int aa = 0; aa < 8; ++aa) {
           const double a0 = Ash[(aa * 2 + 0) * 16 + b], a1 = Ash[(aa * 2 + 1) * 16 + b];
           const double b0 = a0 * t00 + a1 * t01, b1 = a0 * t10 + a1 * t11;
 #pragma unroll
-          for (int k = 0; k < KR; ++k) x[k] += Rsh[k * 32 + aa * 2] * b0 + Rsh[k * 32 + aa * 2 + 1] * b1;
+          for (int k = 0; k < 8; ++k)
+            xn[k] += Rsh[(2 * k + k0) * 32 + aa * 2] * b0 + Rsh[(2 * k + k0) * 32 + aa * 2 + 1] * b1;
         }
+        __syncthreads();   // every lane has read R
+        logs += factor_narrow(xn, vb, Hb, Rsh, Q + i * TQ);
+      } else {
+        {
+          const int b = hi >> 1, dn = hi & 1;
+          const double t00 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 0 * 4 + dn * 2 + par);
+          const double t01 = tab(s, L, lab, pq, t, i - 1, 0 * 8 + 1 * 4 + dn * 2 + par);
+          const double t10 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 0 * 4 + dn * 2 + par);
+          const double t11 = tab(s, L, lab, pq, t, i - 1, 1 * 8 + 1 * 4 + dn * 2 + par);
+#pragma unroll
+          for (int k = 0; k < 32; ++k) x[k] = 0.0;
+          for (int aa = 0; aa < 16; ++aa) {
+            const double a0 = Ash[(aa * 2 + 0) * 16 + b], a1 = Ash[(aa * 2 + 1) * 16 + b];
+            const double b0 = a0 * t00 + a1 * t01, b1 = a0 * t10 + a1 * t11;
+#pragma unroll
+            for (int k = 0; k < 32; ++k) x[k] += Rsh[k * 32 + aa * 2] * b0 + Rsh[k * 32 + aa * 2 + 1] * b1;
+          }
+        }
+        __syncthreads();   // every lane has read R
+        qr64u<32>(x, rd, vb, Hb);
+        logs += store_r(x, rd, Rsh);
+        store_v(x, 32, Hb, Q + i * TQ);
       }
-      __syncthreads();   // every lane has read R
-      qr64u<KR, KR>(x, rd, vb, Hb);
-      logs += store_r(x, rd, Rsh);
-      store_v(x, KR, Hb, Q + i * TQ);
     }
     // bottom cap: Bb[(d, v)][q'] = sum_P S[d][P] CT[P][v][q'], then M[l][q'] = sum R[l][(d, v)] Bb[(d, v)][q']
     for (int e = ln; e < 256; e += 64) Ash[e] = A[(kp + 1) * TS + e];
