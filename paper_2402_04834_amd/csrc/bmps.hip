@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         apply_q(X, 32, Qr, Csh);
         cols_to_rows(X, Xsh, y);
       }
-      logs += svd_step<32>(y, chi, Xsh, Csh, sig, Aj + (int64_t)r * SITE_A, false);
+      logs += svd_step(y, chi, Xsh, Csh, sig, Aj + (int64_t)r * SITE_A, false);
     }
   }
   if (ln == 0) {

@@ -214,9 +214,9 @@ __device__ __forceinline__ double factor_narrow(double (&x)[8], double* vb, doub
 // apply_q and cols_to_rows (wave_mps.hpp) in the narrow form: X = Q C with 16 reflections for the rows < 32
 // and the columns k < 8 that can be nonzero. Lane (kc, g) = (ln & 7, ln >> 3) holds rows 4 g + r (r < 4) of
 // column kc; a reflection is a 4-term partial product, a sum over the eight row groups (three exchanges) and
-// a 4-term update, with the next reflection's entries loaded meanwhile. Then lane (l, t) takes
-// y[k] = X[2 l + t][k] (k < 8; zero beyond, and in the lanes of rows >= 32).
-__device__ __forceinline__ void apply_q_narrow(const double* Vg, const double* Csh, double* Xsh, double (&y)[16]) {
+// a 4-term update, with the next reflection's entries loaded meanwhile. Then, in svd_narrow's layout, lane
+// (l, u) takes y[e] = X[2 l + u / 2][4 (u % 2) + e].
+__device__ __forceinline__ void apply_q_narrow(const double* Vg, const double* Csh, double* Xsh, double (&y)[4]) {
   const int ln = threadIdx.x, kc = ln & 7, g = ln >> 3;
   double X[4], vn[4];
 #pragma unroll
@@ -248,9 +248,125 @@ __device__ __forceinline__ void apply_q_narrow(const double* Vg, const double* C
 #pragma unroll
   for (int r = 0; r < 4; ++r) Xsh[(4 * g + r) * XS + kc] = X[r];
   __syncthreads();
+  const int l = ln >> 2, u = ln & 3;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) y[k] = (k < 8 && ln < 32) ? Xsh[ln * XS + k] : 0.0;
+  for (int e = 0; e < 4; ++e) y[e] = Xsh[(2 * l + (u >> 1)) * XS + 4 * (u & 1) + e];
   __syncthreads();
+}
+
+// svd_step (wave_mps.hpp) in the narrow form: N has at most 16 nonzero rows, each with 2 x 8 nonzero entries
+// (t, k), held as y[e] = N[l][(t, k)] with t = u / 2, k = 4 (u % 2) + e by lane (l, u) = (ln >> 2, ln & 3).
+// The same one-sided Jacobi rotations, stopping test and outputs (kept right singular vectors as site rows,
+// zero beyond chi and beyond k = 8; the carry C = N V / |.|_F into Csh [l][j], rows 16..31 cleared); the
+// round-robin pairs 16 rows (15 rounds per sweep), and a round exchanges 4 entries and a norm per lane and
+// sums a pair's product over the row's four lanes by two exchanges.
+__device__ __forceinline__ double svd_narrow(double (&y)[4], int chi, double* Xsh, double* Csh, double* sig,
+                                             double* site, bool bottom) {
+  constexpr int XN = 5;   // exchange row stride: 4 entries and the row norm
+  const int ln = threadIdx.x, l = ln >> 2, u = ln & 3, t = u >> 1, k0 = 4 * (u & 1);
+  double y0[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) y0[e] = y[e];
+  double nf2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) nf2 += y[e] * y[e];
+  const double thr2 = wsum(nf2) * (RANKTOL * RANKTOL);
+  auto rowsum = [](double v) {
+    v += __shfl_xor(v, 1);
+    return v + __shfl_xor(v, 2);
+  };
+  for (int sw = 0; sw < SWEEPS; ++sw) {
+    int rotated = 0;
+    double c2max = 0.0;
+    double own = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) own += y[e] * y[e];
+    own = rowsum(own);
+    // round rd pairs rows l and pl: 15 and rd, the others (2 rd - l) mod 15, stepped by 2 each round
+    int cyc = (30 - l) % 15;
+    for (int rd = 0; rd < 15; ++rd, cyc = (cyc + 2 >= 15) ? cyc + 2 - 15 : cyc + 2) {
+      const int pl = (l == 15) ? rd : (l == rd) ? 15 : cyc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Xsh[ln * XN + e] = y[e];
+      Xsh[ln * XN + 4] = own;
+      __syncthreads();
+      double z[4], gg = 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        z[e] = Xsh[(4 * pl + u) * XN + e];
+        gg += y[e] * z[e];
+      }
+      const double other = Xsh[(4 * pl + u) * XN + 4];
+      __syncthreads();
+      gg = rowsum(gg);
+      const bool lower = l < pl;
+      const double al = lower ? own : other, be = lower ? other : own;
+      const double c2 = (al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : 0.0;
+      c2max = c2 > c2max ? c2 : c2max;
+      if (c2 > JAC * JAC) {
+        // the angle as in svd_step: tan in FP32, cos and sin in FP64 from it
+        const float zf = (float)(be - al) * __builtin_amdgcn_rcpf(2.0f * (float)gg), azf = fabsf(zf);
+        const float denf = azf + (azf < 1e18f ? __builtin_amdgcn_sqrtf(fmaf(zf, zf, 1.0f)) : azf);
+        const double tt = (double)copysignf(__builtin_amdgcn_rcpf(denf), zf);
+        const double xx = tt * tt + 1.0;
+        double cs = __builtin_amdgcn_rsq(xx);
+        cs = cs * (1.5 - 0.5 * xx * cs * cs);
+        cs = cs * (1.5 - 0.5 * xx * cs * cs);
+        const double sn = cs * tt;
+        const double sz = lower ? -sn : sn;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[e] = fma(sz, z[e], cs * y[e]);
+        const double cc = cs * cs;
+        own = lower ? cc * (al - 2.0 * tt * gg + tt * tt * be) : cc * (be + 2.0 * tt * gg + tt * tt * al);
+        rotated = 1;
+      }
+    }
+    if (!__any(rotated) || wmax(c2max) < 1e-12) break;
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) s2 += y[e] * y[e];
+  const double s2r = rowsum(s2);
+  const double sv = (s2r > thr2) ? sqrt(s2r) : 0.0;
+  const double key = (sv == sv) ? sv : -1.0;
+  if (u == 0) sig[l] = key;
+  __syncthreads();
+  int rank = 0;
+  for (int i = 0; i < 16; ++i) {
+    const double o = sig[i];
+    rank += (o > key || (o == key && i < l)) ? 1 : 0;
+  }
+  const bool kept = rank < chi && sv > 0.0;
+  const double inv = kept ? 1.0 / sv : 0.0;
+  double* Vsh = Xsh;   // the exchange buffer is free now
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (bottom) {
+      if (t == 0) {
+        site[rank * 16 + k0 + e] = y[e] * inv;
+        site[rank * 16 + 8 + k0 + e] = 0.0;
+      }
+    } else {
+      site[(rank * 2 + t) * 16 + k0 + e] = y[e] * inv;
+      site[(rank * 2 + t) * 16 + 8 + k0 + e] = 0.0;
+    }
+    Vsh[rank * 32 + t * 16 + k0 + e] = y[e] * inv;
+  }
+  const double fro = sqrt(wsum((u == 0 && kept) ? sv * sv : 0.0));
+  __syncthreads();
+  const double finv = (fro > 0.0) ? 1.0 / fro : 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc += y0[e] * Vsh[j * 32 + t * 16 + k0 + e];
+    acc = rowsum(acc);
+    if ((j >> 2) == u) Csh[l * 16 + j] = acc * finv;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Csh[(16 + l) * 16 + 4 * u + e] = 0.0;
+  __syncthreads();
+  return log(fro);
 }
 
 // NARROW: the sweeps of the narrow form (trunc_shape.hpp), factored and decomposed at half size; each form has
@@ -456,22 +572,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
     double* Csh = Xsh + 64 * XS;
     double* sig = Csh + 32 * 16;
     for (int i = kp + 1; i >= 1; --i) {
-      double y[16];
-      if (i == kp + 1) {
-        const double* Mg = Q + (kp + 1) * TQ;
+      const double* Mg = Q + (kp + 1) * TQ;   // the bottom cap's M [l][q']
+      if constexpr (NARROW) {
+        double y[4];
+        if (i == kp + 1) {
+          const int l = ln >> 2, u = ln & 3;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = par == 0 ? Mg[hi * 16 + k] : 0.0;
-      } else {
-        // N = Q_i C, then from the column layout to rows: lane (l, t) takes N[l][(t, k)] = X[2l + t][k]
-        if constexpr (NARROW) {
-          apply_q_narrow(Q + i * TQ, Csh, Xsh, y);
+          for (int e = 0; e < 4; ++e) y[e] = (u < 2) ? Mg[l * 16 + 4 * u + e] : 0.0;
         } else {
+          apply_q_narrow(Q + i * TQ, Csh, Xsh, y);   // N = Q_i C
+        }
+        logs += svd_narrow(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
+      } else {
+        double y[16];
+        if (i == kp + 1) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) y[k] = par == 0 ? Mg[hi * 16 + k] : 0.0;
+        } else {
+          // N = Q_i C, then from the column layout to rows: lane (l, t) takes N[l][(t, k)] = X[2l + t][k]
           double X[16];
           apply_q(X, 32, Q + i * TQ, Csh);
           cols_to_rows(X, Xsh, y);
         }
+        logs += svd_step(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
       }
-      logs += svd_step<NARROW ? 16 : 32, NARROW ? 8 : 16>(y, chi, Xsh, Csh, sig, A + i * TS, i == kp + 1);
     }
     // top cap: S_0[q'][j] = sum_m Q_0[q'][m] C[m][j], unit Frobenius norm
     {

@@ -231,42 +231,35 @@ __device__ __forceinline__ double store_r(const double (&x)[32], double rd, doub
 // One-sided Jacobi SVD of the 32 x 32 matrix N held as y[k] = N[l][(par, k)] by lane (l = hi, par), the chi
 // largest singular values kept. Writes the kept right singular vectors (rows j < 16 of V, zero beyond chi) as
 // site [j][par][k] (or, bottom cap, [j][k] from the par = 0 half) and the carry C = N V / |.|_F into Csh
-// [l][j]; returns the log of that norm. NR (16 or 32): rows l >= NR are zero and take no part in the rounds
-// (NR - 1 rounds of the round-robin pairing per Jacobi sweep instead of 31). KC (8 or 16): y[k] = 0 for
-// k >= KC on entry (right bond within 8), so the rounds exchange, multiply and rotate KC entries per lane.
-template <int NR, int KC = 16>
+// [l][j]; returns the log of that norm.
 __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh, double* Csh, double* sig,
                                            double* site, bool bottom) {
-  static_assert((NR == 16 || NR == 32) && (KC == 8 || KC == 16), "Jacobi rows and entries");
   const int ln = threadIdx.x, hi = ln >> 1, par = ln & 1;
   double y0[16];
 #pragma unroll
-  for (int k = 0; k < KC; ++k) y0[k] = y[k];
+  for (int k = 0; k < 16; ++k) y0[k] = y[k];
   double nf2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < KC; ++k) nf2 += y[k] * y[k];
+  for (int k = 0; k < 16; ++k) nf2 += y[k] * y[k];
   const double thr2 = wsum(nf2) * (RANKTOL * RANKTOL);
   for (int sw = 0; sw < SWEEPS; ++sw) {
     int rotated = 0;
     double c2max = 0.0;
     double own = 0.0;
 #pragma unroll
-    for (int k = 0; k < KC; ++k) own += y[k] * y[k];
+    for (int k = 0; k < 16; ++k) own += y[k] * y[k];
     own += __shfl_xor(own, 1);
-    // round rd pairs rows hi and pl among the NR rows: NR - 1 and rd, the others (2 rd - hi) mod (NR - 1),
-    // stepped by 2 each round; a zero row beyond NR meets itself and does not rotate
-    constexpr int nm = NR - 1;
-    const bool live = NR == 32 || hi < NR;   // (hi < 32 always)
-    int cyc = live ? (2 * nm - hi) % nm : 0;
-    for (int rd = 0; rd < nm; ++rd, cyc = (cyc + 2 >= nm) ? cyc + 2 - nm : cyc + 2) {
-      const int pl = !live ? hi : (hi == nm) ? rd : (hi == rd) ? nm : cyc;
+    // round rd pairs rows hi and pl: 31 and rd, the others (2 rd - hi) mod 31, stepped by 2 each round
+    int cyc = (62 - hi) % 31;
+    for (int rd = 0; rd < 31; ++rd, cyc = (cyc + 2 >= 31) ? cyc + 2 - 31 : cyc + 2) {
+      const int pl = (hi == 31) ? rd : (hi == rd) ? 31 : cyc;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) Xsh[ln * XS + k] = y[k];
+      for (int k = 0; k < 16; ++k) Xsh[ln * XS + k] = y[k];
       Xsh[ln * XS + 16] = own;
       __syncthreads();
       double z[16], gg = 0.0;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) {
+      for (int k = 0; k < 16; ++k) {
         z[k] = Xsh[(2 * pl + par) * XS + k];
         gg += y[k] * z[k];
       }
@@ -276,7 +269,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
       const bool lower = hi < pl;
       const double al = lower ? own : other, be = lower ? other : own;
       // squared cosine of the pair (approximate reciprocal: it only decides whether to rotate)
-      const double c2 = (live && al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : 0.0;
+      const double c2 = (al > thr2 && be > thr2) ? gg * gg * __builtin_amdgcn_rcp(al * be) : 0.0;
       c2max = c2 > c2max ? c2 : c2max;
       if (c2 > JAC * JAC) {
         // The angle only has to bring the pair closer to orthogonal, so t = tan(theta) (the smaller root) is
@@ -295,7 +288,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
         // lower row p: c p - s q; higher row q: c q + s p -- one multiply and one fused multiply-add each
         const double sz = lower ? -sn : sn;
 #pragma unroll
-        for (int k = 0; k < KC; ++k) y[k] = fma(sz, z[k], cs * y[k]);
+        for (int k = 0; k < 16; ++k) y[k] = fma(sz, z[k], cs * y[k]);
         const double cc = cs * cs;
         own = lower ? cc * (al - 2.0 * tt * gg + tt * tt * be) : cc * (be + 2.0 * tt * gg + tt * tt * al);
         rotated = 1;
@@ -307,7 +300,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
   }
   double s2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < KC; ++k) s2 += y[k] * y[k];
+  for (int k = 0; k < 16; ++k) s2 += y[k] * y[k];
   const double s2r = s2 + __shfl_xor(s2, 1);
   const double sv = (s2r > thr2) ? sqrt(s2r) : 0.0;
   const double key = (sv == sv) ? sv : -1.0;
@@ -339,7 +332,7 @@ __device__ __forceinline__ double svd_step(double (&y)[16], int chi, double* Xsh
   for (int j = 0; j < 16; ++j) {
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < KC; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
+    for (int k = 0; k < 16; ++k) acc += y0[k] * Vsh[j * 32 + par * 16 + k];
     acc += __shfl_xor(acc, 1);
     if ((j >> 3) == par) Csh[hi * 16 + j] = acc * finv;
   }
