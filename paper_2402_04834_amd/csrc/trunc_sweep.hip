@@ -21,6 +21,8 @@
 //            singular vectors are the new site, N V (unit norm) the carry; the top cap takes Q C.
 //   end      the chain contracted to the dense 2^kp message; normalisation (remark 3), damping (remark 7) and
 //            distance term (remark 4) as in the dense kernels, or the closing overlap of Lemma 3.1.
+//   narrow   with every bond within 8 (trunc_shape.hpp) the factorisations, reflections and SVDs run on the
+//            blocks that can be nonzero, in layouts that keep all 64 lanes busy (trunc_sweep_kernel<true>).
 // Keeping the chi largest values at every bond is the textbook QR + truncated-SVD compression: the part left
 // of a bond is an isometry when it is truncated, so each cut keeps the chi largest Schmidt values of the
 // current state. Where a bond carries at most chi values the SVD keeps them all (the state is unchanged).
@@ -138,8 +140,9 @@ __device__ __forceinline__ void chain(double* W, double* Hv, double* Hb, int K, 
 }
 
 // A crossing site's factorisation in the narrow form: M (rows (k, h) < 32 with R row k < 16, columns (b, dn)
-// < 16) held as x[k] = M[4 k + q][c] by lane (c, q) = (ln >> 2, ln & 3), k < 8 -- the matrix of qr64u<16, 16>
-// without its 16 zero columns, so a lane holds 8 rows instead of 16. Householder QR with 16 reflections
+// < 16) held as x[k] = M[4 k + q][c] by lane (c, q) = (ln >> 2, ln & 3), k < 8 -- the block of the padded
+// 64 x 32 site matrix that can be nonzero, spread so that every lane holds 8 of its rows (the 64 x 32 layout
+// of qr64u would leave half the lanes on zero columns). Householder QR with 16 reflections
 // (vectors broadcast through LDS as in qr64u, sums over a column's four lanes by two exchanges), then R (unit
 // Frobenius norm, zero in the columns >= 16) into Rsh [row][col] and the vectors and coefficients into the
 // factor slot in store_v's format (rows < 32). Returns ln |R|_F.
