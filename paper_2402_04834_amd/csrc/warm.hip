@@ -941,6 +941,11 @@ __global__ void compose_head_kernel(const float* __restrict__ prm, int kpad, uns
 __global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__ Pj, int64_t dstride, int sstride,
                                                        const int32_t* __restrict__ legs, int M, int L, int64_t jobs,
                                                        const float* __restrict__ prm, float* __restrict__ msgs) {
+  // the NPROJ projections of every leg site (a_0 .. a_{K-1}, then b_0 .. b_{K-1}), each a contiguous run of
+  // five 16-byte pieces, loaded by one lane per piece into LDS: one load instruction per wave instead of
+  // two to four dependent 4-byte gathers per lane
+  static_assert(NPROJ == 20, "five 16-byte pieces per site");
+  __shared__ float4 sp4[2 * MAXK * 5];
   const int64_t job = blockIdx.x / M;
   const int e = (int)(blockIdx.x - job * M), lane = threadIdx.x;
   if (job >= jobs) return;
@@ -949,17 +954,23 @@ __global__ __launch_bounds__(64) void head_proj_kernel(const float* __restrict__
   const float* H = prm + OFF.head + (size_t)dir * HEAD;
   const float *bu = H + 2 * C3 * 2, *bp = bu + 2 + 4 * C3 * 4;
   const float* P = Pj + dir * dstride + job * (int64_t)L * L * sstride;
-  auto proj = [&](int site, int j) { return P[(int64_t)site * sstride + j]; };
+  if (lane < 2 * K * 5) {
+    const int m = lane / 5, part = lane - 5 * m;
+    const int site = m < K ? lg[2 + m] : lg[2 + MAXK + m - K];
+    sp4[lane] = *(const float4*)(P + (int64_t)site * sstride + 4 * part);
+  }
+  __syncthreads();
+  const float* sp = (const float*)sp4;
+  auto pa = [&](int i, int j) { return sp[i * NPROJ + j]; };         // leg site a_i
+  auto pb = [&](int i, int j) { return sp[(K + i) * NPROJ + j]; };   // leg site b_i
   // output o = lane: unary 2 i + c, pairwise 2 MAXK + 4 i + q (as head_kernel)
   float outv = 0.0f;
   if (lane < 2 * MAXK) {
     const int i = lane >> 1, c = lane & 1;
-    if (i < K) outv = proj(lg[2 + i], c) + proj(lg[2 + MAXK + i], 2 + c) + bu[c];
+    if (i < K) outv = pa(i, c) + pb(i, 2 + c) + bu[c];
   } else if (lane < NOUT) {
     const int i = (lane - 2 * MAXK) >> 2, q = (lane - 2 * MAXK) & 3;
-    if (i < K - 1)
-      outv = proj(lg[2 + i], 4 + q) + proj(lg[2 + MAXK + i], 8 + q) + proj(lg[2 + i + 1], 12 + q) +
-             proj(lg[2 + MAXK + i + 1], 16 + q) + bp[q];
+    if (i < K - 1) outv = pa(i, 4 + q) + pb(i, 8 + q) + pa(i + 1, 12 + q) + pb(i + 1, 16 + q) + bp[q];
   }
   const int b = lane, nb = 1 << K;
   const bool valid = b < nb;
